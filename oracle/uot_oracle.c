@@ -1,0 +1,456 @@
+/*
+ * FP64 CPU oracle for the entropic unbalanced optimal-transport (UOT)
+ * Sinkhorn scaling loop -- TEST INFRASTRUCTURE ONLY.
+ *
+ * This file is the plain, slow, obviously correct definition that the HIP
+ * library is checked against.  Only the tests, the smoke check and the CPU
+ * baseline leg of the benchmark load it; the product path never does.  It
+ * shares no source, header, table or helper with the HIP library.
+ *
+ * Problem (paper Section 2.1): a non-negative matrix is rescaled
+ * alternately by rows and by columns; the row factor of row i is
+ * (row target_i / row sum_i)^fi with fi = tau/(tau+eps) (the paper's
+ * fi = er/(er+ep)), and likewise for columns, until an error limit.  Written
+ * on scaling vectors (the form used here), the kernel is K = exp(-C/eps),
+ * the plan is P = diag(u) K diag(v), and one iteration is
+ *
+ *     s = K v,      u = (a / s)^fi          (row half-step: parts 4 and 1
+ *     w = K^T u,    v = (b / w)^fi           and column half-step: parts 2, 3
+ *                                            of the four-part split, Sec. 4)
+ *
+ * rows first, starting from v = 1.  Every routine below is FP64, uses no
+ * blocking or reordering beyond what that definition states, and is
+ * parallelised only across independent rows or independent column blocks
+ * (each output element is summed in ascending index order, so results do
+ * not depend on the thread count).
+ *
+ * Readings where the paper is silent (each is listed with its reason in
+ * the design notes):
+ *   - zero mass: a_i = 0 gives u_i = 0 (and b_j = 0 gives v_j = 0), even
+ *     when the sum is 0; a zero sum with positive mass yields +inf (the
+ *     caller sees it as non-finite);
+ *   - stopping: the error after iteration t is the relative L1 change of
+ *     the column marginal c_t = v_t * (K^T u_t), with c_0 = 0; stop when
+ *     tol > 0 and the error is <= tol, otherwise run exactly max_iter;
+ *   - objective: the primal UOT objective
+ *        <C,P> + eps sum P (log P - 1) + tau KL~(P1|a) + tau KL~(P^T1|b),
+ *     KL~(x|y) = sum x log(x/y) - x + y, 0 log 0 = 0; for tau = inf the two
+ *     KL terms are dropped.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_EXPORT __attribute__((visibility("default")))
+
+/* Exponent of the row/column factors (Section 2.1): tau/(tau+eps), or 1 for
+ * the balanced limit tau = inf. */
+static double orc_fi(double eps, double tau) {
+    if (isinf(tau)) return 1.0;
+    return tau / (tau + eps);
+}
+
+/* One scaling factor (target / sum)^fi with the zero-mass rule. */
+static double orc_factor(double target, double sum, double fi) {
+    if (target == 0.0) return 0.0;
+    return pow(target / sum, fi);
+}
+
+/* ------------------------------------------------------------------ */
+/* Costs and kernel                                                     */
+/* ------------------------------------------------------------------ */
+
+/* C_ij = ||x_i - y_j||^2 (kind 0) or 1 - x_i . y_j (kind 1); x is n x d,
+ * y is m x d, both row-major; C is n x m row-major.  With normalize != 0
+ * the whole matrix is divided by its maximum (if that maximum is > 0). */
+ORC_EXPORT void orc_cost_points(const double* x, const double* y, int64_t n, int64_t m,
+                                int64_t d, int kind, int normalize, double* C) {
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t j = 0; j < m; ++j) {
+            double acc = 0.0;
+            if (kind == 0) {
+                for (int64_t k = 0; k < d; ++k) {
+                    double diff = x[i * d + k] - y[j * d + k];
+                    acc += diff * diff;
+                }
+                C[i * m + j] = acc;
+            } else {
+                for (int64_t k = 0; k < d; ++k) acc += x[i * d + k] * y[j * d + k];
+                C[i * m + j] = 1.0 - acc;
+            }
+        }
+    }
+    if (normalize) {
+        double mx = 0.0;
+        for (int64_t t = 0; t < n * m; ++t) if (C[t] > mx) mx = C[t];
+        if (mx > 0.0) {
+            #pragma omp parallel for schedule(static)
+            for (int64_t t = 0; t < n * m; ++t) C[t] = C[t] / mx;
+        }
+    }
+}
+
+/* K_ij = exp((f_i + g_j - C_ij) / eps); f or g may be NULL (taken as 0).
+ * With f = g = 0 this is the Gibbs kernel exp(-C/eps). */
+ORC_EXPORT void orc_kernel(const double* C, int64_t n, int64_t m, double eps,
+                           const double* f, const double* g, double* K) {
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double fi_ = f ? f[i] : 0.0;
+        for (int64_t j = 0; j < m; ++j) {
+            double gj = g ? g[j] : 0.0;
+            K[i * m + j] = exp((fi_ + gj - C[i * m + j]) / eps);
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Mat-vec products                                                     */
+/* ------------------------------------------------------------------ */
+
+/* s = K v (row sums of diag(.) K diag(v)). */
+static void orc_Kv(const double* K, const double* v, int64_t n, int64_t m, double* s) {
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double acc = 0.0;
+        for (int64_t j = 0; j < m; ++j) acc += K[i * m + j] * v[j];
+        s[i] = acc;
+    }
+}
+
+/* w = K^T u, each w_j summed over i in ascending order; threads own blocks
+ * of 64 columns so that rows are still read in contiguous pieces. */
+static void orc_KTu(const double* K, const double* u, int64_t n, int64_t m, double* w) {
+    const int64_t BLK = 64;
+    int64_t nblk = (m + BLK - 1) / BLK;
+    #pragma omp parallel for schedule(static)
+    for (int64_t blk = 0; blk < nblk; ++blk) {
+        int64_t j0 = blk * BLK, j1 = j0 + BLK < m ? j0 + BLK : m;
+        double acc[64];
+        for (int64_t j = j0; j < j1; ++j) acc[j - j0] = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            double ui = u[i];
+            const double* row = K + i * m;
+            for (int64_t j = j0; j < j1; ++j) acc[j - j0] += row[j] * ui;
+        }
+        for (int64_t j = j0; j < j1; ++j) w[j] = acc[j - j0];
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Plain Sinkhorn (vector form, rows first)                             */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Runs the iteration from v = v0 (or 1) for at most max_iter iterations.
+ * Outputs (all caller-allocated, length n or m):
+ *   u, v          final scalings u_T, v_T (u = 1 when max_iter = 0 and no u0)
+ *   s_fin         K v_T            (so the row marginal is r = u * s_fin)
+ *   w_fin         K^T u_T          (so the column marginal is c = v * w_fin)
+ *   err_out       error of the last iteration run (0 when none was run)
+ * Optional trace (NULL to skip), for the reverse pass:
+ *   tr_v  (max_iter+1) x m : v_0 .. v_T
+ *   tr_s  max_iter x n      : s_1 .. s_T     (s_t = K v_{t-1})
+ *   tr_u  max_iter x n      : u_1 .. u_T
+ *   tr_w  max_iter x m      : w_1 .. w_T     (w_t = K^T u_t)
+ * Returns the number of iterations run.
+ */
+ORC_EXPORT int64_t orc_sinkhorn(const double* K, const double* a, const double* b,
+                                int64_t n, int64_t m, double eps, double tau,
+                                int64_t max_iter, double tol,
+                                const double* u0, const double* v0,
+                                double* u, double* v, double* s_fin, double* w_fin,
+                                double* err_out,
+                                double* tr_v, double* tr_s, double* tr_u, double* tr_w) {
+    double fi = orc_fi(eps, tau);
+    double* s = (double*)malloc(sizeof(double) * (size_t)n);
+    double* w = (double*)malloc(sizeof(double) * (size_t)m);
+    double* c_prev = (double*)calloc((size_t)m, sizeof(double));
+    for (int64_t i = 0; i < n; ++i) u[i] = u0 ? u0[i] : 1.0;
+    for (int64_t j = 0; j < m; ++j) v[j] = v0 ? v0[j] : 1.0;
+    if (tr_v) memcpy(tr_v, v, sizeof(double) * (size_t)m);
+    double err = 0.0;
+    int64_t t = 0;
+    while (t < max_iter) {
+        /* row half-step */
+        orc_Kv(K, v, n, m, s);
+        for (int64_t i = 0; i < n; ++i) u[i] = orc_factor(a[i], s[i], fi);
+        /* column half-step */
+        orc_KTu(K, u, n, m, w);
+        for (int64_t j = 0; j < m; ++j) v[j] = orc_factor(b[j], w[j], fi);
+        ++t;
+        if (tr_s) memcpy(tr_s + (t - 1) * n, s, sizeof(double) * (size_t)n);
+        if (tr_u) memcpy(tr_u + (t - 1) * n, u, sizeof(double) * (size_t)n);
+        if (tr_w) memcpy(tr_w + (t - 1) * m, w, sizeof(double) * (size_t)m);
+        if (tr_v) memcpy(tr_v + t * m, v, sizeof(double) * (size_t)m);
+        /* relative L1 change of the column marginal c = v * w */
+        double num = 0.0, den = 0.0;
+        for (int64_t j = 0; j < m; ++j) {
+            double cj = v[j] * w[j];
+            num += fabs(cj - c_prev[j]);
+            den += fabs(cj);
+            c_prev[j] = cj;
+        }
+        err = num / den;
+        if (tol > 0.0 && err <= tol) break;
+    }
+    orc_Kv(K, v, n, m, s_fin);
+    orc_KTu(K, u, n, m, w_fin);
+    if (err_out) *err_out = err;
+    free(s);
+    free(w);
+    free(c_prev);
+    return t;
+}
+
+/* ------------------------------------------------------------------ */
+/* Objective                                                            */
+/* ------------------------------------------------------------------ */
+
+/* KL~(x|y) = x log(x/y) - x + y with 0 log 0 = 0. */
+static double orc_kl_term(double x, double y) {
+    double t = -x + y;
+    if (x > 0.0) t += x * log(x / y);
+    return t;
+}
+
+/*
+ * Primal objective by its definition, summing over all n x m entries of
+ * P = diag(u) K diag(v):  <C,P> + eps sum P(log P - 1) + tau KL~(r|a)
+ * + tau KL~(c|b), with r = P 1 and c = P^T 1 formed here from P.
+ * transport_cost (optional) receives <C,P>.
+ */
+ORC_EXPORT double orc_loss_direct(const double* C, const double* K, const double* u,
+                                  const double* v, const double* a, const double* b,
+                                  int64_t n, int64_t m, double eps, double tau,
+                                  double* transport_cost) {
+    double* r = (double*)calloc((size_t)n, sizeof(double));
+    double* c = (double*)calloc((size_t)m, sizeof(double));
+    double cp = 0.0, ent = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t j = 0; j < m; ++j) {
+            double p = u[i] * K[i * m + j] * v[j];
+            r[i] += p;
+            c[j] += p;
+            cp += C[i * m + j] * p;
+            if (p > 0.0) ent += p * (log(p) - 1.0);
+        }
+    }
+    double L = cp + eps * ent;
+    if (!isinf(tau)) {
+        double kr = 0.0, kc = 0.0;
+        for (int64_t i = 0; i < n; ++i) kr += orc_kl_term(r[i], a[i]);
+        for (int64_t j = 0; j < m; ++j) kc += orc_kl_term(c[j], b[j]);
+        L += tau * (kr + kc);
+    }
+    if (transport_cost) *transport_cost = cp;
+    free(r);
+    free(c);
+    return L;
+}
+
+/*
+ * The same objective from O(n + m) quantities.  Because
+ * eps log P_ij = eps log u_i + eps log v_j - C_ij, the cost and entropy
+ * terms collapse to eps (sum r log u + sum c log v - sum r); r = u * (K v)
+ * and c = v * (K^T u) are passed in.
+ */
+ORC_EXPORT double orc_loss_identity(const double* u, const double* v, const double* r,
+                                    const double* c, const double* a, const double* b,
+                                    int64_t n, int64_t m, double eps, double tau) {
+    double sr = 0.0, sc = 0.0, mass = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (r[i] > 0.0) sr += r[i] * log(u[i]);
+        mass += r[i];
+    }
+    for (int64_t j = 0; j < m; ++j)
+        if (c[j] > 0.0) sc += c[j] * log(v[j]);
+    double L = eps * (sr + sc - mass);
+    if (!isinf(tau)) {
+        double kr = 0.0, kc = 0.0;
+        for (int64_t i = 0; i < n; ++i) kr += orc_kl_term(r[i], a[i]);
+        for (int64_t j = 0; j < m; ++j) kc += orc_kl_term(c[j], b[j]);
+        L += tau * (kr + kc);
+    }
+    return L;
+}
+
+/* ------------------------------------------------------------------ */
+/* Stabilised (absorbed) iteration                                      */
+/* ------------------------------------------------------------------ */
+
+/*
+ * The same iterates written on (f, g, u, v) with total scalings
+ * U = u e^{f/eps}, V = v e^{g/eps} and the rescaled kernel
+ * Kt_ij = exp((f_i + g_j - C_ij)/eps):
+ *     u = (a / (Kt v))^fi * exp(-(1-fi) f / eps)
+ *     v = (b / (Kt^T u))^fi * exp(-(1-fi) g / eps)
+ * After each half-step, if max|log u| or max|log v| exceeds threshold
+ * (> 0), both are absorbed (f += eps log u, g += eps log v, u = v = 1) and
+ * Kt is rebuilt.  Initial f_i = min_j C_ij, g = 0 (an exact
+ * reparameterisation: it only moves scale between u and Kt).
+ * Outputs f, g (final potentials of the total scalings, i.e. including the
+ * residual u, v), the residual u, v are folded in.  Returns iterations;
+ * *absorptions receives the number of absorptions.
+ */
+ORC_EXPORT int64_t orc_sinkhorn_stabilized(const double* C, const double* a, const double* b,
+                                           int64_t n, int64_t m, double eps, double tau,
+                                           int64_t max_iter, double threshold,
+                                           double* f, double* g, int64_t* absorptions) {
+    double fi = orc_fi(eps, tau);
+    double* Kt = (double*)malloc(sizeof(double) * (size_t)(n * m));
+    double* u = (double*)malloc(sizeof(double) * (size_t)n);
+    double* v = (double*)malloc(sizeof(double) * (size_t)m);
+    double* s = (double*)malloc(sizeof(double) * (size_t)n);
+    double* w = (double*)malloc(sizeof(double) * (size_t)m);
+    for (int64_t i = 0; i < n; ++i) {
+        double mn = INFINITY;
+        for (int64_t j = 0; j < m; ++j) if (C[i * m + j] < mn) mn = C[i * m + j];
+        f[i] = mn;
+        u[i] = 1.0;
+    }
+    for (int64_t j = 0; j < m; ++j) { g[j] = 0.0; v[j] = 1.0; }
+    orc_kernel(C, n, m, eps, f, g, Kt);
+    int64_t nabs = 0;
+    for (int64_t t = 0; t < max_iter; ++t) {
+        orc_Kv(Kt, v, n, m, s);
+        for (int64_t i = 0; i < n; ++i)
+            u[i] = (a[i] == 0.0) ? 0.0
+                 : pow(a[i] / s[i], fi) * exp(-(1.0 - fi) * f[i] / eps);
+        orc_KTu(Kt, u, n, m, w);
+        for (int64_t j = 0; j < m; ++j)
+            v[j] = (b[j] == 0.0) ? 0.0
+                 : pow(b[j] / w[j], fi) * exp(-(1.0 - fi) * g[j] / eps);
+        if (threshold > 0.0) {
+            double mx = 0.0;
+            for (int64_t i = 0; i < n; ++i) if (u[i] > 0.0 && fabs(log(u[i])) > mx) mx = fabs(log(u[i]));
+            for (int64_t j = 0; j < m; ++j) if (v[j] > 0.0 && fabs(log(v[j])) > mx) mx = fabs(log(v[j]));
+            if (mx > threshold) {
+                for (int64_t i = 0; i < n; ++i) { if (u[i] > 0.0) f[i] += eps * log(u[i]); u[i] = 1.0; }
+                for (int64_t j = 0; j < m; ++j) { if (v[j] > 0.0) g[j] += eps * log(v[j]); v[j] = 1.0; }
+                orc_kernel(C, n, m, eps, f, g, Kt);
+                ++nabs;
+            }
+        }
+    }
+    for (int64_t i = 0; i < n; ++i) f[i] = (u[i] > 0.0) ? f[i] + eps * log(u[i]) : -INFINITY;
+    for (int64_t j = 0; j < m; ++j) g[j] = (v[j] > 0.0) ? g[j] + eps * log(v[j]) : -INFINITY;
+    if (absorptions) *absorptions = nabs;
+    free(Kt); free(u); free(v); free(s); free(w);
+    return max_iter;
+}
+
+/* ------------------------------------------------------------------ */
+/* Reverse mode through the unrolled iteration                          */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Exact gradient of the objective (identity form, as a function of K, a, b
+ * through the T unrolled iterations from v_0 = 1) by reverse-mode
+ * differentiation.  Uses the forward trace written by orc_sinkhorn.
+ *
+ * Seeds, with r = u_T * (K v_T), c = v_T * (K^T u_T):
+ *   rbar = eps log u + tau log(r/a) - eps,   cbar = eps log v + tau log(c/b)
+ *   ubar = eps r/u + rbar * (K v) + K (cbar * v)
+ *   vbar = eps c/v + K^T (rbar * u) + cbar * (K^T u)
+ *   Kbar = (rbar * u) v^T + u (cbar * v)^T
+ *   abar = tau (1 - r/a),  bbar = tau (1 - c/b)          (tau = inf: 0, and
+ *                                                         the log(r/a) terms drop)
+ * Then for t = T..1:
+ *   wbar = -fi vbar * v_t / w_t;  bbar += fi vbar * v_t / b
+ *   ubar += K wbar;               Kbar += u_t wbar^T
+ *   sbar = -fi ubar * u_t / s_t;  abar += fi ubar * u_t / a
+ *   vbar  = K^T sbar;             Kbar += sbar v_{t-1}^T;   ubar = 0
+ * Outputs: grad_a (n), grad_b (m), and G = dL/dC = -Kbar * K / eps (n x m,
+ * optional, NULL to skip).  Zero-mass entries are not supported here.
+ */
+ORC_EXPORT void orc_adjoint(const double* K, const double* a, const double* b,
+                            int64_t n, int64_t m, double eps, double tau, int64_t T,
+                            const double* tr_v, const double* tr_s, const double* tr_u,
+                            const double* tr_w, double* grad_a, double* grad_b, double* G) {
+    double fi = orc_fi(eps, tau);
+    int bal = isinf(tau);
+    const double* uT = tr_u + (T - 1) * n;
+    const double* vT = tr_v + T * m;
+    double* Kbar = (double*)calloc((size_t)(n * m), sizeof(double));
+    double* sv = (double*)malloc(sizeof(double) * (size_t)n);   /* K v_T */
+    double* wu = (double*)malloc(sizeof(double) * (size_t)m);   /* K^T u_T */
+    double* rbar = (double*)malloc(sizeof(double) * (size_t)n);
+    double* cbar = (double*)malloc(sizeof(double) * (size_t)m);
+    double* ubar = (double*)malloc(sizeof(double) * (size_t)n);
+    double* vbar = (double*)malloc(sizeof(double) * (size_t)m);
+    double* tmpn = (double*)malloc(sizeof(double) * (size_t)n);
+    double* tmpm = (double*)malloc(sizeof(double) * (size_t)m);
+    double* wbar = (double*)malloc(sizeof(double) * (size_t)m);
+    double* sbar = (double*)malloc(sizeof(double) * (size_t)n);
+
+    orc_Kv(K, vT, n, m, sv);
+    orc_KTu(K, uT, n, m, wu);
+    for (int64_t i = 0; i < n; ++i) {
+        double r = uT[i] * sv[i];
+        rbar[i] = eps * log(uT[i]) - eps + (bal ? 0.0 : tau * log(r / a[i]));
+        grad_a[i] = bal ? 0.0 : tau * (1.0 - r / a[i]);
+    }
+    for (int64_t j = 0; j < m; ++j) {
+        double c = vT[j] * wu[j];
+        cbar[j] = eps * log(vT[j]) + (bal ? 0.0 : tau * log(c / b[j]));
+        grad_b[j] = bal ? 0.0 : tau * (1.0 - c / b[j]);
+    }
+    /* ubar = eps r/u + rbar*(K v) + K (cbar*v) ; note eps r/u = eps (K v) */
+    for (int64_t j = 0; j < m; ++j) tmpm[j] = cbar[j] * vT[j];
+    orc_Kv(K, tmpm, n, m, tmpn);
+    for (int64_t i = 0; i < n; ++i) ubar[i] = eps * sv[i] + rbar[i] * sv[i] + tmpn[i];
+    /* vbar = eps c/v + K^T(rbar*u) + cbar*(K^T u) ; eps c/v = eps (K^T u) */
+    for (int64_t i = 0; i < n; ++i) tmpn[i] = rbar[i] * uT[i];
+    orc_KTu(K, tmpn, n, m, tmpm);
+    for (int64_t j = 0; j < m; ++j) vbar[j] = eps * wu[j] + tmpm[j] + cbar[j] * wu[j];
+    /* Kbar = (rbar*u) v^T + u (cbar*v)^T */
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < m; ++j)
+            Kbar[i * m + j] = rbar[i] * uT[i] * vT[j] + uT[i] * cbar[j] * vT[j];
+
+    for (int64_t t = T; t >= 1; --t) {
+        const double* vt = tr_v + t * m;
+        const double* vprev = tr_v + (t - 1) * m;
+        const double* st = tr_s + (t - 1) * n;
+        const double* ut = tr_u + (t - 1) * n;
+        const double* wt = tr_w + (t - 1) * m;
+        for (int64_t j = 0; j < m; ++j) {
+            wbar[j] = (vt[j] == 0.0) ? 0.0 : -fi * vbar[j] * vt[j] / wt[j];
+            if (b[j] != 0.0) grad_b[j] += fi * vbar[j] * vt[j] / b[j];
+        }
+        orc_Kv(K, wbar, n, m, tmpn);
+        for (int64_t i = 0; i < n; ++i) ubar[i] += tmpn[i];
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = 0; j < m; ++j) Kbar[i * m + j] += ut[i] * wbar[j];
+        for (int64_t i = 0; i < n; ++i) {
+            sbar[i] = (ut[i] == 0.0) ? 0.0 : -fi * ubar[i] * ut[i] / st[i];
+            if (a[i] != 0.0) grad_a[i] += fi * ubar[i] * ut[i] / a[i];
+        }
+        orc_KTu(K, sbar, n, m, vbar);
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = 0; j < m; ++j) Kbar[i * m + j] += sbar[i] * vprev[j];
+        for (int64_t i = 0; i < n; ++i) ubar[i] = 0.0;
+    }
+    if (G) {
+        for (int64_t t = 0; t < n * m; ++t) G[t] = -Kbar[t] * K[t] / eps;
+    }
+    free(Kbar); free(sv); free(wu); free(rbar); free(cbar); free(ubar); free(vbar);
+    free(tmpn); free(tmpm); free(wbar); free(sbar);
+}
+
+/* Gradient with respect to the source points of a squared-Euclidean cost
+ * (not max-normalised): dL/dx_i = 2 sum_j G_ij (x_i - y_j). */
+ORC_EXPORT void orc_grad_points_sqeuclid(const double* G, const double* x, const double* y,
+                                         int64_t n, int64_t m, int64_t d, double* grad_x) {
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t k = 0; k < d; ++k) {
+            double acc = 0.0;
+            for (int64_t j = 0; j < m; ++j) acc += G[i * m + j] * (x[i * d + k] - y[j * d + k]);
+            grad_x[i * d + k] = 2.0 * acc;
+        }
+    }
+}

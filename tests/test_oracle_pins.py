@@ -1,0 +1,319 @@
+"""Pins of the FP64 oracle against mathematics that fixes its results.
+
+Every test here runs on the CPU.  The oracle is exercised on rectangular
+(n != m), non-symmetric problems so that a transposed operand, a swapped
+index, a dropped term or a wrong sign in it fails at least one test.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import pins
+import workloads
+
+
+def _problem_arrays(prob):
+    C = oracle.cost_points(prob.x, prob.y, prob.cost_kind, prob.normalize_max)
+    K = oracle.kernel(C, prob.eps)
+    return C, K
+
+
+# ---------------------------------------------------------------- P1: 1 x 1
+@pytest.mark.parametrize("T", [1, 2, 3, 7, 40])
+@pytest.mark.parametrize("tau", [1.0, 0.3, math.inf])
+def test_one_by_one_iterates(T, tau):
+    a, b, C, eps = 0.7, 1.3, 0.4, 0.05
+    K = np.array([[math.exp(-C / eps)]])
+    res = oracle.sinkhorn(K, np.array([a]), np.array([b]), eps, tau, T)
+    u_ref, v_ref = pins.one_by_one(a, b, C, eps, tau, T)
+    assert res.iters == T
+    assert res.u[0] == pytest.approx(u_ref, rel=1e-13)
+    assert res.v[0] == pytest.approx(v_ref, rel=1e-13)
+
+
+def test_one_by_one_limit_and_counterexample():
+    # Vector form reaches the UOT optimum; the paper's literal in-place form
+    # with fi < 1 reaches a different, cost-independent value (a reading
+    # recorded in the design notes).
+    a, b, C, eps, tau = 0.7, 1.3, 0.4, 0.05, 1.0
+    K = np.array([[math.exp(-C / eps)]])
+    res = oracle.sinkhorn(K, np.array([a]), np.array([b]), eps, tau, 2000)
+    P = res.u[0] * K[0, 0] * res.v[0]
+    assert P == pytest.approx(pins.one_by_one_limit(a, b, C, eps, tau), rel=1e-13)
+    assert P == pytest.approx(0.785742, abs=5e-7)
+    A = pins.paper_matrix_form(K, np.array([a]), np.array([b]), eps, tau, 2000)
+    fi = pins.fi_of(eps, tau)
+    literal = math.exp((math.log(b) + (1 - fi) * math.log(a)) / (2 - fi))
+    assert A[0, 0] == pytest.approx(literal, rel=1e-12)
+    assert A[0, 0] == pytest.approx(1.26393, abs=5e-6)
+
+
+# ---------------------------------------------------------------- P2: rank 1
+@pytest.mark.parametrize("n,m,T", [(37, 53, 1), (37, 53, 5), (64, 19, 30), (200, 311, 60)])
+@pytest.mark.parametrize("tau", [0.5, math.inf])
+def test_rank1_closed_form(n, m, T, tau):
+    prob = workloads.rank1(n, m, tau=tau)
+    C = np.add.outer(prob.alpha, prob.beta)
+    K = oracle.kernel(C, prob.eps)
+    res = oracle.sinkhorn(K, prob.a, prob.b, prob.eps, prob.tau, T)
+    lu, lv = pins.rank1(prob.alpha, prob.beta, prob.a, prob.b, prob.eps, prob.tau, T)
+    np.testing.assert_allclose(np.log(res.u), lu, rtol=0, atol=1e-11)
+    np.testing.assert_allclose(np.log(res.v), lv, rtol=0, atol=1e-11)
+
+
+# ---------------------------------------------------------------- P3: balanced limit
+def test_balanced_column_marginal_exact_and_paper_form():
+    prob = workloads.random_small(23, 17, seed=7, eps=0.2, tau=math.inf)
+    C, K = _problem_arrays(prob)
+    for T in (1, 4, 25):
+        res = oracle.sinkhorn(K, prob.a, prob.b, prob.eps, math.inf, T)
+        # after each column half-step with fi = 1 the column marginal is b
+        np.testing.assert_allclose(res.c, prob.b, rtol=1e-13, atol=0)
+        A = pins.paper_matrix_form(K, prob.a, prob.b, prob.eps, math.inf, T)
+        P = res.u[:, None] * K * res.v[None, :]
+        np.testing.assert_allclose(P, A, rtol=1e-12, atol=1e-300)
+
+
+def test_balanced_row_marginal_converges_with_equal_mass():
+    prob = workloads.random_small(23, 17, seed=8, eps=0.2, tau=math.inf)
+    b = prob.b / prob.b.sum()             # equal masses
+    C, K = _problem_arrays(prob)
+    res = oracle.sinkhorn(K, prob.a, b, prob.eps, math.inf, 3000)
+    np.testing.assert_allclose(res.r, prob.a, rtol=1e-10)
+
+
+def test_large_tau_approaches_balanced():
+    prob = workloads.random_small(15, 21, seed=9, eps=0.2, tau=math.inf)
+    b = prob.b / prob.b.sum()
+    C, K = _problem_arrays(prob)
+    bal = oracle.sinkhorn(K, prob.a, b, prob.eps, math.inf, 3000)
+    unb = oracle.sinkhorn(K, prob.a, b, prob.eps, 1e6, 3000)
+    P0 = bal.u[:, None] * K * bal.v[None, :]
+    P1 = unb.u[:, None] * K * unb.v[None, :]
+    assert np.max(np.abs(P1 - P0)) / np.max(P0) < 1e-5
+
+
+# ---------------------------------------------------------------- P4: invariants
+def _converged_plan(C, a, b, eps, tau, iters=4000):
+    K = oracle.kernel(C, eps)
+    res = oracle.sinkhorn(K, a, b, eps, tau, iters)
+    return res.u[:, None] * K * res.v[None, :]
+
+
+def test_cost_shift_and_mass_scaling_invariants():
+    prob = workloads.random_small(11, 14, seed=10, eps=0.3, tau=0.7)
+    C, _ = _problem_arrays(prob)
+    eps, tau = prob.eps, prob.tau
+    P = _converged_plan(C, prob.a, prob.b, eps, tau)
+    k = 0.37
+    Pk = _converged_plan(C + k, prob.a, prob.b, eps, tau)
+    np.testing.assert_allclose(Pk, P * math.exp(-k / (eps + 2 * tau)), rtol=1e-11)
+    lam = 2.5
+    Pl = _converged_plan(C, lam * prob.a, lam * prob.b, eps, tau)
+    np.testing.assert_allclose(Pl, P * lam ** (2 * tau / (eps + 2 * tau)), rtol=1e-11)
+
+
+def test_permutation_equivariance():
+    prob = workloads.random_small(12, 9, seed=11, eps=0.1, tau=0.5)
+    C, K = _problem_arrays(prob)
+    rng = np.random.default_rng(0)
+    pi, rho = rng.permutation(12), rng.permutation(9)
+    res = oracle.sinkhorn(K, prob.a, prob.b, prob.eps, prob.tau, 17)
+    resp = oracle.sinkhorn(K[pi][:, rho], prob.a[pi], prob.b[rho], prob.eps, prob.tau, 17)
+    np.testing.assert_allclose(resp.u, res.u[pi], rtol=1e-13)
+    np.testing.assert_allclose(resp.v, res.v[rho], rtol=1e-13)
+    assert resp.loss == pytest.approx(res.loss, rel=1e-13)
+
+
+# ---------------------------------------------------------------- P5: dual ascent
+def test_dual_monotone_and_weak_duality():
+    prob = workloads.random_small(13, 8, seed=12, eps=0.15, tau=0.8)
+    C, K = _problem_arrays(prob)
+    T = 60
+    res = oracle.sinkhorn(K, prob.a, prob.b, prob.eps, prob.tau, T, trace=True)
+    tr = res.trace
+    eps, tau = prob.eps, prob.tau
+    vals = []
+    gaps = []
+    for t in range(1, T + 1):
+        u = tr["u"][t - 1]
+        vprev, v = tr["v"][t - 1], tr["v"][t]
+        vals.append(pins.dual_value(eps * np.log(u), eps * np.log(vprev), C, prob.a, prob.b, eps, tau))
+        vals.append(pins.dual_value(eps * np.log(u), eps * np.log(v), C, prob.a, prob.b, eps, tau))
+        P = u[:, None] * K * v[None, :]
+        gaps.append(pins.primal_value(P, C, prob.a, prob.b, eps, tau) - vals[-1])
+    vals = np.array(vals)
+    assert np.all(np.diff(vals) >= -1e-14 * np.abs(vals[1:]))
+    assert min(gaps) >= -1e-13
+    assert gaps[-1] < 1e-3 * gaps[0]
+
+
+# ---------------------------------------------------------------- P6: objective identity
+@pytest.mark.parametrize("tau", [0.6, math.inf])
+def test_loss_identity_equals_definition(tau):
+    prob = workloads.random_small(19, 26, seed=13, eps=0.07, tau=tau)
+    C, K = _problem_arrays(prob)
+    res = oracle.sinkhorn(K, prob.a, prob.b, prob.eps, tau, 9)
+    direct, tc = oracle.loss_direct(C, K, res.u, res.v, prob.a, prob.b, prob.eps, tau)
+    P = res.u[:, None] * K * res.v[None, :]
+    numpy_def = pins.primal_value(P, C, prob.a, prob.b, prob.eps, tau)
+    assert res.loss == pytest.approx(direct, rel=1e-12)
+    assert direct == pytest.approx(numpy_def, rel=1e-12)
+    assert tc == pytest.approx(float((C * P).sum()), rel=1e-12)
+
+
+# ---------------------------------------------------------------- P7: Newton dual
+@pytest.mark.parametrize("n,m,eps,tau", [(5, 7, 0.5, 1.0), (8, 6, 0.1, 0.4), (3, 8, 0.05, 1.0)])
+def test_newton_dual_matches_converged_sinkhorn(n, m, eps, tau):
+    prob = workloads.random_small(n, m, seed=14 + n, eps=eps, tau=tau)
+    C, K = _problem_arrays(prob)
+    u_n, v_n, gnorm = pins.newton_dual(C, prob.a, prob.b, eps, tau)
+    assert gnorm < 1e-13
+    res = oracle.sinkhorn(K, prob.a, prob.b, eps, tau, 20000)
+    P_s = res.u[:, None] * K * res.v[None, :]
+    P_n = u_n[:, None] * K * v_n[None, :]
+    np.testing.assert_allclose(P_s, P_n, rtol=1e-10, atol=1e-14)
+    np.testing.assert_allclose(res.u, u_n, rtol=1e-10)
+    np.testing.assert_allclose(res.v, v_n, rtol=1e-10)
+
+
+# ---------------------------------------------------------------- P8: fixed point
+def test_fixed_point_residual_vanishes():
+    prob = workloads.plain_fp64(n=120, m=90)
+    C, K = _problem_arrays(prob)
+    fi = pins.fi_of(prob.eps, prob.tau)
+    res = oracle.sinkhorn(K, prob.a, prob.b, prob.eps, prob.tau, 3000)
+    Kv = K @ res.v
+    KTu = K.T @ res.u
+    assert np.max(np.abs(np.log(res.u) - fi * (np.log(prob.a) - np.log(Kv)))) < 1e-11
+    assert np.max(np.abs(np.log(res.v) - fi * (np.log(prob.b) - np.log(KTu)))) < 1e-11
+
+
+# ---------------------------------------------------------------- P9: adjoint
+def _fd_loss(C, a, b, eps, tau, T):
+    K = oracle.kernel(C, eps)
+    return oracle.sinkhorn(K, a, b, eps, tau, T).loss
+
+
+@pytest.mark.parametrize("T", [1, 3, 12])
+@pytest.mark.parametrize("tau", [0.8, math.inf])
+def test_adjoint_matches_central_differences(T, tau):
+    prob = workloads.random_small(6, 5, seed=21, eps=0.2, tau=tau)
+    C, K = _problem_arrays(prob)
+    a, b, eps = prob.a, prob.b, prob.eps
+    res = oracle.sinkhorn(K, a, b, eps, tau, T, trace=True)
+    ga, gb, G = oracle.adjoint(K, a, b, eps, tau, res)
+    # steps relative to each histogram entry (some are ~1e-4)
+    ha = 1e-5 * a
+    hb = 1e-5 * b
+    fd_a = np.array([(_fd_loss(C, a + ha[i] * e, b, eps, tau, T)
+                      - _fd_loss(C, a - ha[i] * e, b, eps, tau, T)) / (2 * ha[i])
+                     for i, e in enumerate(np.eye(6))])
+    fd_b = np.array([(_fd_loss(C, a, b + hb[j] * e, eps, tau, T)
+                      - _fd_loss(C, a, b - hb[j] * e, eps, tau, T)) / (2 * hb[j])
+                     for j, e in enumerate(np.eye(5))])
+    h = 1e-6
+    fd_C = np.zeros_like(C)
+    for i in range(6):
+        for j in range(5):
+            E = np.zeros_like(C)
+            E[i, j] = h
+            fd_C[i, j] = (_fd_loss(C + E, a, b, eps, tau, T) - _fd_loss(C - E, a, b, eps, tau, T)) / (2 * h)
+    scale_a = max(1.0, np.max(np.abs(fd_a)))
+    np.testing.assert_allclose(ga, fd_a, rtol=0, atol=2e-7 * scale_a)
+    np.testing.assert_allclose(gb, fd_b, rtol=0, atol=2e-7 * max(1.0, np.max(np.abs(fd_b))))
+    np.testing.assert_allclose(G, fd_C, rtol=0, atol=2e-7 * max(1.0, np.max(np.abs(fd_C))))
+
+
+def test_adjoint_points_matches_central_differences():
+    prob = workloads.grad(n=7, m=6, max_iter=8)
+    eps, tau, T = prob.eps, prob.tau, prob.max_iter
+
+    def loss_x(x):
+        C = oracle.cost_points(x, prob.y, 0, False)
+        return _fd_loss(C, prob.a, prob.b, eps, tau, T)
+
+    C, K = _problem_arrays(prob)
+    res = oracle.sinkhorn(K, prob.a, prob.b, eps, tau, T, trace=True)
+    _, _, G = oracle.adjoint(K, prob.a, prob.b, eps, tau, res)
+    gx = oracle.grad_points_sqeuclid(G, prob.x, prob.y)
+    h = 1e-6
+    fd = np.zeros_like(prob.x)
+    for i in range(prob.x.shape[0]):
+        for k in range(3):
+            E = np.zeros_like(prob.x)
+            E[i, k] = h
+            fd[i, k] = (loss_x(prob.x + E) - loss_x(prob.x - E)) / (2 * h)
+    np.testing.assert_allclose(gx, fd, rtol=0, atol=2e-7 * max(1.0, np.max(np.abs(fd))))
+
+
+def test_adjoint_envelope_at_convergence():
+    # At the optimum dL/dC = P, dL/da = tau (1 - r/a), dL/db = tau (1 - c/b).
+    prob = workloads.random_small(9, 7, seed=22, eps=0.3, tau=1.0)
+    C, K = _problem_arrays(prob)
+    res = oracle.sinkhorn(K, prob.a, prob.b, prob.eps, prob.tau, 400, trace=True)
+    ga, gb, G = oracle.adjoint(K, prob.a, prob.b, prob.eps, prob.tau, res)
+    P = res.u[:, None] * K * res.v[None, :]
+    np.testing.assert_allclose(G, P, rtol=1e-9, atol=1e-14)
+    np.testing.assert_allclose(ga, prob.tau * (1 - res.r / prob.a), rtol=0, atol=1e-9)
+    np.testing.assert_allclose(gb, prob.tau * (1 - res.c / prob.b), rtol=0, atol=1e-9)
+
+
+# ---------------------------------------------------------------- P10: absorption
+def test_stabilized_equals_plain():
+    prob = workloads.random_small(14, 10, seed=23, eps=0.02, tau=0.3)
+    C, K = _problem_arrays(prob)
+    T = 40
+    res = oracle.sinkhorn(K, prob.a, prob.b, prob.eps, prob.tau, T)
+    for thr in (0.0, 0.5, 3.0):
+        f, g, nabs = oracle.sinkhorn_stabilized(C, prob.a, prob.b, prob.eps, prob.tau, T, thr)
+        np.testing.assert_allclose(f / prob.eps, np.log(res.u), rtol=0, atol=1e-11)
+        np.testing.assert_allclose(g / prob.eps, np.log(res.v), rtol=0, atol=1e-11)
+        if thr == 0.5:
+            assert nabs > 0
+
+
+# ---------------------------------------------------------------- special cases
+def test_zero_mass_entries_and_zero_iterations():
+    prob = workloads.random_small(10, 8, seed=24, eps=0.1, tau=0.5)
+    C, K = _problem_arrays(prob)
+    a = prob.a.copy()
+    b = prob.b.copy()
+    a[3] = 0.0
+    b[5] = 0.0
+    res = oracle.sinkhorn(K, a, b, prob.eps, prob.tau, 12)
+    assert res.u[3] == 0.0 and res.v[5] == 0.0
+    assert res.r[3] == 0.0 and res.c[5] == 0.0
+    assert np.all(np.isfinite(res.u)) and np.isfinite(res.loss)
+    r0 = oracle.sinkhorn(K, a, b, prob.eps, prob.tau, 0)
+    assert r0.iters == 0 and np.all(r0.u == 1.0) and np.all(r0.v == 1.0)
+    direct, _ = oracle.loss_direct(C, K, r0.u, r0.v, a, b, prob.eps, prob.tau)
+    assert r0.loss == pytest.approx(direct, rel=1e-12)
+
+
+def test_tolerance_stops_early_and_err_is_relative_l1():
+    prob = workloads.random_small(30, 20, seed=25, eps=0.1, tau=0.5)
+    C, K = _problem_arrays(prob)
+    res = oracle.sinkhorn(K, prob.a, prob.b, prob.eps, prob.tau, 5000, tol=1e-9)
+    assert 1 < res.iters < 5000 and res.err <= 1e-9
+    r1 = oracle.sinkhorn(K, prob.a, prob.b, prob.eps, prob.tau, res.iters - 1)
+    r2 = oracle.sinkhorn(K, prob.a, prob.b, prob.eps, prob.tau, res.iters)
+    assert np.sum(np.abs(r2.c - r1.c)) / np.sum(r2.c) == pytest.approx(res.err, rel=1e-9)
+    assert np.sum(np.abs(r2.c - r1.c)) / np.sum(r2.c) <= 1e-9
+    prev = oracle.sinkhorn(K, prob.a, prob.b, prob.eps, prob.tau, res.iters - 1, tol=1e-9)
+    assert prev.iters == res.iters - 1      # it did not stop earlier
+
+
+def test_cost_points_kinds():
+    rng = np.random.default_rng(3)
+    x = rng.random((4, 3))
+    y = rng.random((5, 3))
+    C = oracle.cost_points(x, y, 0, False)
+    assert C[2, 4] == pytest.approx(float(np.sum((x[2] - y[4]) ** 2)), rel=1e-15)
+    Cn = oracle.cost_points(x, y, 0, True)
+    assert Cn.max() == 1.0
+    np.testing.assert_allclose(Cn * C.max(), C, rtol=1e-15)
+    Cc = oracle.cost_points(x, y, 1, False)
+    assert Cc[1, 3] == pytest.approx(1.0 - float(x[1] @ y[3]), rel=1e-15)
