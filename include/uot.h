@@ -1,0 +1,209 @@
+/*
+ * uot.h -- C-ABI of the MI355X (gfx950) entropic unbalanced-OT Sinkhorn
+ * library (libuot.so).
+ *
+ * The method (paper Section 2.1, with the four-part split of Section 4):
+ * a non-negative n x m matrix is rescaled alternately by rows and by
+ * columns, the factor of row i being (row target_i / row sum_i)^fi with
+ * fi = tau/(tau+eps).  Written on scaling vectors, with the Gibbs kernel
+ * K = exp(-C/eps) and the plan P = diag(u) K diag(v), one iteration is
+ *
+ *     row half-step     s = K v,      u = (a / s)^fi       (parts 4, 1)
+ *     column half-step  w = K^T u,    v = (b / w)^fi       (parts 2, 3)
+ *
+ * rows first, from v = 1.  The library streams K once per iteration
+ * (fused single pass; the paper's interleaving idea of Section 4.1 applied
+ * to a read-only K) or twice (plain two-pass form, for comparison).
+ *
+ * Conventions shared by every entry point:
+ *  - Every array pointer is a DEVICE pointer owned by the caller; the
+ *    library never frees or retains it after the call returns.  Scratch
+ *    memory comes only from the caller's workspace (ws, ws_bytes); the
+ *    library allocates no device memory.  (It allocates one small pinned
+ *    host buffer per process, once, to read the convergence flag.)
+ *  - Matrices are row-major with a leading dimension (elements between the
+ *    starts of consecutive rows).  Matrix base pointers must be 16-byte
+ *    aligned and the leading dimension a multiple of 16/sizeof(element);
+ *    otherwise UOT_ERR_ALIGN.  Vector pointers must be 8-byte aligned.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  All work is
+ *    enqueued on it; calls return before the GPU finishes unless stated.
+ *  - Argument errors are detected on the host before anything is enqueued
+ *    and returned as a uot_status; uot_last_error() then describes them.
+ *    Numerical trouble found on the GPU (non-finite scalings, a zero row or
+ *    column sum with positive mass) is reported in uot_info.flags, which is
+ *    device memory: read it after synchronising the stream.
+ */
+#ifndef UOT_H
+#define UOT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum uot_status {
+    UOT_OK = 0,
+    UOT_ERR_ARG = 1,          /* bad size, NULL pointer, eps <= 0, tau <= 0, ... */
+    UOT_ERR_DTYPE = 2,        /* dtype not supported by this entry point */
+    UOT_ERR_ALIGN = 3,        /* base or leading dimension not aligned */
+    UOT_ERR_WORKSPACE = 4,    /* ws_bytes smaller than the size query returns */
+    UOT_ERR_UNSUPPORTED = 5,  /* valid request outside the implemented envelope */
+    UOT_ERR_HIP = 6           /* a HIP runtime call failed */
+} uot_status;
+
+typedef enum uot_dtype {
+    UOT_F64 = 0,
+    UOT_F32 = 1,
+    UOT_BF16 = 2,             /* bfloat16, round-to-nearest-even from FP64 */
+    UOT_FP8_E4M3 = 3          /* OCP E4M3FN (max 448), RNE with saturation */
+} uot_dtype;
+
+typedef enum uot_cost_kind {
+    UOT_COST_SQEUCLID = 0,    /* C_ij = ||x_i - y_j||^2 */
+    UOT_COST_COSINE = 1       /* C_ij = 1 - x_i . y_j  */
+} uot_cost_kind;
+
+typedef enum uot_accum {
+    UOT_ACC_F32 = 0,          /* per-lane products and column partials in FP32 */
+    UOT_ACC_F64 = 1           /* ... in FP64 (FP32 K only; FP64 K always uses FP64) */
+} uot_accum;
+
+/* uot_info.flags bits */
+#define UOT_FLAG_NONFINITE     1u   /* a scaling became inf or NaN */
+#define UOT_FLAG_ZERO_SUM      2u   /* a row or column sum was 0 with positive mass */
+#define UOT_FLAG_NOT_CONVERGED 8u   /* tol > 0 and max_iter reached first */
+
+/* Device-resident solver report. */
+typedef struct uot_info {
+    int64_t iters;            /* iterations run */
+    double err;               /* relative L1 change of the column marginal at the last iteration */
+    int32_t absorptions;      /* log-domain absorptions performed */
+    uint32_t flags;           /* UOT_FLAG_* */
+} uot_info;
+
+/* One UOT problem (Section 2.1).  a: n row targets, b: m column targets
+ * (FP64, >= 0; a zero entry gives a zero scaling).  The kernel is given
+ * either as K (k_dtype, K, ldk) or, when K is NULL, built from the FP64 cost
+ * C (ldc) into the workspace in k_dtype.  eps > 0; tau > 0 or +inf
+ * (balanced limit, fi = 1). */
+typedef struct uot_problem {
+    int64_t n, m;
+    const double* a;
+    const double* b;
+    int32_t k_dtype;          /* uot_dtype of K */
+    const void* K;            /* n x ldk, or NULL */
+    int64_t ldk;
+    const double* C;          /* n x ldc FP64 cost, or NULL (needed when K is NULL) */
+    int64_t ldc;
+    double eps;
+    double tau;
+} uot_problem;
+
+typedef struct uot_options {
+    int32_t max_iter;         /* >= 0 iterations */
+    int32_t check_every;      /* with tol > 0: host reads the stop flag every this many iterations (<= 0: 1) */
+    double tol;               /* > 0: stop when the error is <= tol; <= 0: run exactly max_iter */
+    int32_t fused;            /* 1: single pass over K per iteration; 0: plain row pass + column pass */
+    int32_t accum;            /* uot_accum */
+    double absorb_log_threshold;  /* reserved, must be 0 */
+    int32_t checkpoint_every; /* reserved, must be 0 */
+    int32_t tune;             /* 0: default launch shape; k > 0: use tuned shape index k-1 */
+    const double* u0;         /* optional warm start (device, n), else u = 1 */
+    const double* v0;         /* optional warm start (device, m), else v = 1 */
+} uot_options;
+
+typedef struct uot_outputs {
+    double* u;                /* required: device n, final u_T (FP64) */
+    double* v;                /* required: device m, final v_T (FP64) */
+    double* r;                /* optional: device n, row marginal u * (K v) */
+    double* c;                /* optional: device m, column marginal v * (K^T u) */
+    double* loss;             /* optional: device scalar, UOT objective of P_T */
+    uot_info* info;           /* optional: device report */
+} uot_outputs;
+
+/* Per-kernel durations of one uot_sinkhorn_profiled call, measured with HIP
+ * events recorded on `stream` around every launch of the iteration loop. */
+typedef struct uot_profile {
+    int32_t fused_launches;   /* single-pass launches (row + column half-steps) */
+    float fused_ms;           /* their summed duration */
+    int32_t row_launches;     /* plain row-pass launches */
+    float row_ms;
+    int32_t col_launches;     /* plain column-pass launches */
+    float col_ms;
+    int32_t finalize_launches;
+    float finalize_ms;
+    float loop_ms;            /* first to last event of the iteration loop */
+} uot_profile;
+
+/* Status text, and a thread-local description of the last error. */
+const char* uot_status_string(uot_status s);
+const char* uot_last_error(void);
+
+/*
+ * Dense FP64 cost from points (the cost C whose Gibbs kernel is rescaled,
+ * Section 2.1).  x: n x d, y: m x d (FP64, row-major, contiguous).
+ * kind: uot_cost_kind.  normalize_max != 0 divides the whole matrix by its
+ * maximum (when that maximum is > 0).  C: n x ldc FP64 output, ldc >= m.
+ * Workspace: uot_cost_workspace_size(n, m) bytes (for the max reduction).
+ * Errors: UOT_ERR_ARG for n, m, d <= 0 or NULL pointers; UOT_ERR_WORKSPACE.
+ */
+size_t uot_cost_workspace_size(int64_t n, int64_t m);
+uot_status uot_cost_from_points(const double* x, const double* y, int64_t n, int64_t m,
+                                int64_t d, int32_t kind, int32_t normalize_max,
+                                double* C, int64_t ldc, void* ws, size_t ws_bytes,
+                                void* stream);
+
+/*
+ * Gibbs kernel K_ij = exp((f_i + g_j - C_ij)/eps) (Section 2.1's matrix A,
+ * built from its cost), evaluated in FP64 and rounded to nearest-even into
+ * k_dtype (UOT_F64 or UOT_F32).  f, g: optional FP64 potentials (NULL = 0).
+ * C: n x ldc FP64.  K: n x ldk output.
+ * Errors: UOT_ERR_ARG, UOT_ERR_DTYPE, UOT_ERR_ALIGN.
+ */
+uot_status uot_kernel_from_cost(const double* C, int64_t ldc, int64_t n, int64_t m,
+                                double eps, const double* f, const double* g,
+                                int32_t k_dtype, void* K, int64_t ldk, void* stream);
+
+/*
+ * Workspace bytes that uot_sinkhorn needs for this problem and options
+ * (0 on invalid arguments).
+ */
+size_t uot_sinkhorn_workspace_size(const uot_problem* prob, const uot_options* opt);
+
+/*
+ * The UOT Sinkhorn scaling loop (Section 2.1; Section 4's interleaved
+ * single pass when opt->fused != 0).  Runs up to opt->max_iter iterations
+ * of the row then column half-step from v = 1 (or the warm start), stops
+ * early when tol > 0 and the relative L1 change of the column marginal
+ * c = v * (K^T u) is <= tol, then forms the marginals and the objective
+ *     <C,P> + eps sum P(log P - 1) + tau KL~(P1|a) + tau KL~(P^T1|b)
+ * (KL~(x|y) = sum x log(x/y) - x + y; the KL terms are dropped for
+ * tau = inf) in FP64 from O(n+m) quantities.
+ *
+ * K dtypes: UOT_F64, UOT_F32.  Scalings and all reductions across lanes
+ * and workgroups are FP64 (opt->accum picks the per-lane type for FP32 K).
+ * Results are bitwise reproducible for a fixed problem and launch shape.
+ * With tol > 0 the host synchronises on `stream` every check_every
+ * iterations; with tol <= 0 the call only enqueues work.
+ *
+ * Errors: UOT_ERR_ARG (n or m < 1, NULL a/b/u/v, eps <= 0, tau <= 0,
+ * max_iter < 0, neither K nor C), UOT_ERR_DTYPE, UOT_ERR_ALIGN,
+ * UOT_ERR_WORKSPACE, UOT_ERR_UNSUPPORTED (m above the row length one
+ * workgroup holds: 16384 FP32, 8192 FP64), UOT_ERR_HIP.
+ */
+uot_status uot_sinkhorn(const uot_problem* prob, const uot_options* opt,
+                        const uot_outputs* out, void* ws, size_t ws_bytes, void* stream);
+
+/* uot_sinkhorn with per-kernel HIP-event timing written to *prof (host
+ * pointer).  Synchronises `stream` before returning. */
+uot_status uot_sinkhorn_profiled(const uot_problem* prob, const uot_options* opt,
+                                 const uot_outputs* out, void* ws, size_t ws_bytes,
+                                 void* stream, uot_profile* prof);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* UOT_H */

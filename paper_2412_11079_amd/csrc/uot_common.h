@@ -1,0 +1,201 @@
+// Internal declarations shared by the HIP translation units of libuot.so.
+// (Not part of the public C-ABI; see include/uot.h.)
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "uot.h"
+
+namespace uot {
+
+// ---------------------------------------------------------------------------
+// Device control block (lives in the workspace).
+// ---------------------------------------------------------------------------
+struct Ctrl {
+    uint32_t done;      // set once the stopping test passed; later launches return at once
+    uint32_t counter;   // arrival counter of the column-finalize blocks (reset by the last)
+    uint32_t flags;     // UOT_FLAG_* accumulated on the device
+    uint32_t pad0;
+    int64_t iters;      // iterations completed
+    double err;         // error of the last completed iteration
+};
+
+// ---------------------------------------------------------------------------
+// Storage types of K and their 16-byte vector loads.
+// ---------------------------------------------------------------------------
+struct bf16_t { uint16_t bits; };
+struct fp8_t { uint8_t bits; };
+
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <typename KT> struct KVec;
+template <> struct KVec<double> { using raw = f64x2; static constexpr int N = 2; };
+template <> struct KVec<float>  { using raw = f32x4; static constexpr int N = 4; };
+template <> struct KVec<bf16_t> { using raw = u32x4; static constexpr int N = 8; };
+template <> struct KVec<fp8_t>  { using raw = u32x4; static constexpr int N = 16; };
+
+template <typename T>
+__device__ __forceinline__ T zero_raw() {
+    T z;
+    __builtin_memset(&z, 0, sizeof(T));
+    return z;
+}
+
+// Expand one 16-byte vector into N arithmetic values.
+template <typename AT>
+__device__ __forceinline__ void unpack(const f64x2& r, AT* o) {
+    o[0] = (AT)r[0];
+    o[1] = (AT)r[1];
+}
+template <typename AT>
+__device__ __forceinline__ void unpack(const f32x4& r, AT* o) {
+    o[0] = (AT)r[0];
+    o[1] = (AT)r[1];
+    o[2] = (AT)r[2];
+    o[3] = (AT)r[3];
+}
+
+// ---------------------------------------------------------------------------
+// Cross-lane helpers (wave64).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum_f64(double x) {
+    // Butterfly: every lane ends with the same, order-fixed sum.
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+__device__ __forceinline__ double wave_max_f64(double x) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x = fmax(x, __shfl_xor(x, off, 64));
+    return x;
+}
+
+__device__ __forceinline__ double readlane_f64(double x, int lane) {
+    int lo = __double2loint(x), hi = __double2hiint(x);
+    lo = __builtin_amdgcn_readlane(lo, lane);
+    hi = __builtin_amdgcn_readlane(hi, lane);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ float readlane_f32(float x, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
+}
+
+template <typename AT> __device__ __forceinline__ AT readlane_at(AT x, int lane);
+template <> __device__ __forceinline__ float readlane_at<float>(float x, int lane) { return readlane_f32(x, lane); }
+template <> __device__ __forceinline__ double readlane_at<double>(double x, int lane) { return readlane_f64(x, lane); }
+
+// Scaling factor (target / sum)^fi times exp(shift); zero target -> 0.
+__device__ __forceinline__ double scale_factor(double target, double sum, double fi, int fi_is_one,
+                                               double shift) {
+    if (target == 0.0) return 0.0;
+    double q = target / sum;
+    double f = fi_is_one ? q : exp(fi * log(q));
+    if (shift != 0.0) f *= exp(shift);
+    return f;
+}
+
+__device__ __forceinline__ uint32_t ld_volatile_u32(const uint32_t* p) {
+    return *(const volatile uint32_t*)p;
+}
+
+// ---------------------------------------------------------------------------
+// Pass kernels (pass.hip).
+// ---------------------------------------------------------------------------
+enum PassMode { MODE_FUSED = 0, MODE_ROW = 1, MODE_COL = 2, MODE_MARG = 3 };
+
+struct PassLaunch {
+    const void* K;
+    int64_t ldk;
+    int64_t n, m;
+    int64_t rows_per_wg;
+    int32_t grid;              // number of row strips (workgroups)
+    const double* v;           // m
+    const double* a;           // n
+    double* u;                 // n
+    double* s_out;             // n (MODE_MARG)
+    void* partials;            // grid x ldp, FP32 or FP64
+    int64_t ldp;
+    double fi;
+    int32_t fi_is_one;
+    const double* fpot;        // optional row potentials (stabilised form)
+    double inv_eps;
+    Ctrl* ctrl;
+    int32_t check_done;
+    int64_t ldv_bytes;         // LDS bytes for v (shapes that keep v in LDS), multiple of 16
+};
+
+struct PassShape {
+    int wg;       // threads per workgroup
+    int nc;       // 16-byte chunks per lane per row
+    int depth;    // rows in flight (software pipeline depth)
+    int vlds;     // 1: v read from LDS, 0: v held in registers
+};
+
+// Number of instantiated shapes and their table.
+int pass_shape_count();
+PassShape pass_shape(int idx);
+size_t pass_lds_bytes(int shape_idx, int mode, int acc64, const PassLaunch& L);
+
+// Launch one streaming pass; returns hipSuccess or an error.  k_dtype and
+// acc64 select the instantiation; shape_idx indexes pass_shape().
+hipError_t launch_pass(int k_dtype, int acc64, int mode, int shape_idx, const PassLaunch& L,
+                       hipStream_t stream);
+
+// ---------------------------------------------------------------------------
+// Auxiliary kernels (aux.hip).
+// ---------------------------------------------------------------------------
+struct FinLaunch {
+    const void* partials;     // G x ldp
+    int64_t ldp;
+    int32_t G;
+    int64_t m;
+    const double* b;
+    double* v;                // in/out
+    double* w_out;            // m (optional)
+    double* cprev;            // m
+    double* c_out;            // m (marginal mode, optional)
+    double fi;
+    int32_t fi_is_one;
+    const double* gpot;       // optional column potentials
+    double inv_eps;
+    Ctrl* ctrl;
+    double tol;
+    double* blockpart;        // 2 x nblocks
+    int32_t marginal_only;    // 1: only w and c are formed
+    int32_t acc64;
+};
+
+hipError_t launch_finalize(const FinLaunch& F, hipStream_t stream);
+int finalize_blocks(int64_t m);
+
+hipError_t launch_init(double* u, int64_t n, const double* u0, double* v, int64_t m, const double* v0,
+                       double* cprev, Ctrl* ctrl, hipStream_t stream);
+
+struct ObjLaunch {
+    const double* u; const double* v;
+    const double* s; const double* w;   // K v and K^T u
+    const double* a; const double* b;
+    int64_t n, m;
+    double eps, tau;
+    int32_t tau_inf;
+    double* r_out; double* c_out; double* loss;
+    uot_info* info;
+    const Ctrl* ctrl;
+    double tol;
+};
+hipError_t launch_objective(const ObjLaunch& O, hipStream_t stream);
+
+hipError_t launch_cost(const double* x, const double* y, int64_t n, int64_t m, int64_t d, int kind,
+                       int normalize, double* C, int64_t ldc, double* blockmax, hipStream_t stream);
+int64_t cost_blocks(int64_t n, int64_t m);
+
+hipError_t launch_kernel_build(const double* C, int64_t ldc, int64_t n, int64_t m, double eps,
+                               const double* f, const double* g, int k_dtype, void* K, int64_t ldk,
+                               hipStream_t stream);
+
+}  // namespace uot
