@@ -74,6 +74,7 @@ typedef enum uot_accum {
 #define UOT_FLAG_NONFINITE     1u   /* a scaling became inf or NaN */
 #define UOT_FLAG_ZERO_SUM      2u   /* a row or column sum was 0 with positive mass */
 #define UOT_FLAG_NOT_CONVERGED 8u   /* tol > 0 and max_iter reached first */
+#define UOT_FLAG_BARRIER_TIMEOUT 16u /* persistent loop: a grid-barrier wait hit its bound (results invalid) */
 
 /* Device-resident solver report. */
 typedef struct uot_info {
@@ -112,6 +113,10 @@ typedef struct uot_options {
     int32_t tune;             /* 0: default launch shape; k > 0: use tuned shape index k-1 */
     const double* u0;         /* optional warm start (device, n), else u = 1 */
     const double* v0;         /* optional warm start (device, m), else v = 1 */
+    int32_t persistent;       /* fused only: 1 = the whole loop in one cooperative launch with grid
+                                 barriers (UOT_ERR_UNSUPPORTED when the grid cannot be co-resident
+                                 or m > workgroup size * grid); 0 = two launches per iteration */
+    int32_t reserved0;
 } uot_options;
 
 typedef struct uot_outputs {
@@ -124,9 +129,10 @@ typedef struct uot_outputs {
 } uot_outputs;
 
 /* Per-kernel durations of one uot_sinkhorn_profiled call, measured with HIP
- * events recorded on `stream` around every launch of the iteration loop. */
+ * events recorded on `stream` around every launch of every 8th iteration
+ * (counts below are those timed launches), plus the whole loop. */
 typedef struct uot_profile {
-    int32_t fused_launches;   /* single-pass launches (row + column half-steps) */
+    int32_t fused_launches;   /* timed single-pass launches (row + column half-steps) */
     float fused_ms;           /* their summed duration */
     int32_t row_launches;     /* plain row-pass launches */
     float row_ms;
@@ -134,7 +140,7 @@ typedef struct uot_profile {
     float col_ms;
     int32_t finalize_launches;
     float finalize_ms;
-    float loop_ms;            /* first to last event of the iteration loop */
+    float loop_ms;            /* whole iteration loop (all iterations) */
 } uot_profile;
 
 /* Status text, and a thread-local description of the last error. */
@@ -196,8 +202,8 @@ size_t uot_sinkhorn_workspace_size(const uot_problem* prob, const uot_options* o
 uot_status uot_sinkhorn(const uot_problem* prob, const uot_options* opt,
                         const uot_outputs* out, void* ws, size_t ws_bytes, void* stream);
 
-/* uot_sinkhorn with per-kernel HIP-event timing written to *prof (host
- * pointer).  Synchronises `stream` before returning. */
+/* uot_sinkhorn with HIP-event timing of the streaming kernels written to
+ * *prof (host pointer).  Synchronises `stream` before returning. */
 uot_status uot_sinkhorn_profiled(const uot_problem* prob, const uot_options* opt,
                                  const uot_outputs* out, void* ws, size_t ws_bytes,
                                  void* stream, uot_profile* prof);

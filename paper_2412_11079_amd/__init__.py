@@ -144,7 +144,8 @@ def sinkhorn(a: torch.Tensor, b: torch.Tensor, K: Optional[torch.Tensor] = None,
              m: Optional[int] = None, eps: float, tau: float, max_iter: int, tol: float = 0.0,
              fused: bool = True, accum: str = "f32", check_every: int = 1, tune: int = 0,
              k_dtype: Optional[torch.dtype] = None, u0: Optional[torch.Tensor] = None,
-             v0: Optional[torch.Tensor] = None, profile: bool = False) -> SinkhornResult:
+             v0: Optional[torch.Tensor] = None, persistent: bool = False,
+             profile: bool = False) -> SinkhornResult:
     """UOT Sinkhorn scaling loop on the GPU (see include/uot.h, uot_sinkhorn).
 
     ``K`` is an (n, ldk) FP32/FP64 kernel (as returned by kernel_from_cost);
@@ -170,6 +171,7 @@ def sinkhorn(a: torch.Tensor, b: torch.Tensor, K: Optional[torch.Tensor] = None,
     opt.tune = int(tune)
     opt.u0 = None if u0 is None else _vec64(u0, "u0", n, device).data_ptr()
     opt.v0 = None if v0 is None else _vec64(v0, "v0", m, device).data_ptr()
+    opt.persistent = 1 if persistent else 0
     L = _lib.lib()
     need = L.uot_sinkhorn_workspace_size(ctypes.byref(prob), ctypes.byref(opt))
     if need == 0:

@@ -11,7 +11,7 @@ UOT_OK, UOT_ERR_ARG, UOT_ERR_DTYPE, UOT_ERR_ALIGN, UOT_ERR_WORKSPACE, UOT_ERR_UN
 UOT_F64, UOT_F32, UOT_BF16, UOT_FP8_E4M3 = range(4)
 UOT_COST_SQEUCLID, UOT_COST_COSINE = 0, 1
 UOT_ACC_F32, UOT_ACC_F64 = 0, 1
-UOT_FLAG_NONFINITE, UOT_FLAG_ZERO_SUM, UOT_FLAG_NOT_CONVERGED = 1, 2, 8
+UOT_FLAG_NONFINITE, UOT_FLAG_ZERO_SUM, UOT_FLAG_NOT_CONVERGED, UOT_FLAG_BARRIER_TIMEOUT = 1, 2, 8, 16
 
 _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
@@ -32,7 +32,7 @@ class Problem(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("max_iter", _i32), ("check_every", _i32), ("tol", _dbl), ("fused", _i32), ("accum", _i32),
                 ("absorb_log_threshold", _dbl), ("checkpoint_every", _i32), ("tune", _i32),
-                ("u0", _vp), ("v0", _vp)]
+                ("u0", _vp), ("v0", _vp), ("persistent", _i32), ("reserved0", _i32)]
 
 
 class Outputs(ctypes.Structure):

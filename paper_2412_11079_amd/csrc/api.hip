@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -93,6 +94,10 @@ struct Plan {
     int64_t ldk_ws;       // leading dimension of a K built into the workspace
     int64_t ldv_bytes;    // LDS bytes holding v (shapes with v in LDS)
     size_t lds_bytes;     // LDS per workgroup (estimate incl. static)
+    bool persistent;      // whole loop in one cooperative launch
+    int32_t fin_cols;     // persistent: columns finalized per workgroup
+    int64_t scratch_bytes;  // persistent: LDS before the row strips
+    int32_t fin_blocks;   // blocks that write stopping-test sums
     bool build_k;
     // workspace offsets
     size_t off_ctrl, off_cprev, off_w, off_s, off_bp, off_part, off_k, total;
@@ -166,13 +171,35 @@ uot_status make_plan(const uot_problem* p, const uot_options* o, Plan& P) {
                         (long long)p->m, 4096 * P.vec);
     }
     PassShape s = pass_shape(P.shape);
+    P.ldp = round_up(p->m, 64);
+    P.ldv_bytes = round_up(round_up(p->m, P.vec) * (P.acc64 ? 8 : 4), 16);
+    P.persistent = o->persistent != 0;
+    if (P.persistent && !o->fused)
+        return fail(UOT_ERR_ARG, "the persistent loop runs the fused pass only");
     int64_t target = 256LL * (1024 / s.wg);     // about one wave of workgroups on 256 CUs
+    if (P.persistent) {
+        // LDS: max(v, finalize scratch of 4 doubles per thread), then the row strips
+        P.scratch_bytes = round_up(std::max<int64_t>(s.vlds ? P.ldv_bytes : 0, (int64_t)s.wg * 32), 16);
+        int64_t rows_guess = (p->n + 255) / 256;
+        size_t lds_guess = (size_t)P.scratch_bytes + 2 * sizeof(double) * (size_t)rows_guess;
+        int gmax = persist_max_grid(P.k_dtype, P.acc64, P.shape, lds_guess);
+        if (gmax <= 0) return fail(UOT_ERR_UNSUPPORTED, "shape %d cannot run as a cooperative launch", P.shape);
+        target = gmax;
+    }
     if (target > p->n) target = p->n;
     P.rows_per_wg = (p->n + target - 1) / target;
     P.G = (int32_t)((p->n + P.rows_per_wg - 1) / P.rows_per_wg);
-    P.ldp = round_up(p->m, 64);
-    P.ldv_bytes = round_up(round_up(p->m, P.vec) * (P.acc64 ? 8 : 4), 16);
-    P.lds_bytes = 2 * sizeof(double) * (size_t)P.rows_per_wg + (s.vlds ? (size_t)P.ldv_bytes : 0) + 1024;
+    if (P.persistent) {
+        P.fin_cols = (int32_t)round_up((p->m + P.G - 1) / P.G, 4);
+        if (P.fin_cols > s.wg)
+            return fail(UOT_ERR_UNSUPPORTED, "persistent loop needs m <= workgroup size * grid (m=%lld, grid=%d)",
+                        (long long)p->m, P.G);
+        P.lds_bytes = (size_t)P.scratch_bytes + 2 * sizeof(double) * (size_t)P.rows_per_wg;
+        if (persist_max_grid(P.k_dtype, P.acc64, P.shape, P.lds_bytes) < P.G)
+            return fail(UOT_ERR_UNSUPPORTED, "grid of %d workgroups cannot be co-resident", P.G);
+    } else {
+        P.lds_bytes = 2 * sizeof(double) * (size_t)P.rows_per_wg + (s.vlds ? (size_t)P.ldv_bytes : 0) + 1024;
+    }
     if ((int64_t)P.lds_bytes > max_lds_bytes())
         return fail(UOT_ERR_UNSUPPORTED, "launch shape %d needs %zu bytes of LDS", P.shape, P.lds_bytes);
     P.build_k = (p->K == nullptr);
@@ -183,7 +210,8 @@ uot_status make_plan(const uot_problem* p, const uot_options* o, Plan& P) {
     P.off_cprev = off; off = align_up(off + sizeof(double) * p->m, kAlign);
     P.off_w = off; off = align_up(off + sizeof(double) * p->m, kAlign);
     P.off_s = off; off = align_up(off + sizeof(double) * p->n, kAlign);
-    P.off_bp = off; off = align_up(off + sizeof(double) * 2 * finalize_blocks(p->m), kAlign);
+    P.fin_blocks = P.persistent ? P.G : finalize_blocks(p->m);
+    P.off_bp = off; off = align_up(off + sizeof(double) * 2 * (size_t)P.fin_blocks, kAlign);
     P.off_part = off; off = align_up(off + acc_size * (size_t)P.G * P.ldp, kAlign);
     P.off_k = off;
     if (P.build_k) off = align_up(off + (size_t)elem_size(p->k_dtype) * p->n * P.ldk_ws, kAlign);
@@ -265,42 +293,78 @@ uot_status run_sinkhorn(const uot_problem* p, const uot_options* o, const uot_ou
     F.fi_is_one = (fi == 1.0);
     F.inv_eps = 1.0 / p->eps;
     F.ctrl = ctrl;
-    F.tol = o->tol;
     F.blockpart = bp;
     F.acc64 = P.acc64;
 
     const int check_every = o->check_every > 0 ? o->check_every : 1;
     const bool fused = o->fused != 0;
+    L.test_stop = 0;
+    L.fin_blocks = finalize_blocks(p->m);
+    L.blockpart = bp;
+    L.tol = o->tol;
 
+    // Profiling: events around every launch of sampled iterations
+    // (t % kProfileStride == 0) plus the whole loop; unsampled iterations run
+    // exactly as without profiling.
+    constexpr int kProfileStride = 8;
+    enum { K_FUSED = 0, K_ROW = 1, K_COL = 2, K_FIN = 3 };
     std::vector<hipEvent_t> ev;
-    const int per_iter = fused ? 2 : 3;       // timed launches per iteration
+    std::vector<int> ev_kind;
+    const int per_iter = fused ? 2 : 3;
+    size_t evi = 0;
     if (prof) {
         memset(prof, 0, sizeof(*prof));
-        UOT_HIP(events((size_t)2 * per_iter * (size_t)o->max_iter + 2, ev), "hipEventCreate");
+        size_t sampled = (size_t)(o->max_iter + kProfileStride - 1) / kProfileStride + 1;
+        UOT_HIP(events(2 * per_iter * sampled + 2, ev), "hipEventCreate");
+        UOT_HIP(hipEventRecord(ev[evi++], stream), "hipEventRecord");
     }
-    size_t evi = 0;
-    auto timed = [&](auto&& launch) -> hipError_t {
-        if (prof) {
+    bool sample = false;
+    auto timed = [&](int kind, auto&& launch) -> hipError_t {
+        if (sample) {
+            ev_kind.push_back(kind);
             hipError_t e = hipEventRecord(ev[evi++], stream);
             if (e != hipSuccess) return e;
         }
         hipError_t e = launch();
         if (e != hipSuccess) return e;
-        if (prof) return hipEventRecord(ev[evi++], stream);
+        if (sample) return hipEventRecord(ev[evi++], stream);
         return hipSuccess;
     };
 
-    for (int t = 0; t < o->max_iter; ++t) {
+    L.fin_blocks = P.fin_blocks;
+    int64_t iters_run = 0;
+    if (P.persistent && o->max_iter > 0) {
+        PersistLaunch PL;
+        memset(&PL, 0, sizeof(PL));
+        PL.L = L;
+        PL.L.check_done = 0;
+        PL.F = F;
+        PL.max_iter = o->max_iter;
+        PL.fin_cols = P.fin_cols;
+        PL.scratch_bytes = P.scratch_bytes;
+        sample = prof != nullptr;
+        UOT_HIP(timed(K_FUSED, [&] { return launch_persist(P.k_dtype, P.acc64, P.shape, PL, P.lds_bytes, stream); }),
+                "persistent loop");
+        iters_run = o->max_iter;
+    }
+    for (int t = 0; t < (P.persistent ? 0 : o->max_iter); ++t) {
+        sample = prof && (t % kProfileStride == 0);
+        L.iter = t + 1;
+        PassLaunch L1 = L;
+        L1.test_stop = 1;       // the first pass of an iteration applies the stopping test
         if (fused) {
-            UOT_HIP(timed([&] { return launch_pass(P.k_dtype, P.acc64, MODE_FUSED, P.shape, L, stream); }),
+            UOT_HIP(timed(K_FUSED, [&] { return launch_pass(P.k_dtype, P.acc64, MODE_FUSED, P.shape, L1, stream); }),
                     "fused pass");
         } else {
-            UOT_HIP(timed([&] { return launch_pass(P.k_dtype, P.acc64, MODE_ROW, P.shape, L, stream); }),
+            UOT_HIP(timed(K_ROW, [&] { return launch_pass(P.k_dtype, P.acc64, MODE_ROW, P.shape, L1, stream); }),
                     "row pass");
-            UOT_HIP(timed([&] { return launch_pass(P.k_dtype, P.acc64, MODE_COL, P.shape, L, stream); }),
+            UOT_HIP(timed(K_COL, [&] { return launch_pass(P.k_dtype, P.acc64, MODE_COL, P.shape, L, stream); }),
                     "column pass");
         }
-        UOT_HIP(timed([&] { return launch_finalize(F, stream); }), "column finalize");
+        UOT_HIP(timed(K_FIN, [&] { return launch_finalize(F, stream); }), "column finalize");
+        iters_run = t + 1;
+        // Iteration t+1's first pass decides whether iteration t met tol, so a
+        // stop is seen here one check later; the extra launches return at once.
         if (flag_host && (t + 1) % check_every == 0 && t + 1 < o->max_iter) {
             UOT_HIP(hipMemcpyAsync(flag_host, &ctrl->done, sizeof(uint32_t), hipMemcpyDeviceToHost, stream),
                     "flag copy");
@@ -308,6 +372,8 @@ uot_status run_sinkhorn(const uot_problem* p, const uot_options* o, const uot_ou
             if (*(volatile uint32_t*)flag_host) break;
         }
     }
+    sample = false;
+    if (prof) UOT_HIP(hipEventRecord(ev[evi++], stream), "hipEventRecord");
 
     // Marginals of the final scalings: s = K v_T and w = K^T u_T in one pass.
     PassLaunch LM = L;
@@ -337,28 +403,24 @@ uot_status run_sinkhorn(const uot_problem* p, const uot_options* o, const uot_ou
     O.info = out->info;
     O.ctrl = ctrl;
     O.tol = o->tol;
+    O.iters_run = iters_run;
+    O.blockpart = bp;
+    O.fin_blocks = P.fin_blocks;
     UOT_HIP(launch_objective(O, stream), "objective");
 
     if (prof) {
         UOT_HIP(hipStreamSynchronize(stream), "profile sync");
-        size_t k = 0;
-        int slot = 0;
-        while (k + 1 < evi) {
+        for (size_t q = 0; q < ev_kind.size(); ++q) {
             float ms = 0.f;
-            UOT_HIP(hipEventElapsedTime(&ms, ev[k], ev[k + 1]), "hipEventElapsedTime");
-            int kind = slot % per_iter;
-            if (fused) {
-                if (kind == 0) { prof->fused_launches++; prof->fused_ms += ms; }
-                else { prof->finalize_launches++; prof->finalize_ms += ms; }
-            } else {
-                if (kind == 0) { prof->row_launches++; prof->row_ms += ms; }
-                else if (kind == 1) { prof->col_launches++; prof->col_ms += ms; }
-                else { prof->finalize_launches++; prof->finalize_ms += ms; }
+            UOT_HIP(hipEventElapsedTime(&ms, ev[1 + 2 * q], ev[2 + 2 * q]), "hipEventElapsedTime");
+            switch (ev_kind[q]) {
+                case K_FUSED: prof->fused_launches++; prof->fused_ms += ms; break;
+                case K_ROW: prof->row_launches++; prof->row_ms += ms; break;
+                case K_COL: prof->col_launches++; prof->col_ms += ms; break;
+                default: prof->finalize_launches++; prof->finalize_ms += ms; break;
             }
-            k += 2;
-            ++slot;
         }
-        if (evi >= 2) UOT_HIP(hipEventElapsedTime(&prof->loop_ms, ev[0], ev[evi - 1]), "hipEventElapsedTime");
+        UOT_HIP(hipEventElapsedTime(&prof->loop_ms, ev[0], ev[evi - 1]), "hipEventElapsedTime");
     }
     return UOT_OK;
 }

@@ -21,7 +21,7 @@ __global__ void init_kernel(double* u, int64_t n, const double* u0, double* v, i
     }
     if (t == 0) {
         ctrl->done = 0;
-        ctrl->counter = 0;
+        ctrl->bar = 0;
         ctrl->flags = 0;
         ctrl->pad0 = 0;
         ctrl->iters = 0;
@@ -41,49 +41,65 @@ hipError_t launch_init(double* u, int64_t n, const double* u0, double* v, int64_
 
 // ---------------------------------------------------------------------------
 // Column finalize: w = sum over strips of the partials (fixed order, FP64),
-// v = (b / w)^fi, c = v * w, error = sum|c - c_prev| / sum|c|.
-// Block: 1024 threads = 16 waves over 64 columns; wave k sums strips
-// k, k+16, k+32, ...; wave 0 combines the 16 sums in order.
+// v = (b / w)^fi, c = v * w, and per-block sums of |c - c_prev| and |c| for
+// the stopping test (evaluated by the next iteration's first pass).
+// Block: 256 threads over 16 columns.  Thread t reads 4 adjacent columns
+// (one 16-byte chunk) of strips t/4, t/4 + 64, ... with all loads of a
+// group of 8 strips issued before any add; the 64 strip phases are then
+// combined in LDS in a fixed order (one lane per column).
 // ---------------------------------------------------------------------------
-constexpr int FIN_COLS = 64;
-constexpr int FIN_WAVES = 16;
+constexpr int FIN_COLS = 16;
+constexpr int FIN_THREADS = 256;
+constexpr int FIN_PHASES = FIN_THREADS / (FIN_COLS / 4);   // 64
 
 int finalize_blocks(int64_t m) { return (int)((m + FIN_COLS - 1) / FIN_COLS); }
 
 template <typename AT>
-__global__ __launch_bounds__(1024) void finalize_kernel(FinLaunch F) {
-    __shared__ double part[FIN_WAVES][FIN_COLS];
+__global__ __launch_bounds__(FIN_THREADS) void finalize_kernel(FinLaunch F) {
+    __shared__ double part[FIN_PHASES][FIN_COLS + 1];
     Ctrl* ctrl = F.ctrl;
     if (!F.marginal_only && ld_volatile_u32(&ctrl->done)) return;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int64_t j = (int64_t)blockIdx.x * FIN_COLS + lane;
-    const AT* P = (const AT*)F.partials;
-    double acc = 0.0;
-    if (j < F.m) {
-        int g = wave;
-        // unrolled by 4 for memory-level parallelism; order of the sum is fixed
-        for (; g + 3 * FIN_WAVES < F.G; g += 4 * FIN_WAVES) {
-            double p0 = (double)P[(int64_t)g * F.ldp + j];
-            double p1 = (double)P[(int64_t)(g + FIN_WAVES) * F.ldp + j];
-            double p2 = (double)P[(int64_t)(g + 2 * FIN_WAVES) * F.ldp + j];
-            double p3 = (double)P[(int64_t)(g + 3 * FIN_WAVES) * F.ldp + j];
-            acc += p0;
-            acc += p1;
-            acc += p2;
-            acc += p3;
+    const int cg = tid & (FIN_COLS / 4 - 1);   // 4-column group within the block
+    const int ph = tid / (FIN_COLS / 4);       // strip phase
+    const int64_t c0 = (int64_t)blockIdx.x * FIN_COLS + 4 * cg;
+    const AT* P = (const AT*)F.partials + c0;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (c0 < F.m) {
+        // ldp is a multiple of 64, so the 4 columns never leave the partial row.
+        constexpr int U = 8;
+        int g = ph;
+        for (; g + (U - 1) * FIN_PHASES < F.G; g += U * FIN_PHASES) {
+            double x[U][4];
+#pragma unroll
+            for (int q = 0; q < U; ++q) Chunk4<AT>::load(P + (int64_t)(g + q * FIN_PHASES) * F.ldp, x[q]);
+#pragma unroll
+            for (int q = 0; q < U; ++q)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[e] += x[q][e];
         }
-        for (; g < F.G; g += FIN_WAVES) acc += (double)P[(int64_t)g * F.ldp + j];
+        for (; g < F.G; g += FIN_PHASES) {
+            double x[4];
+            Chunk4<AT>::load(P + (int64_t)g * F.ldp, x);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[e] += x[e];
+        }
     }
-    part[wave][lane] = acc;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) part[ph][4 * cg + e] = acc[e];
     __syncthreads();
     if (wave != 0) return;
 
+    // lanes >= FIN_COLS carry no column; they take part in the wave sums with zeros
+    const int64_t j = (lane < FIN_COLS) ? (int64_t)blockIdx.x * FIN_COLS + lane : F.m;
     double w = 0.0;
-#pragma unroll
-    for (int k = 0; k < FIN_WAVES; ++k) w += part[k][lane];
+    if (lane < FIN_COLS) {
+#pragma unroll 16
+        for (int k = 0; k < FIN_PHASES; ++k) w += part[k][lane];
+    }
 
     double dsum = 0.0, csum = 0.0;
     if (j < F.m) {
@@ -107,36 +123,14 @@ __global__ __launch_bounds__(1024) void finalize_kernel(FinLaunch F) {
     if (F.marginal_only) return;
     dsum = wave_sum_f64(dsum);
     csum = wave_sum_f64(csum);
-    int is_last = 0;
     if (lane == 0) {
         F.blockpart[2 * blockIdx.x] = dsum;
         F.blockpart[2 * blockIdx.x + 1] = csum;
-        __threadfence();
-        unsigned prev = atomicAdd(&ctrl->counter, 1u);
-        is_last = (prev == gridDim.x - 1);
-    }
-    // all 64 lanes of wave 0 are active here, so the first active lane is lane 0
-    if (!__builtin_amdgcn_readfirstlane(is_last)) return;
-    __threadfence();
-    const volatile double* bp = F.blockpart;
-    double dn = 0.0, dc = 0.0;
-    for (int k = lane; k < (int)gridDim.x; k += 64) {
-        dn += bp[2 * k];
-        dc += bp[2 * k + 1];
-    }
-    dn = wave_sum_f64(dn);
-    dc = wave_sum_f64(dc);
-    if (lane == 0) {
-        double err = dn / dc;
-        ctrl->err = err;
-        ctrl->iters += 1;
-        if (F.tol > 0.0 && err <= F.tol) ctrl->done = 1;
-        ctrl->counter = 0;
     }
 }
 
 hipError_t launch_finalize(const FinLaunch& F, hipStream_t stream) {
-    dim3 grid(finalize_blocks(F.m)), block(1024);
+    dim3 grid(finalize_blocks(F.m)), block(FIN_THREADS);
     if (F.acc64)
         hipLaunchKernelGGL(finalize_kernel<double>, grid, block, 0, stream, F);
     else
@@ -175,6 +169,9 @@ __global__ __launch_bounds__(1024) void objective_kernel(ObjLaunch O) {
         if (c > 0.0) sc += c * log(O.v[j]);
         kc += kl_term(c, O.b[j]);
     }
+    double stop_err = 0.0;
+    const bool stopped = O.ctrl->done != 0;
+    if (wave == 0 && !stopped && O.iters_run > 0) stop_err = stop_error(O.blockpart, O.fin_blocks, lane);
     double vals[4] = {sr + sc - mass, kr, kc, 0.0};
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
@@ -193,11 +190,13 @@ __global__ __launch_bounds__(1024) void objective_kernel(ObjLaunch O) {
         if (!O.tau_inf) L += O.tau * (a + b);
         if (O.loss) *O.loss = L;
         if (O.info) {
-            O.info->iters = O.ctrl->iters;
-            O.info->err = O.ctrl->err;
+            // Stopped: the pass that found err <= tol recorded it.  Otherwise
+            // all enqueued iterations ran; the last one may still meet tol.
+            O.info->iters = stopped ? O.ctrl->iters : O.iters_run;
+            O.info->err = stopped ? O.ctrl->err : stop_err;
             O.info->absorptions = 0;
             uint32_t fl = O.ctrl->flags;
-            if (O.tol > 0.0 && !O.ctrl->done) fl |= UOT_FLAG_NOT_CONVERGED;
+            if (O.tol > 0.0 && !stopped && !(O.iters_run > 0 && stop_err <= O.tol)) fl |= UOT_FLAG_NOT_CONVERGED;
             if (!isfinite(L)) fl |= UOT_FLAG_NONFINITE;
             O.info->flags = fl;
         }

@@ -28,105 +28,107 @@ namespace uot {
 
 // Word 3 of a raw buffer resource on gfx9-class parts (untyped 32-bit data).
 constexpr int kBufferWord3 = 0x00020000;
-// Cache policy of the K loads (0: default).
+// Cache-policy bits of the K loads.
+// 2 = non-temporal: K is streamed once per pass and should not displace v,
+// the partials or other workgroups' lines in L2 / the memory-side cache.
 #ifndef UOT_K_LOAD_AUX
-#define UOT_K_LOAD_AUX 0
+#define UOT_K_LOAD_AUX 2
 #endif
 constexpr int kLoadAux = UOT_K_LOAD_AUX;
 
+// ---------------------------------------------------------------------------
+// One workgroup's streaming pass over its strip of rows.  Shared by the
+// per-iteration pass kernel and the persistent kernel.
+// ---------------------------------------------------------------------------
 template <typename KT, typename AT, int WG, int NC, int D, bool VLDS, int MODE>
-__global__ __launch_bounds__(WG) void pass_kernel(PassLaunch L) {
+struct Strip {
     using KV = KVec<KT>;
     using Raw = typename KV::raw;
-    constexpr int V = KV::N;
-    constexpr int E = NC * V;
-    constexpr int NW = WG / 64;
-    constexpr bool kDot = (MODE != MODE_COL);
-    constexpr bool kAcc = (MODE != MODE_ROW);
-    constexpr bool kVreg = kDot && !VLDS;
+    static constexpr int V = KV::N;
+    static constexpr int E = NC * V;
+    static constexpr int NW = WG / 64;
+    static constexpr bool kDot = (MODE != MODE_COL);
+    static constexpr bool kAcc = (MODE != MODE_ROW);
+    static constexpr bool kVreg = kDot && !VLDS;
 
-    __shared__ double red[2][NW];
-    extern __shared__ __align__(16) unsigned char dyn_lds[];
-
-    if (L.check_done && ld_volatile_u32(&L.ctrl->done)) return;
-
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const int64_t m = L.m;
-    const int64_t r0 = (int64_t)blockIdx.x * L.rows_per_wg;
-    int64_t r1 = r0 + L.rows_per_wg;
-    if (r1 > L.n) r1 = L.n;
-    const int nrows = (int)(r1 - r0);
-
-    // LDS: [v as AT, padded to ldv] [row input: a or u] [row shift]
-    AT* vl = (AT*)dyn_lds;
-    double* row_in = (double*)(dyn_lds + (VLDS && kDot ? L.ldv_bytes : 0));
-    double* row_sh = row_in + L.rows_per_wg;
-    for (int k = tid; k < nrows; k += WG) {
-        if constexpr (MODE == MODE_FUSED || MODE == MODE_ROW) {
-            row_in[k] = L.a[r0 + k];
-            row_sh[k] = L.fpot ? -(1.0 - L.fi) * L.fpot[r0 + k] * L.inv_eps : 0.0;
-        } else {
-            row_in[k] = L.u[r0 + k];
-        }
-    }
-    if constexpr (VLDS && kDot) {
-        const int64_t mv = (m + V - 1) / V * V;
-        for (int64_t j = tid; j < mv; j += WG) vl[j] = (j < m) ? (AT)L.v[j] : (AT)0;
-    }
-    __syncthreads();
-
-    // Buffer resource over this workgroup's strip of rows.
-    const uint32_t row_bytes = (uint32_t)(L.ldk * (int64_t)sizeof(KT));
-    const uint32_t strip_bytes = (uint32_t)((int64_t)nrows * L.ldk * (int64_t)sizeof(KT));
-    const KT* strip = (const KT*)L.K + r0 * L.ldk;
-    __amdgpu_buffer_rsrc_t rsrc =
-        __builtin_amdgcn_make_buffer_rsrc((void*)strip, (short)0, (int)strip_bytes, kBufferWord3);
-
+    __amdgpu_buffer_rsrc_t rsrc;
+    uint32_t row_bytes;
+    int64_t m;
+    int64_t r0;
+    int nrows;
+    bool ragged;
     int64_t col[NC];
     uint32_t voff[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        col[c] = ((int64_t)c * WG + tid) * V;
-        voff[c] = col[c] < m ? (uint32_t)(col[c] * (int64_t)sizeof(KT)) : strip_bytes;
-    }
-    const bool ragged = (m % V) != 0;
-
-    AT vv[kVreg ? E : 1];
-    if constexpr (kVreg) {
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-#pragma unroll
-            for (int e = 0; e < V; ++e) {
-                int64_t j = col[c] + e;
-                vv[c * V + e] = (j < m) ? (AT)L.v[j] : (AT)0;
-            }
-    }
-    AT acc[kAcc ? E : 1];
-#pragma unroll
-    for (int e = 0; e < (kAcc ? E : 1); ++e) acc[e] = (AT)0;
-
     Raw buf[D][NC];
+    AT vv[kVreg ? E : 1];
+    AT acc[kAcc ? E : 1];
 
-    auto load_row = [&](Raw (&b)[NC], int k) {
-        // k = row index within the strip; rows >= nrows land past strip_bytes (zeros)
+    __device__ __forceinline__ void setup(const PassLaunch& L, int64_t r0_, int nrows_) {
+        m = L.m;
+        r0 = r0_;
+        nrows = nrows_;
+        row_bytes = (uint32_t)(L.ldk * (int64_t)sizeof(KT));
+        // Buffer resource over the strip: loads past its last row and the
+        // chunks of lanes beyond column m (offset set to the strip size) read 0.
+        const uint32_t strip_bytes = (uint32_t)((int64_t)nrows * L.ldk * (int64_t)sizeof(KT));
+        const KT* strip = (const KT*)L.K + r0 * L.ldk;
+        rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)strip, (short)0, (int)strip_bytes, kBufferWord3);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            col[c] = ((int64_t)c * WG + threadIdx.x) * V;
+            voff[c] = col[c] < m ? (uint32_t)(col[c] * (int64_t)sizeof(KT)) : strip_bytes;
+        }
+        ragged = (m % V) != 0;
+    }
+
+    template <int Q>
+    __device__ __forceinline__ void load_row(int k) {
         const uint32_t soff = (uint32_t)k * row_bytes;
 #pragma unroll
         for (int c = 0; c < NC; ++c)
-            b[c] = __builtin_bit_cast(Raw, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)voff[c], (int)soff,
-                                                                                 kLoadAux));
-    };
+            buf[Q][c] = __builtin_bit_cast(
+                Raw, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)voff[c], (int)soff, kLoadAux));
+    }
 
-    int slot = 0;
-    auto process = [&](Raw (&b)[NC], int k) {
+    // Rows 0 .. D-2 in flight (issued before anything the pass waits on).
+    __device__ __forceinline__ void prime() {
+        if constexpr (D >= 2) load_row<0>(0);
+        if constexpr (D >= 3) load_row<1>(1);
+        if constexpr (D >= 4) load_row<2>(2);
+    }
+
+    __device__ __forceinline__ void load_v_regs(const double* v) {
+        if constexpr (kVreg) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    int64_t j = col[c] + e;
+                    vv[c * V + e] = (j < m) ? (AT)v[j] : (AT)0;
+                }
+        }
+    }
+
+    __device__ __forceinline__ void clear_acc() {
+#pragma unroll
+        for (int e = 0; e < (kAcc ? E : 1); ++e) acc[e] = (AT)0;
+    }
+
+    // One row: dot with v (FUSED/ROW/MARG), cross-wave reduction, scaling,
+    // accumulation of the column partials (FUSED/COL/MARG).
+    template <int Q>
+    __device__ __forceinline__ void process(const PassLaunch& L, int k, const AT* vl, const double* row_in,
+                                            const double* row_sh, double (*red)[NW], int& slot) {
+        const int tid = threadIdx.x;
+        const int lane = tid & 63;
+        const int wave = tid >> 6;
         AT ur;
         if constexpr (kDot) {
             AT s = (AT)0;
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 AT x[V];
-                unpack<AT>(b[c], x);
+                unpack<AT>(buf[Q][c], x);
                 if (ragged) {
 #pragma unroll
                     for (int e = 0; e < V; ++e)
@@ -171,37 +173,263 @@ __global__ __launch_bounds__(WG) void pass_kernel(PassLaunch L) {
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 AT x[V];
-                unpack<AT>(b[c], x);
+                unpack<AT>(buf[Q][c], x);
 #pragma unroll
                 for (int e = 0; e < V; ++e) acc[c * V + e] = fma(x[e], ur, acc[c * V + e]);
             }
         }
-    };
+    }
 
-    // Prologue: rows 0 .. D-2 in flight.
-#pragma unroll
-    for (int q = 0; q < D - 1; ++q) load_row(buf[q], q);
-    for (int k0 = 0; k0 < nrows; k0 += D) {
-#pragma unroll
-        for (int q = 0; q < D; ++q) {
-            const int k = k0 + q;
-            if (k >= nrows) break;
-            load_row(buf[(q + D - 1) % D], k + D - 1);
-            process(buf[q], k);
+    template <int Q>
+    __device__ __forceinline__ bool step(const PassLaunch& L, int k0, const AT* vl, const double* row_in,
+                                         const double* row_sh, double (*red)[NW], int& slot) {
+        const int k = k0 + Q;
+        if (k >= nrows) return false;
+        load_row<(Q + D - 1) % D>(k + D - 1);
+        process<Q>(L, k, vl, row_in, row_sh, red, slot);
+        return true;
+    }
+
+    // All rows of the strip; expects prime() to have been called.
+    __device__ __forceinline__ void stream(const PassLaunch& L, const AT* vl, const double* row_in,
+                                           const double* row_sh, double (*red)[NW]) {
+        int slot = 0;
+        for (int k0 = 0; k0 < nrows; k0 += D) {
+            if (!step<0>(L, k0, vl, row_in, row_sh, red, slot)) break;
+            if constexpr (D >= 2) if (!step<1 % D>(L, k0, vl, row_in, row_sh, red, slot)) break;
+            if constexpr (D >= 3) if (!step<2 % D>(L, k0, vl, row_in, row_sh, red, slot)) break;
+            if constexpr (D >= 4) if (!step<3 % D>(L, k0, vl, row_in, row_sh, red, slot)) break;
         }
     }
 
-    if constexpr (kAcc) {
-        AT* P = (AT*)L.partials + (int64_t)blockIdx.x * L.ldp;
+    __device__ __forceinline__ void store_partials(AT* P) {
+        if constexpr (kAcc) {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            if (col[c] >= m) continue;
+            for (int c = 0; c < NC; ++c) {
+                if (col[c] >= m) continue;
 #pragma unroll
-            for (int e = 0; e < V; ++e) {
-                // ldp is a multiple of 64 >= m, so the whole chunk lies inside the partial row.
-                P[col[c] + e] = acc[c * V + e];
+                for (int e = 0; e < V; ++e) {
+                    // ldp is a multiple of 64 >= m, so the chunk lies inside the partial
+                    // row; streaming stores: the partials are read once, elsewhere.
+                    __builtin_nontemporal_store(acc[c * V + e], &P[col[c] + e]);
+                }
             }
         }
+    }
+};
+
+// Stage the strip's per-row inputs (a and the stabilised shift, or u) and,
+// for shapes that keep v in LDS, v itself.
+template <typename S, int MODE, bool VLDS, typename AT>
+__device__ __forceinline__ void stage_rows(const PassLaunch& L, int64_t r0, int nrows, double* row_in,
+                                           double* row_sh) {
+    for (int k = threadIdx.x; k < nrows; k += blockDim.x) {
+        if constexpr (MODE == MODE_FUSED || MODE == MODE_ROW) {
+            row_in[k] = L.a[r0 + k];
+            row_sh[k] = L.fpot ? -(1.0 - L.fi) * L.fpot[r0 + k] * L.inv_eps : 0.0;
+        } else {
+            row_in[k] = L.u[r0 + k];
+        }
+    }
+}
+
+template <int V, typename AT>
+__device__ __forceinline__ void stage_v(const double* v, int64_t m, AT* vl) {
+    const int64_t mv = (m + V - 1) / V * V;
+    for (int64_t j = threadIdx.x; j < mv; j += blockDim.x) vl[j] = (j < m) ? (AT)v[j] : (AT)0;
+}
+
+// Stopping test of the previous iteration (see PassLaunch): identical in
+// every workgroup.  Returns true when the loop is to stop.
+__device__ __forceinline__ bool stop_test(const PassLaunch& L, int64_t iter, double* err_sh) {
+    if (!(L.tol > 0.0) || iter <= 1) return false;
+    if ((threadIdx.x >> 6) == 0) {
+        double err = stop_error(L.blockpart, L.fin_blocks, threadIdx.x & 63);
+        if ((threadIdx.x & 63) == 0) *err_sh = err;
+    }
+    __syncthreads();
+    const double err = *err_sh;
+    __syncthreads();
+    if (err <= L.tol) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            L.ctrl->iters = iter - 1;
+            L.ctrl->err = err;
+            L.ctrl->done = 1;
+        }
+        return true;
+    }
+    return false;
+}
+
+// ---------------------------------------------------------------------------
+// Per-iteration pass kernel.
+// ---------------------------------------------------------------------------
+template <typename KT, typename AT, int WG, int NC, int D, bool VLDS, int MODE>
+__global__ __launch_bounds__(WG) void pass_kernel(PassLaunch L) {
+    using S = Strip<KT, AT, WG, NC, D, VLDS, MODE>;
+    __shared__ double red[2][S::NW];
+    __shared__ double err_sh;
+    extern __shared__ __align__(16) unsigned char dyn_lds[];
+
+    if (L.check_done && ld_volatile_u32(&L.ctrl->done)) return;
+    if (L.test_stop && stop_test(L, L.iter, &err_sh)) return;
+
+    const int64_t r0 = (int64_t)blockIdx.x * L.rows_per_wg;
+    int64_t r1 = r0 + L.rows_per_wg;
+    if (r1 > L.n) r1 = L.n;
+    const int nrows = (int)(r1 - r0);
+
+    S st;
+    st.setup(L, r0, nrows);
+    st.prime();
+
+    // LDS: [v as AT, padded to ldv] [row input: a or u] [row shift]
+    AT* vl = (AT*)dyn_lds;
+    double* row_in = (double*)(dyn_lds + (VLDS && S::kDot ? L.ldv_bytes : 0));
+    double* row_sh = row_in + L.rows_per_wg;
+    stage_rows<S, MODE, VLDS, AT>(L, r0, nrows, row_in, row_sh);
+    if constexpr (VLDS && S::kDot) stage_v<S::V, AT>(L.v, L.m, vl);
+    __syncthreads();
+    st.load_v_regs(L.v);
+    st.clear_acc();
+    st.stream(L, vl, row_in, row_sh, red);
+    st.store_partials((AT*)L.partials + (int64_t)blockIdx.x * L.ldp);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent kernel: the whole iteration loop in one cooperative launch.
+// Per iteration: fused pass over the strip, grid barrier, column finalize of
+// this workgroup's column block (the same fixed-order FP64 sums as the
+// finalize kernel), grid barrier.  The launch must be co-resident (checked
+// by the cooperative launch); every barrier wait is bounded.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void grid_barrier(uint32_t* count, uint32_t target, uint32_t* flags) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        atomicAdd(count, 1u);
+        uint32_t spins = 0;
+        while (__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > kBarrierSpinLimit) {
+                atomicOr(flags, UOT_FLAG_BARRIER_TIMEOUT);
+                break;
+            }
+        }
+        __threadfence();
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+template <typename KT, typename AT, int WG, int NC, int D, bool VLDS>
+__global__ __launch_bounds__(WG) void persist_kernel(PersistLaunch P) {
+    using S = Strip<KT, AT, WG, NC, D, VLDS, MODE_FUSED>;
+    __shared__ double red[2][S::NW];
+    __shared__ double err_sh;
+    __shared__ double fin_red[2][S::NW];
+    extern __shared__ __align__(16) unsigned char dyn_lds[];
+    const PassLaunch& L = P.L;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const uint32_t G = gridDim.x;
+
+    const int64_t r0 = (int64_t)blockIdx.x * L.rows_per_wg;
+    int64_t r1 = r0 + L.rows_per_wg;
+    if (r1 > L.n) r1 = L.n;
+    const int nrows = (int)(r1 - r0);
+
+    // LDS: [v / finalize scratch (max of both)] [a strip] [shift strip]
+    AT* vl = (AT*)dyn_lds;
+    double* fin = (double*)dyn_lds;
+    double* row_in = (double*)(dyn_lds + P.scratch_bytes);
+    double* row_sh = row_in + L.rows_per_wg;
+    stage_rows<S, MODE_FUSED, VLDS, AT>(L, r0, nrows, row_in, row_sh);
+
+    // Column block finalized by this workgroup: [cb0, cb0 + P.fin_cols).
+    const int64_t cb0 = (int64_t)blockIdx.x * P.fin_cols;
+    const int groups = P.fin_cols / 4;            // 4-column chunks
+    const int phases = WG / groups;               // strip phases per chunk
+    const int cg = tid % groups;
+    const int ph = tid / groups;
+
+    S st;
+    st.setup(L, r0, nrows);
+    uint32_t bar = 0;
+    int64_t t = 1;
+    for (; t <= P.max_iter; ++t) {
+        if (stop_test(L, t, &err_sh)) break;
+        st.prime();
+        if constexpr (VLDS) stage_v<S::V, AT>(L.v, L.m, vl);
+        __syncthreads();
+        st.load_v_regs(L.v);
+        st.clear_acc();
+        st.stream(L, vl, row_in, row_sh, red);
+        st.store_partials((AT*)L.partials + (int64_t)blockIdx.x * L.ldp);
+        bar += G;
+        grid_barrier(&L.ctrl->bar, bar, &L.ctrl->flags);
+
+        // ---- column finalize of this workgroup's block
+        double accf[4] = {0.0, 0.0, 0.0, 0.0};
+        const int64_t c0 = cb0 + 4 * cg;
+        if (ph < phases && c0 < L.m) {
+            const AT* Pp = (const AT*)L.partials + c0;
+            for (int g = ph; g < (int)G; g += phases) {
+                double x[4];
+                Chunk4<AT>::load(Pp + (int64_t)g * L.ldp, x);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) accf[e] += x[e];
+            }
+        }
+        __syncthreads();   // v in LDS is dead from here; reuse it as scratch
+        if (ph < phases) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) fin[ph * P.fin_cols + 4 * cg + e] = accf[e];
+        }
+        __syncthreads();
+        double dsum = 0.0, csum = 0.0;
+        if (tid < P.fin_cols) {
+            const int64_t j = cb0 + tid;
+            double w = 0.0;
+            for (int q = 0; q < phases; ++q) w += fin[q * P.fin_cols + tid];
+            if (j < L.m) {
+                const FinLaunch& F = P.F;
+                const double bj = F.b[j];
+                double shift = F.gpot ? -(1.0 - F.fi) * F.gpot[j] * F.inv_eps : 0.0;
+                double vj = scale_factor(bj, w, F.fi, F.fi_is_one, shift);
+                F.v[j] = vj;
+                F.w_out[j] = w;
+                double cj = vj * w;
+                double cp = F.cprev[j];
+                F.cprev[j] = cj;
+                dsum = fabs(cj - cp);
+                csum = fabs(cj);
+                if (bj > 0.0 && !(w > 0.0)) atomicOr(&L.ctrl->flags, UOT_FLAG_ZERO_SUM);
+                if (!isfinite(vj)) atomicOr(&L.ctrl->flags, UOT_FLAG_NONFINITE);
+            }
+        }
+        // block sums for the stopping test, in a fixed order
+        if (tid < ((P.fin_cols + 63) & ~63)) {
+            dsum = wave_sum_f64(dsum);
+            csum = wave_sum_f64(csum);
+            if (lane == 0) {
+                fin_red[0][wave] = dsum;
+                fin_red[1][wave] = csum;
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double a0 = 0.0, a1 = 0.0;
+            for (int w = 0; w < (P.fin_cols + 63) / 64; ++w) {
+                a0 += fin_red[0][w];
+                a1 += fin_red[1][w];
+            }
+            P.F.blockpart[2 * blockIdx.x] = a0;
+            P.F.blockpart[2 * blockIdx.x + 1] = a1;
+        }
+        bar += G;
+        grid_barrier(&L.ctrl->bar, bar, &L.ctrl->flags);
     }
 }
 
@@ -279,6 +507,67 @@ hipError_t launch_pass(int k_dtype, int acc64, int mode, int shape_idx, const Pa
         return launch_typed<float, float>(mode, shape_idx, L, lds, stream);
     }
     return hipErrorInvalidValue;
+}
+
+
+// ---------------------------------------------------------------------------
+// Persistent launch
+// ---------------------------------------------------------------------------
+template <typename KT, typename AT, int WG, int NC, int D, bool VLDS>
+static const void* persist_fn() {
+    return (const void*)persist_kernel<KT, AT, WG, NC, D, VLDS>;
+}
+
+template <typename KT, typename AT>
+static const void* persist_typed(int shape_idx, int* wg) {
+    switch (shape_idx) {
+        case 0: *wg = 256; return persist_fn<KT, AT, 256, 1, 4, false>();
+        case 1: *wg = 512; return persist_fn<KT, AT, 512, 1, 4, false>();
+        case 2: *wg = 1024; return persist_fn<KT, AT, 1024, 1, 4, false>();
+        case 3: *wg = 1024; return persist_fn<KT, AT, 1024, 2, 3, false>();
+        case 4: *wg = 512; return persist_fn<KT, AT, 512, 4, 3, false>();
+        case 5: *wg = 512; return persist_fn<KT, AT, 512, 8, 2, true>();
+        case 6: *wg = 1024; return persist_fn<KT, AT, 1024, 4, 2, true>();
+        case 7: *wg = 512; return persist_fn<KT, AT, 512, 8, 3, true>();
+        default: return nullptr;
+    }
+}
+
+static const void* persist_lookup(int k_dtype, int acc64, int shape_idx, int* wg) {
+    if (k_dtype == UOT_F64) return persist_typed<double, double>(shape_idx, wg);
+    if (k_dtype == UOT_F32) {
+        if (acc64) return persist_typed<float, double>(shape_idx, wg);
+        return persist_typed<float, float>(shape_idx, wg);
+    }
+    return nullptr;
+}
+
+int persist_max_grid(int k_dtype, int acc64, int shape_idx, size_t lds) {
+    int wg = 0;
+    const void* fn = persist_lookup(k_dtype, acc64, shape_idx, &wg);
+    if (!fn) return 0;
+    if (lds > 65536 && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return 0;
+    int dev = 0, cus = 0, coop = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, wg, lds) != hipSuccess) return 0;
+    return per_cu * cus;
+}
+
+hipError_t launch_persist(int k_dtype, int acc64, int shape_idx, const PersistLaunch& P, size_t lds,
+                          hipStream_t stream) {
+    int wg = 0;
+    const void* fn = persist_lookup(k_dtype, acc64, shape_idx, &wg);
+    if (!fn) return hipErrorInvalidValue;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    PersistLaunch arg = P;
+    void* args[] = {&arg};
+    return hipLaunchCooperativeKernel(fn, dim3(P.L.grid), dim3(wg), args, (unsigned)lds, stream);
 }
 
 }  // namespace uot

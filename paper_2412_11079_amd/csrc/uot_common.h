@@ -14,11 +14,11 @@ namespace uot {
 // ---------------------------------------------------------------------------
 struct Ctrl {
     uint32_t done;      // set once the stopping test passed; later launches return at once
-    uint32_t counter;   // arrival counter of the column-finalize blocks (reset by the last)
+    uint32_t bar;       // grid-barrier arrival count of the persistent kernel
     uint32_t flags;     // UOT_FLAG_* accumulated on the device
     uint32_t pad0;
-    int64_t iters;      // iterations completed
-    double err;         // error of the last completed iteration
+    int64_t iters;      // iteration at which the stopping test passed (valid when done)
+    double err;         // its error (valid when done)
 };
 
 // ---------------------------------------------------------------------------
@@ -57,6 +57,27 @@ __device__ __forceinline__ void unpack(const f32x4& r, AT* o) {
     o[2] = (AT)r[2];
     o[3] = (AT)r[3];
 }
+
+// Four adjacent column partials (one 16-byte FP32 chunk or two FP64 chunks)
+// widened to FP64.
+template <typename AT> struct Chunk4;
+template <> struct Chunk4<float> {
+    static __device__ __forceinline__ void load(const float* p, double* o) {
+        f32x4 x = *(const f32x4*)p;
+        o[0] = x[0]; o[1] = x[1]; o[2] = x[2]; o[3] = x[3];
+    }
+};
+template <> struct Chunk4<double> {
+    static __device__ __forceinline__ void load(const double* p, double* o) {
+        f64x2 x = *(const f64x2*)p;
+        f64x2 y = *(const f64x2*)(p + 2);
+        o[0] = x[0]; o[1] = x[1]; o[2] = y[0]; o[3] = y[1];
+    }
+};
+
+// Bound on the sleep-loop iterations of one grid-barrier wait (about a
+// second); exceeding it sets UOT_FLAG_BARRIER_TIMEOUT instead of hanging.
+constexpr uint32_t kBarrierSpinLimit = 1u << 24;
 
 // ---------------------------------------------------------------------------
 // Cross-lane helpers (wave64).
@@ -103,6 +124,21 @@ __device__ __forceinline__ uint32_t ld_volatile_u32(const uint32_t* p) {
     return *(const volatile uint32_t*)p;
 }
 
+// Relative L1 change of the column marginal from the per-block sums the
+// column finalize wrote: sum_k bp[2k] / sum_k bp[2k+1].  Called by one full
+// wave; lanes stride over blocks, then a butterfly, so every caller gets the
+// same bits.
+__device__ __forceinline__ double stop_error(const double* bp, int nblocks, int lane) {
+    double dn = 0.0, dc = 0.0;
+    for (int k = lane; k < nblocks; k += 64) {
+        dn += bp[2 * k];
+        dc += bp[2 * k + 1];
+    }
+    dn = wave_sum_f64(dn);
+    dc = wave_sum_f64(dc);
+    return dn / dc;
+}
+
 // ---------------------------------------------------------------------------
 // Pass kernels (pass.hip).
 // ---------------------------------------------------------------------------
@@ -125,8 +161,16 @@ struct PassLaunch {
     const double* fpot;        // optional row potentials (stabilised form)
     double inv_eps;
     Ctrl* ctrl;
-    int32_t check_done;
+    int32_t check_done;        // 1: return at once when ctrl->done is set
     int64_t ldv_bytes;         // LDS bytes for v (shapes that keep v in LDS), multiple of 16
+    // Stopping test of the previous iteration, evaluated at the start of this
+    // one (the first pass of iteration `iter` reads the column-finalize block
+    // sums of iteration iter-1): stop when tol > 0 and err <= tol.
+    int64_t iter;              // 1-based index of the iteration this launch belongs to
+    int32_t test_stop;         // 1 on the first pass of an iteration
+    int32_t fin_blocks;
+    const double* blockpart;   // 2 x fin_blocks: sum|c - c_prev|, sum|c| per block
+    double tol;
 };
 
 struct PassShape {
@@ -164,13 +208,25 @@ struct FinLaunch {
     const double* gpot;       // optional column potentials
     double inv_eps;
     Ctrl* ctrl;
-    double tol;
     double* blockpart;        // 2 x nblocks
     int32_t marginal_only;    // 1: only w and c are formed
     int32_t acc64;
 };
 
 hipError_t launch_finalize(const FinLaunch& F, hipStream_t stream);
+
+// Persistent (cooperative) whole-loop launch of the fused pass.
+struct PersistLaunch {
+    PassLaunch L;             // L.fin_blocks = grid, L.blockpart: 2 x grid
+    FinLaunch F;              // b, v, w_out, cprev, fi, gpot
+    int32_t max_iter;
+    int32_t fin_cols;         // columns finalized per workgroup (multiple of 4, <= workgroup size)
+    int64_t scratch_bytes;    // LDS bytes before the row staging: max(v, finalize scratch)
+};
+// Largest co-resident grid for the shape (0 when the shape cannot run persistently).
+int persist_max_grid(int k_dtype, int acc64, int shape_idx, size_t lds);
+hipError_t launch_persist(int k_dtype, int acc64, int shape_idx, const PersistLaunch& P, size_t lds,
+                          hipStream_t stream);
 int finalize_blocks(int64_t m);
 
 hipError_t launch_init(double* u, int64_t n, const double* u0, double* v, int64_t m, const double* v0,
@@ -187,6 +243,9 @@ struct ObjLaunch {
     uot_info* info;
     const Ctrl* ctrl;
     double tol;
+    int64_t iters_run;        // iterations enqueued (used when the stopping test never passed)
+    const double* blockpart;  // block sums of the last finalize (error when not stopped)
+    int32_t fin_blocks;
 };
 hipError_t launch_objective(const ObjLaunch& O, hipStream_t stream);
 

@@ -30,7 +30,7 @@ def gpu_cost(prob) -> torch.Tensor:
 
 
 def gpu_solve(prob, k_dtype=torch.float32, max_iter=None, tol=None, fused=True, check_every=1, tune=0,
-              accum="f32", C=None, K=None):
+              accum="f32", C=None, K=None, persistent=False):
     if C is None and K is None:
         C = gpu_cost(prob)
     if K is None:
@@ -38,7 +38,7 @@ def gpu_solve(prob, k_dtype=torch.float32, max_iter=None, tol=None, fused=True, 
     res = uot.sinkhorn(to_dev(prob.a), to_dev(prob.b), K, m=prob.m, eps=prob.eps, tau=prob.tau,
                        max_iter=prob.max_iter if max_iter is None else max_iter,
                        tol=prob.tol if tol is None else tol, fused=fused, check_every=check_every,
-                       tune=tune, accum=accum)
+                       tune=tune, accum=accum, persistent=persistent)
     torch.cuda.synchronize()
     return res, K
 

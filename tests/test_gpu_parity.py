@@ -266,3 +266,36 @@ def test_headline_full_size_against_oracle():
     say("  GPU ...")
     res, _ = gpu_solve(prob, k_dtype=torch.float32)
     compare(res, ref, 1e-6, 1e-6, "headline T=10")
+
+
+# ------------------------------------------------------------------ persistent loop
+@pytest.mark.parametrize("n,m,dtype,tune", [(3000, 5000, torch.float32, 0), (3000, 5000, torch.float64, 0),
+                                            (1000, 16381, torch.float32, 6), (2048, 16381, torch.float32, 8),
+                                            (257, 100, torch.float32, 0)])
+def test_persistent_loop_matches_oracle(n, m, dtype, tune):
+    prob = workloads.headline(n=n, m=m, max_iter=25)
+    ref = _oracle(prob)
+    tol = 1e-12 if dtype == torch.float64 else 1e-6
+    say(f"persistent n={n} m={m} {dtype} tune={tune}")
+    res, _ = gpu_solve(prob, k_dtype=dtype, persistent=True, tune=tune)
+    info = res.info()
+    assert info["iters"] == 25 and info["flags"] == 0, info
+    compare(res, ref, tol, tol, "persistent")
+
+
+def test_persistent_tolerance_stop():
+    prob = workloads.headline(n=900, m=1100, max_iter=2000, tol=1e-6)
+    ref = _oracle(prob)
+    res, _ = gpu_solve(prob, k_dtype=torch.float64, persistent=True)
+    info = res.info()
+    assert info["iters"] == ref.iters and info["err"] <= 1e-6
+    compare(res, ref, 1e-12, 1e-12, "persistent tol stop")
+
+
+def test_persistent_headline_full_size():
+    prob = workloads.headline(max_iter=10)
+    ref = _oracle(prob)
+    for tune in (6, 8):
+        res, _ = gpu_solve(prob, k_dtype=torch.float32, persistent=True, tune=tune)
+        assert res.info()["flags"] == 0
+        compare(res, ref, 1e-6, 1e-6, f"persistent headline T=10 tune={tune}")
