@@ -109,7 +109,8 @@ typedef struct uot_options {
     int32_t fused;            /* 1: single pass over K per iteration; 0: plain row pass + column pass */
     int32_t accum;            /* uot_accum */
     double absorb_log_threshold;  /* reserved, must be 0 */
-    int32_t checkpoint_every; /* reserved, must be 0 */
+    int32_t checkpoint_every; /* k > 0: write v and K^T u every k iterations to outputs.ckpt
+                                 (needs tol <= 0 and persistent = 0); 0 = none */
     int32_t tune;             /* 0: default launch shape; k > 0: use tuned shape index k-1 */
     const double* u0;         /* optional warm start (device, n), else u = 1 */
     const double* v0;         /* optional warm start (device, m), else v = 1 */
@@ -126,6 +127,9 @@ typedef struct uot_outputs {
     double* c;                /* optional: device m, column marginal v * (K^T u) */
     double* loss;             /* optional: device scalar, UOT objective of P_T */
     uot_info* info;           /* optional: device report */
+    double* ckpt;             /* with options.checkpoint_every = k > 0: device buffer of
+                                 (ceil(max_iter/k) + 1) x 2m doubles; slot c holds v and K^T u
+                                 after iteration c*k (slot 0: the starting v) */
 } uot_outputs;
 
 /* Per-kernel durations of one uot_sinkhorn_profiled call, measured with HIP
@@ -207,6 +211,38 @@ uot_status uot_sinkhorn(const uot_problem* prob, const uot_options* opt,
 uot_status uot_sinkhorn_profiled(const uot_problem* prob, const uot_options* opt,
                                  const uot_outputs* out, void* ws, size_t ws_bytes,
                                  void* stream, uot_profile* prof);
+
+/*
+ * Gradient of the objective returned by uot_sinkhorn (the loop unrolled
+ * for exactly opt->max_iter iterations from v = 1, differentiated in
+ * reverse mode; the paper gives no gradient, this is the exact derivative of
+ * the iteration of Section 2.1 as written above).  Each reverse step streams
+ * K once: row dots with the adjoint column vector (and, for point gradients,
+ * with it and v_{t-1} times each coordinate of y), then the column partials
+ * of K^T sbar.  Iterates are recomputed segment by segment from the
+ * checkpoints of the forward call (same problem and options, including
+ * checkpoint_every; the forward must not have been given u0/v0).
+ *
+ *   u, v        forward results u_T, v_T (device, n and m)
+ *   ckpt        the forward's outputs.ckpt
+ *   grad_loss   device scalar g; outputs are g times dL/d(input)
+ *   grad_a      device n or NULL;  grad_b  device m or NULL
+ *   x, y, dim   source (n x dim) and target (m x dim) points, row-major FP64,
+ *               of a squared-Euclidean cost C_ij = ||x_i - y_j||^2 that was
+ *               not max-normalised; dim 0 (no point gradient), 2 or 3
+ *   grad_x      device n x dim or NULL: dL/dx via dL/dC_ij = -Kbar_ij K_ij / eps
+ *
+ * Requirements: max_iter >= 1, checkpoint_every >= 1, tol <= 0, histogram
+ * entries > 0, rows of at most 8192 columns (FP32 or FP64 K).
+ * Errors: UOT_ERR_ARG, UOT_ERR_UNSUPPORTED, UOT_ERR_WORKSPACE, UOT_ERR_ALIGN,
+ * UOT_ERR_HIP.  Workspace: uot_sinkhorn_backward_workspace_size bytes.
+ */
+size_t uot_sinkhorn_backward_workspace_size(const uot_problem* prob, const uot_options* opt, int64_t dim);
+uot_status uot_sinkhorn_backward(const uot_problem* prob, const uot_options* opt,
+                                 const double* u, const double* v, const double* ckpt,
+                                 const double* grad_loss, double* grad_a, double* grad_b,
+                                 const double* x, const double* y, int64_t dim, double* grad_x,
+                                 void* ws, size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

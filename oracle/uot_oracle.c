@@ -407,6 +407,7 @@ ORC_EXPORT void orc_adjoint(const double* K, const double* a, const double* b,
     orc_KTu(K, tmpn, n, m, tmpm);
     for (int64_t j = 0; j < m; ++j) vbar[j] = eps * wu[j] + tmpm[j] + cbar[j] * wu[j];
     /* Kbar = (rbar*u) v^T + u (cbar*v)^T */
+    #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i)
         for (int64_t j = 0; j < m; ++j)
             Kbar[i * m + j] = rbar[i] * uT[i] * vT[j] + uT[i] * cbar[j] * vT[j];
@@ -423,6 +424,7 @@ ORC_EXPORT void orc_adjoint(const double* K, const double* a, const double* b,
         }
         orc_Kv(K, wbar, n, m, tmpn);
         for (int64_t i = 0; i < n; ++i) ubar[i] += tmpn[i];
+        #pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < n; ++i)
             for (int64_t j = 0; j < m; ++j) Kbar[i * m + j] += ut[i] * wbar[j];
         for (int64_t i = 0; i < n; ++i) {
@@ -430,11 +432,13 @@ ORC_EXPORT void orc_adjoint(const double* K, const double* a, const double* b,
             if (a[i] != 0.0) grad_a[i] += fi * ubar[i] * ut[i] / a[i];
         }
         orc_KTu(K, sbar, n, m, vbar);
+        #pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < n; ++i)
             for (int64_t j = 0; j < m; ++j) Kbar[i * m + j] += sbar[i] * vprev[j];
         for (int64_t i = 0; i < n; ++i) ubar[i] = 0.0;
     }
     if (G) {
+        #pragma omp parallel for schedule(static)
         for (int64_t t = 0; t < n * m; ++t) G[t] = -Kbar[t] * K[t] / eps;
     }
     free(Kbar); free(sv); free(wu); free(rbar); free(cbar); free(ubar); free(vbar);

@@ -17,7 +17,8 @@ from . import _lib
 from ._lib import (UOT_ACC_F32, UOT_ACC_F64, UOT_BF16, UOT_COST_COSINE, UOT_COST_SQEUCLID, UOT_F32, UOT_F64,
                    UOT_FLAG_NONFINITE, UOT_FLAG_NOT_CONVERGED, UOT_FLAG_ZERO_SUM, UOT_FP8_E4M3, UOTError)
 
-__all__ = ["sinkhorn", "cost_from_points", "kernel_from_cost", "SinkhornResult", "UOTError", "lib_path",
+__all__ = ["sinkhorn", "sinkhorn_backward", "UOTLoss", "uot_loss", "cost_from_points", "kernel_from_cost",
+           "SinkhornResult", "UOTError", "lib_path",
            "UOT_F64", "UOT_F32", "UOT_BF16", "UOT_FP8_E4M3", "UOT_COST_SQEUCLID", "UOT_COST_COSINE"]
 
 _DTYPES = {torch.float64: UOT_F64, torch.float32: UOT_F32}
@@ -145,7 +146,7 @@ def sinkhorn(a: torch.Tensor, b: torch.Tensor, K: Optional[torch.Tensor] = None,
              fused: bool = True, accum: str = "f32", check_every: int = 1, tune: int = 0,
              k_dtype: Optional[torch.dtype] = None, u0: Optional[torch.Tensor] = None,
              v0: Optional[torch.Tensor] = None, persistent: bool = False,
-             profile: bool = False) -> SinkhornResult:
+             checkpoint_every: int = 0, profile: bool = False) -> SinkhornResult:
     """UOT Sinkhorn scaling loop on the GPU (see include/uot.h, uot_sinkhorn).
 
     ``K`` is an (n, ldk) FP32/FP64 kernel (as returned by kernel_from_cost);
@@ -167,7 +168,7 @@ def sinkhorn(a: torch.Tensor, b: torch.Tensor, K: Optional[torch.Tensor] = None,
     opt.fused = 1 if fused else 0
     opt.accum = UOT_ACC_F64 if accum == "f64" else UOT_ACC_F32
     opt.absorb_log_threshold = 0.0
-    opt.checkpoint_every = 0
+    opt.checkpoint_every = int(checkpoint_every)
     opt.tune = int(tune)
     opt.u0 = None if u0 is None else _vec64(u0, "u0", n, device).data_ptr()
     opt.v0 = None if v0 is None else _vec64(v0, "v0", m, device).data_ptr()
@@ -183,7 +184,12 @@ def sinkhorn(a: torch.Tensor, b: torch.Tensor, K: Optional[torch.Tensor] = None,
     c = torch.empty(m, dtype=torch.float64, device=device)
     loss = torch.empty((), dtype=torch.float64, device=device)
     info = torch.zeros(ctypes.sizeof(_lib.Info), dtype=torch.uint8, device=device)
-    out = _lib.Outputs(u.data_ptr(), v.data_ptr(), r.data_ptr(), c.data_ptr(), loss.data_ptr(), info.data_ptr())
+    ckpt = None
+    if checkpoint_every > 0:
+        slots = (int(max_iter) + int(checkpoint_every) - 1) // int(checkpoint_every) + 1
+        ckpt = torch.zeros(slots * 2 * m, dtype=torch.float64, device=device)
+    out = _lib.Outputs(u.data_ptr(), v.data_ptr(), r.data_ptr(), c.data_ptr(), loss.data_ptr(), info.data_ptr(),
+                       None if ckpt is None else ckpt.data_ptr())
     prof = None
     if profile:
         p = _lib.Profile()
@@ -195,4 +201,86 @@ def sinkhorn(a: torch.Tensor, b: torch.Tensor, K: Optional[torch.Tensor] = None,
                                   _stream(device)))
     res = SinkhornResult(u=u, v=v, r=r, c=c, loss=loss, info_raw=info, profile=prof)
     res._keepalive = (ws, K, C, a, b)  # buffers must outlive the enqueued work
+    res._problem = prob
+    res._options = opt
+    res.ckpt = ckpt
     return res
+
+
+def sinkhorn_backward(res: SinkhornResult, grad_loss: torch.Tensor, *, x: Optional[torch.Tensor] = None,
+                      y: Optional[torch.Tensor] = None, want_a: bool = True, want_b: bool = True):
+    """Reverse pass of ``sinkhorn(..., checkpoint_every=k)`` (include/uot.h,
+    uot_sinkhorn_backward).  ``grad_loss`` is a device FP64 scalar.  With the
+    points ``x`` (n x d) and ``y`` (m x d) of an un-normalised squared-Euclidean
+    cost, also returns dL/dx.  Returns (grad_a, grad_b, grad_x)."""
+    if res.ckpt is None:
+        raise ValueError("the forward call needs checkpoint_every > 0")
+    prob, opt = res._problem, res._options
+    device = res.u.device
+    n, m = res.u.shape[0], res.v.shape[0]
+    g = grad_loss.reshape(()).to(dtype=torch.float64, device=device).contiguous()
+    dim = 0
+    if y is not None:
+        if y.dtype != torch.float64 or y.dim() != 2 or y.shape[0] != m:
+            raise ValueError("y must be an (m, d) float64 tensor")
+        y = y.contiguous()
+        dim = y.shape[1]
+    if x is not None:
+        if y is None or x.dtype != torch.float64 or x.shape != (n, dim):
+            raise ValueError("x must be an (n, d) float64 tensor matching y")
+        x = x.contiguous()
+    L = _lib.lib()
+    need = L.uot_sinkhorn_backward_workspace_size(ctypes.byref(prob), ctypes.byref(opt), dim)
+    if need == 0:
+        _lib.check(L.uot_sinkhorn_backward(ctypes.byref(prob), ctypes.byref(opt), None, None, None, None, None,
+                                           None, None, None, dim, None, None, 0, None))
+    ws = _workspace(need, device)
+    ga = torch.empty(n, dtype=torch.float64, device=device) if want_a else None
+    gb = torch.empty(m, dtype=torch.float64, device=device) if want_b else None
+    gx = torch.empty((n, dim), dtype=torch.float64, device=device) if x is not None else None
+    _lib.check(L.uot_sinkhorn_backward(ctypes.byref(prob), ctypes.byref(opt), _ptr(res.u), _ptr(res.v),
+                                       _ptr(res.ckpt), _ptr(g), _ptr(ga), _ptr(gb), _ptr(x), _ptr(y), dim,
+                                       _ptr(gx), _ptr(ws), ws.numel(), _stream(device)))
+    ga_keep = (ws, g, x, y)
+    del ga_keep
+    return ga, gb, gx
+
+
+class UOTLoss(torch.autograd.Function):
+    """UOT objective of the unrolled loop on points, with gradients w.r.t. the
+    source points x, and the histograms a and b (the target points y get none).
+
+    Forward: squared-Euclidean cost of (x, y) (not normalised), Gibbs kernel
+    in ``k_dtype``, ``max_iter`` fused iterations with v and K^T u saved every
+    ``checkpoint_every``; backward: the library's reverse pass."""
+
+    @staticmethod
+    def forward(ctx, x, y, a, b, eps: float, tau: float, max_iter: int, checkpoint_every: int = 50,
+                k_dtype: torch.dtype = torch.float32):
+        x64 = x.detach().to(torch.float64).contiguous()
+        y64 = y.detach().to(torch.float64).contiguous()
+        C = cost_from_points(x64, y64, UOT_COST_SQEUCLID, False)
+        K = kernel_from_cost(C, eps, k_dtype)
+        del C
+        res = sinkhorn(a.detach().to(torch.float64).contiguous(), b.detach().to(torch.float64).contiguous(), K,
+                       eps=eps, tau=tau, max_iter=max_iter, checkpoint_every=checkpoint_every)
+        ctx.res = res
+        ctx.save_for_backward(x64, y64)
+        ctx.dtypes = (x.dtype, a.dtype, b.dtype)
+        return res.loss.clone().to(x.dtype)
+
+    @staticmethod
+    def backward(ctx, grad):
+        x64, y64 = ctx.saved_tensors
+        need_x, _, need_a, need_b = ctx.needs_input_grad[:4]
+        ga, gb, gx = sinkhorn_backward(ctx.res, grad.detach().to(torch.float64), x=x64 if need_x else None,
+                                       y=y64 if need_x else None, want_a=need_a, want_b=need_b)
+        xd, ad, bd = ctx.dtypes
+        return (gx.to(xd) if gx is not None else None, None, ga.to(ad) if ga is not None else None,
+                gb.to(bd) if gb is not None else None, None, None, None, None, None)
+
+
+def uot_loss(x, y, a, b, eps: float, tau: float, max_iter: int, checkpoint_every: int = 50,
+             k_dtype: torch.dtype = torch.float32) -> torch.Tensor:
+    """Differentiable UOT objective (see UOTLoss)."""
+    return UOTLoss.apply(x, y, a, b, eps, tau, max_iter, checkpoint_every, k_dtype)

@@ -36,7 +36,7 @@ class Options(ctypes.Structure):
 
 
 class Outputs(ctypes.Structure):
-    _fields_ = [("u", _vp), ("v", _vp), ("r", _vp), ("c", _vp), ("loss", _vp), ("info", _vp)]
+    _fields_ = [("u", _vp), ("v", _vp), ("r", _vp), ("c", _vp), ("loss", _vp), ("info", _vp), ("ckpt", _vp)]
 
 
 class Profile(ctypes.Structure):
@@ -59,6 +59,9 @@ SIGNATURES = {
                      _i32),
     "uot_sinkhorn_profiled": ([ctypes.POINTER(Problem), ctypes.POINTER(Options), ctypes.POINTER(Outputs), _vp,
                                _sz, _vp, ctypes.POINTER(Profile)], _i32),
+    "uot_sinkhorn_backward_workspace_size": ([ctypes.POINTER(Problem), ctypes.POINTER(Options), _i64], _sz),
+    "uot_sinkhorn_backward": ([ctypes.POINTER(Problem), ctypes.POINTER(Options), _vp, _vp, _vp, _vp, _vp, _vp,
+                               _vp, _vp, _i64, _vp, _vp, _sz, _vp], _i32),
 }
 
 _lib = None

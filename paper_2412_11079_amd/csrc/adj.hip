@@ -1,0 +1,384 @@
+// Reverse mode through the unrolled UOT Sinkhorn iteration.
+//
+// The forward iteration (paper Section 2.1 on scaling vectors; rows first
+// from v_0 = 1) is t = 1..T:  s_t = K v_{t-1}, u_t = (a/s_t)^fi,
+// w_t = K^T u_t, v_t = (b/w_t)^fi, and the objective is
+//   L = eps (sum r log u_T + sum c log v_T - sum r) + tau KL~(r|a) + tau KL~(c|b),
+// r = u_T * (K v_T), c = v_T * (K^T u_T).  Its exact gradient:
+//
+// seeds   rbar = eps log u + tau log(r/a) - eps,   cbar = eps log v + tau log(c/b)
+//         ubar_T = eps K v + rbar * K v + K (cbar * v)
+//         vbar_T = eps K^T u + K^T (rbar * u) + cbar * K^T u
+//         Kbar  = (rbar * u) v^T + u (cbar * v)^T,   abar = tau (1 - r/a),  bbar = tau (1 - c/b)
+// step t  wbar = -fi vbar_t * v_t / w_t;   bbar += fi vbar_t * v_t / b
+//         ubar_t = K wbar (+ ubar_T at t = T);   Kbar += u_t wbar^T
+//         sbar = -fi ubar_t * u_t / s_t;   abar += fi ubar_t * u_t / a
+//         vbar_{t-1} = K^T sbar;   Kbar += sbar v_{t-1}^T
+//
+// dL/dC = -Kbar * K / eps is never formed: for a squared-Euclidean cost of
+// points, dL/dx_i = 2 (x_i sum_j G_ij - sum_j G_ij y_j), G = dL/dC, and both
+// row sums follow from extra right-hand sides of the same row pass:
+//   sum_j K_ij Kbar_ij (1, y_j) = u_i (K (wbar*(1,y)))_i + sbar_i (K (v_{t-1}*(1,y)))_i.
+//
+// One adjoint pass per step streams K once (row dots with A = wbar and
+// B = v_{t-1}, times 1 and each coordinate of y; then the column partials of
+// K^T sbar), so a reverse step costs what a forward iteration costs.
+#include "strip.h"
+
+namespace uot {
+
+template <typename KT, typename AT, int WG, int NC, int D, int DIM, int PHASE>
+__global__ __launch_bounds__(WG) void adj_kernel(AdjLaunch L) {
+    using S = Strip<KT, AT, WG, NC, D, false, MODE_COL>;
+    using Raw = typename S::Raw;
+    constexpr int V = S::V;
+    constexpr int E = S::E;
+    constexpr int NW = WG / 64;
+    constexpr bool kB = (PHASE == ADJ_SEED) || (DIM > 0);   // dots with B needed
+    constexpr int ND = 2 + 2 * DIM;                         // dA, dB, dAy[DIM], dBy[DIM]
+    __shared__ double red[2][ND][NW];
+    extern __shared__ __align__(16) unsigned char dyn_lds[];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * L.rows_per_wg;
+    int64_t r1 = r0 + L.rows_per_wg;
+    if (r1 > L.n) r1 = L.n;
+    const int nrows = (int)(r1 - r0);
+    const int64_t m = L.m;
+
+    PassLaunch P;
+    P.K = L.K;
+    P.ldk = L.ldk;
+    P.m = L.m;
+    S st;
+    st.setup(P, r0, nrows);
+    st.prime();
+
+    // LDS per row of the strip: u, s, a, useed, abar, gsum, gy[DIM]
+    const int R = (int)L.rows_per_wg;
+    double* lu = (double*)dyn_lds;
+    double* ls = lu + R;
+    double* la = ls + R;
+    double* lseed = la + R;
+    double* labar = lseed + R;
+    double* lgsum = labar + R;
+    double* lgy = lgsum + R;
+    for (int k = tid; k < nrows; k += WG) {
+        const int64_t i = r0 + k;
+        lu[k] = L.u[i];
+        la[k] = L.a[i];
+        if constexpr (PHASE == ADJ_STEP) {
+            ls[k] = L.s[i];
+            lseed[k] = L.add_seed ? L.useed[i] : 0.0;
+            labar[k] = L.abar[i];
+            if constexpr (DIM > 0) {
+                lgsum[k] = L.gsum[i];
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) lgy[k * DIM + d] = L.gy[i * DIM + d];
+            }
+        }
+    }
+
+    // Coordinates of y in LDS, one contiguous row per coordinate (after the
+    // per-row arrays): yl[d * mp + j].
+    const int64_t mp = (m + V - 1) / V * V;
+    AT* yl = (AT*)(lgy + (size_t)R * (DIM > 0 ? DIM : 1));
+    if constexpr (DIM > 0) {
+        for (int64_t j = tid; j < mp; j += WG)
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) yl[d * mp + j] = (j < m) ? (AT)L.y[j * DIM + d] : (AT)0;
+    }
+    // Right-hand sides of this lane's columns.
+    AT Av[E], Bv[kB ? E : 1];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            const int64_t j = st.col[c] + e;
+            const bool in = j < m;
+            Av[c * V + e] = in ? (AT)L.A[j] : (AT)0;
+            if constexpr (kB) Bv[c * V + e] = in ? (AT)L.B[j] : (AT)0;
+        }
+    st.clear_acc();
+    __syncthreads();
+
+    const double inv_eps = 1.0 / L.eps;
+    int slot = 0;
+    auto process = [&](Raw (&b)[NC], int k) {
+        AT dA = 0, dB = 0, dAy[DIM > 0 ? DIM : 1], dBy[DIM > 0 ? DIM : 1];
+#pragma unroll
+        for (int d = 0; d < (DIM > 0 ? DIM : 1); ++d) dAy[d] = dBy[d] = 0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            AT x[V];
+            unpack<AT>(b[c], x);
+            if (st.ragged) {
+#pragma unroll
+                for (int e = 0; e < V; ++e)
+                    if (st.col[c] + e >= m) x[e] = (AT)0;
+            }
+            const bool live = st.col[c] < m;
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const int q = c * V + e;
+                const AT tA = x[e] * Av[q];
+                dA += tA;
+                AT tB = (AT)0;
+                if constexpr (kB) {
+                    tB = x[e] * Bv[q];
+                    dB += tB;
+                }
+                if constexpr (DIM > 0) {
+                    if (live) {
+#pragma unroll
+                        for (int d = 0; d < DIM; ++d) {
+                            const AT yv = yl[d * mp + st.col[c] + e];
+                            dAy[d] = fma(tA, yv, dAy[d]);
+                            dBy[d] = fma(tB, yv, dBy[d]);
+                        }
+                    }
+                }
+            }
+        }
+        double part[ND];
+        part[0] = wave_sum_f64((double)dA);
+        part[1] = kB ? wave_sum_f64((double)dB) : 0.0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            part[2 + d] = wave_sum_f64((double)dAy[d]);
+            part[2 + DIM + d] = wave_sum_f64((double)dBy[d]);
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int q = 0; q < ND; ++q) red[slot][q][wave] = part[q];
+        }
+        __syncthreads();
+        double T[ND];
+#pragma unroll
+        for (int q = 0; q < ND; ++q) {
+            double acc = 0.0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) acc += red[slot][q][w];
+            T[q] = acc;
+        }
+        slot ^= 1;
+        const double ui = lu[k], ai = la[k];
+        double qrow;
+        if constexpr (PHASE == ADJ_SEED) {
+            // T[0] = (K (cbar v))_i, T[1] = (K v_T)_i
+            double rbar = 0.0, useed = 0.0, abar = 0.0;
+            if (ui > 0.0) {
+                const double r = ui * T[1];
+                rbar = L.eps * log(ui) - L.eps + (L.tau_inf ? 0.0 : L.tau * log(r / ai));
+                useed = L.eps * T[1] + rbar * T[1] + T[0];
+                abar = L.tau_inf ? 0.0 : L.tau * (1.0 - r / ai);
+            }
+            qrow = rbar * ui;
+            if (tid == 0) {
+                lseed[k] = useed;
+                labar[k] = abar;
+                if constexpr (DIM > 0) {
+                    lgsum[k] = -inv_eps * (rbar * ui * T[1] + ui * T[0]);
+#pragma unroll
+                    for (int d = 0; d < DIM; ++d)
+                        lgy[k * DIM + d] = -inv_eps * (rbar * ui * T[2 + DIM + d] + ui * T[2 + d]);
+                }
+            }
+        } else {
+            // T[0] = (K wbar)_i, T[1] = (K v_{t-1})_i = s_t,i
+            const double ubar = T[0] + lseed[k];
+            const double si = ls[k];
+            const double sbar = (ui > 0.0) ? -L.fi * ubar * ui / si : 0.0;
+            qrow = sbar;
+            if (tid == 0) {
+                if (ai > 0.0) labar[k] += L.fi * ubar * ui / ai;
+                if constexpr (DIM > 0) {
+                    lgsum[k] += -inv_eps * (ui * T[0] + sbar * T[1]);
+#pragma unroll
+                    for (int d = 0; d < DIM; ++d) lgy[k * DIM + d] += -inv_eps * (ui * T[2 + d] + sbar * T[2 + DIM + d]);
+                }
+            }
+        }
+        const AT qa = (AT)qrow;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            AT x[V];
+            unpack<AT>(b[c], x);
+#pragma unroll
+            for (int e = 0; e < V; ++e) st.acc[c * V + e] = fma(x[e], qa, st.acc[c * V + e]);
+        }
+    };
+
+    static_assert(D == 2, "the adjoint pass is pipelined two rows deep");
+    for (int k0 = 0; k0 < nrows; k0 += 2) {
+        st.template load_row<1>(k0 + 1);
+        process(st.buf[0], k0);
+        if (k0 + 1 >= nrows) break;
+        st.template load_row<0>(k0 + 2);
+        process(st.buf[1], k0 + 1);
+    }
+
+    __syncthreads();
+    for (int k = tid; k < nrows; k += WG) {
+        const int64_t i = r0 + k;
+        if constexpr (PHASE == ADJ_SEED) L.useed[i] = lseed[k];
+        L.abar[i] = labar[k];
+        if constexpr (DIM > 0) {
+            L.gsum[i] = lgsum[k];
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) L.gy[i * DIM + d] = lgy[k * DIM + d];
+        }
+    }
+    st.store_partials((AT*)L.partials + (int64_t)blockIdx.x * L.ldp);
+}
+
+size_t adj_lds_bytes(int64_t rows_per_wg, int dim, int64_t m, int elem) {
+    const int64_t mp = (m + 15) / 16 * 16;
+    return sizeof(double) * (size_t)rows_per_wg * (6 + (size_t)(dim > 0 ? dim : 1)) + (size_t)elem * mp * dim + 16;
+}
+
+template <typename KT, typename AT, int WG, int NC, int DIM>
+static hipError_t adj_launch_dim(int phase, const AdjLaunch& L, hipStream_t stream) {
+    const size_t lds = adj_lds_bytes(L.rows_per_wg, DIM, L.m, (int)sizeof(AT));
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)adj_kernel<KT, AT, WG, NC, 2, DIM, ADJ_SEED>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        e = hipFuncSetAttribute((const void*)adj_kernel<KT, AT, WG, NC, 2, DIM, ADJ_STEP>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    if (phase == ADJ_SEED)
+        hipLaunchKernelGGL((adj_kernel<KT, AT, WG, NC, 2, DIM, ADJ_SEED>), dim3(L.grid), dim3(WG), lds, stream, L);
+    else
+        hipLaunchKernelGGL((adj_kernel<KT, AT, WG, NC, 2, DIM, ADJ_STEP>), dim3(L.grid), dim3(WG), lds, stream, L);
+    return hipGetLastError();
+}
+
+template <typename KT, typename AT, int WG, int NC>
+static hipError_t adj_launch_nc(int phase, int dim, const AdjLaunch& L, hipStream_t stream) {
+    switch (dim) {
+        case 0: return adj_launch_dim<KT, AT, WG, NC, 0>(phase, L, stream);
+        case 2: return adj_launch_dim<KT, AT, WG, NC, 2>(phase, L, stream);
+        case 3: return adj_launch_dim<KT, AT, WG, NC, 3>(phase, L, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// 512-lane workgroups (two waves per SIMD, 256 VGPRs): each lane holds A, B
+// and the coordinates of y for its columns in registers.
+int adj_chunks_max(int k_dtype) { return 4; }
+int adj_wg() { return 512; }
+
+hipError_t launch_adj(int k_dtype, int nc, int phase, int dim, const AdjLaunch& L, hipStream_t stream) {
+    if (k_dtype == UOT_F32) {
+        if (nc == 1) return adj_launch_nc<float, float, 512, 1>(phase, dim, L, stream);
+        if (nc == 2) return adj_launch_nc<float, float, 512, 2>(phase, dim, L, stream);
+        if (nc == 4) return adj_launch_nc<float, float, 512, 4>(phase, dim, L, stream);
+    } else if (k_dtype == UOT_F64) {
+        if (nc == 1) return adj_launch_nc<double, double, 512, 1>(phase, dim, L, stream);
+        if (nc == 2) return adj_launch_nc<double, double, 512, 2>(phase, dim, L, stream);
+        if (nc == 4) return adj_launch_nc<double, double, 512, 4>(phase, dim, L, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Column side of the reverse pass: sums of the partials (fixed order, FP64)
+// and the O(m) updates around them.
+//   ADJ_COL_PREP  w = K^T u_T; c = v w; cbar, h = cbar * v (the seed pass's A), bbar = tau(1 - c/b)
+//   ADJ_COL_SEED  vbar_T = sum + eps w + cbar w; then the step-T update below
+//   ADJ_COL_STEP  vbar_{t-1} = sum; then wbar = -fi vbar v / w, bbar += fi vbar v / b
+// ---------------------------------------------------------------------------
+constexpr int ACOL_COLS = 16;
+constexpr int ACOL_THREADS = 256;
+constexpr int ACOL_PHASES = ACOL_THREADS / (ACOL_COLS / 4);
+
+template <typename AT>
+__global__ __launch_bounds__(ACOL_THREADS) void adj_col_kernel(AdjColLaunch C) {
+    __shared__ double part[ACOL_PHASES][ACOL_COLS + 1];
+    const int tid = threadIdx.x;
+    const int cg = tid & (ACOL_COLS / 4 - 1);
+    const int ph = tid / (ACOL_COLS / 4);
+    const int64_t c0 = (int64_t)blockIdx.x * ACOL_COLS + 4 * cg;
+    const AT* Pp = (const AT*)C.partials + c0;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (c0 < C.m) {
+        for (int g = ph; g < C.G; g += ACOL_PHASES) {
+            double x[4];
+            Chunk4<AT>::load(Pp + (int64_t)g * C.ldp, x);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[e] += x[e];
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) part[ph][4 * cg + e] = acc[e];
+    __syncthreads();
+    if (tid >= ACOL_COLS) return;
+    const int64_t j = (int64_t)blockIdx.x * ACOL_COLS + tid;
+    if (j >= C.m) return;
+    double sum = 0.0;
+    for (int k = 0; k < ACOL_PHASES; ++k) sum += part[k][tid];
+    const double vj = C.v[j], bj = C.b[j];
+    if (C.mode == ADJ_COL_PREP) {
+        const double w = sum;
+        const double c = vj * w;
+        double cbar = 0.0, bbar = 0.0;
+        if (vj > 0.0) {
+            cbar = C.eps * log(vj) + (C.tau_inf ? 0.0 : C.tau * log(c / bj));
+            bbar = C.tau_inf ? 0.0 : C.tau * (1.0 - c / bj);
+        }
+        C.w[j] = w;
+        C.cbar[j] = cbar;
+        C.out[j] = cbar * vj;
+        C.bbar[j] = bbar;
+        return;
+    }
+    double vbar = sum;
+    if (C.mode == ADJ_COL_SEED) vbar += C.eps * C.w[j] + C.cbar[j] * C.w[j];
+    double wbar = 0.0;
+    if (vj > 0.0) {
+        wbar = -C.fi * vbar * vj / C.w[j];
+        C.bbar[j] += C.fi * vbar * vj / bj;
+    }
+    C.out[j] = wbar;
+}
+
+hipError_t launch_adj_col(const AdjColLaunch& C, hipStream_t stream) {
+    dim3 grid((unsigned)((C.m + ACOL_COLS - 1) / ACOL_COLS)), block(ACOL_THREADS);
+    if (C.acc64)
+        hipLaunchKernelGGL(adj_col_kernel<double>, grid, block, 0, stream, C);
+    else
+        hipLaunchKernelGGL(adj_col_kernel<float>, grid, block, 0, stream, C);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Final scaling by dLoss: grad_a = g abar, grad_b = g bbar,
+// grad_x_i = 2 g (x_i gsum_i - gy_i).
+// ---------------------------------------------------------------------------
+__global__ void adj_finish_kernel(AdjFinish F) {
+    const double g = *F.grad_loss;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = t; i < F.n; i += stride) {
+        if (F.grad_a) F.grad_a[i] = g * F.abar[i];
+        if (F.grad_x)
+            for (int d = 0; d < F.dim; ++d)
+                F.grad_x[i * F.dim + d] = 2.0 * g * (F.x[i * F.dim + d] * F.gsum[i] - F.gy[i * F.dim + d]);
+    }
+    for (int64_t j = t; j < F.m; j += stride)
+        if (F.grad_b) F.grad_b[j] = g * F.bbar[j];
+}
+
+hipError_t launch_adj_finish(const AdjFinish& F, hipStream_t stream) {
+    int64_t mx = F.n > F.m ? F.n : F.m;
+    int blocks = (int)((mx + 255) / 256);
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(adj_finish_kernel, dim3(blocks), dim3(256), 0, stream, F);
+    return hipGetLastError();
+}
+
+}  // namespace uot

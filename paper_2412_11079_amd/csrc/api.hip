@@ -113,7 +113,9 @@ uot_status check_problem(const uot_problem* p, const uot_options* o) {
     if (o->max_iter < 0) return fail(UOT_ERR_ARG, "max_iter must be >= 0");
     if (o->absorb_log_threshold != 0.0)
         return fail(UOT_ERR_UNSUPPORTED, "log-domain absorption is not available in this entry point");
-    if (o->checkpoint_every != 0) return fail(UOT_ERR_UNSUPPORTED, "checkpoints are not available in this entry point");
+    if (o->checkpoint_every < 0) return fail(UOT_ERR_ARG, "checkpoint_every must be >= 0");
+    if (o->checkpoint_every > 0 && (o->tol > 0.0 || o->persistent))
+        return fail(UOT_ERR_UNSUPPORTED, "checkpoints need a fixed iteration count (tol <= 0) and per-iteration launches");
     if (p->k_dtype != UOT_F64 && p->k_dtype != UOT_F32)
         return fail(UOT_ERR_DTYPE, "K dtype %d not supported (FP64, FP32)", (int)p->k_dtype);
     const int es = elem_size(p->k_dtype);
@@ -256,6 +258,13 @@ uot_status run_sinkhorn(const uot_problem* p, const uot_options* o, const uot_ou
 
     const double fi = fi_of(p->eps, p->tau);
     UOT_HIP(launch_init(out->u, p->n, o->u0, out->v, p->m, o->v0, cprev, ctrl, stream), "init");
+    // Checkpoint slot c holds v and K^T u after iteration c*k (slot 0: the start v).
+    const int ck = o->checkpoint_every;
+    if (ck > 0) {
+        if (!out->ckpt) return fail(UOT_ERR_ARG, "checkpoint_every > 0 needs outputs->ckpt");
+        UOT_HIP(hipMemcpyAsync(out->ckpt, out->v, sizeof(double) * p->m, hipMemcpyDeviceToDevice, stream),
+                "checkpoint copy");
+    }
 
     PassLaunch L;
     memset(&L, 0, sizeof(L));
@@ -363,6 +372,13 @@ uot_status run_sinkhorn(const uot_problem* p, const uot_options* o, const uot_ou
         }
         UOT_HIP(timed(K_FIN, [&] { return launch_finalize(F, stream); }), "column finalize");
         iters_run = t + 1;
+        if (ck > 0 && (t + 1) % ck == 0 && t + 1 < o->max_iter) {
+            double* slot = out->ckpt + (size_t)((t + 1) / ck) * 2 * p->m;
+            UOT_HIP(hipMemcpyAsync(slot, out->v, sizeof(double) * p->m, hipMemcpyDeviceToDevice, stream),
+                    "checkpoint copy");
+            UOT_HIP(hipMemcpyAsync(slot + p->m, wbuf, sizeof(double) * p->m, hipMemcpyDeviceToDevice, stream),
+                    "checkpoint copy");
+        }
         // Iteration t+1's first pass decides whether iteration t met tol, so a
         // stop is seen here one check later; the extra launches return at once.
         if (flag_host && (t + 1) % check_every == 0 && t + 1 < o->max_iter) {
@@ -422,6 +438,264 @@ uot_status run_sinkhorn(const uot_problem* p, const uot_options* o, const uot_ou
         }
         UOT_HIP(hipEventElapsedTime(&prof->loop_ms, ev[0], ev[evi - 1]), "hipEventElapsedTime");
     }
+    return UOT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Reverse pass driver
+// ---------------------------------------------------------------------------
+struct BwdPlan {
+    Plan F;                   // forward plan (recompute and the column pass)
+    int nc;                   // adjoint chunks per lane
+    int64_t rows_per_wg;
+    int32_t G;
+    int32_t dim;
+    int k, nseg;
+    size_t off_fwd, off_part, off_str, off_utr, off_wtr, off_vtr, off_useed, off_abar, off_gsum, off_gy,
+        off_bbar, off_cbar, off_wfin, off_avec, total;
+};
+
+uot_status make_bwd_plan(const uot_problem* p, const uot_options* o, int64_t dim, BwdPlan& B) {
+    uot_options fo = *o;
+    fo.fused = 1;
+    fo.persistent = 0;
+    uot_status st = make_plan(p, &fo, B.F);
+    if (st != UOT_OK) return st;
+    if (o->max_iter < 1) return fail(UOT_ERR_ARG, "the reverse pass needs max_iter >= 1");
+    if (o->checkpoint_every < 1) return fail(UOT_ERR_ARG, "the reverse pass needs checkpoint_every >= 1");
+    if (o->tol > 0.0) return fail(UOT_ERR_UNSUPPORTED, "the reverse pass differentiates a fixed iteration count (tol <= 0)");
+    if (dim != 0 && dim != 2 && dim != 3) return fail(UOT_ERR_UNSUPPORTED, "point dimension %lld (0, 2 or 3)", (long long)dim);
+    const int64_t nv = (p->m + B.F.vec - 1) / B.F.vec;
+    const int awg = adj_wg();
+    B.nc = (int)((nv + awg - 1) / awg);
+    if (B.nc == 3) B.nc = 4;
+    if (B.nc > adj_chunks_max(p->k_dtype))
+        return fail(UOT_ERR_UNSUPPORTED, "the reverse pass holds rows of up to %d columns",
+                    adj_chunks_max(p->k_dtype) * awg * B.F.vec);
+    int64_t target = p->n < 256 ? p->n : 256;
+    B.rows_per_wg = (p->n + target - 1) / target;
+    B.G = (int32_t)((p->n + B.rows_per_wg - 1) / B.rows_per_wg);
+    B.dim = (int32_t)dim;
+    B.k = o->checkpoint_every;
+    B.nseg = (o->max_iter + B.k - 1) / B.k;
+    const int64_t n = p->n, m = p->m;
+    const size_t d8 = sizeof(double);
+    const size_t acc = (p->k_dtype == UOT_F64) ? 8 : 4;
+    size_t off = 0;
+    B.off_fwd = off; off = align_up(off + B.F.total, kAlign);
+    B.off_part = off; off = align_up(off + acc * (size_t)B.G * B.F.ldp, kAlign);
+    B.off_str = off; off = align_up(off + d8 * (size_t)B.k * n, kAlign);
+    B.off_utr = off; off = align_up(off + d8 * (size_t)B.k * n, kAlign);
+    B.off_wtr = off; off = align_up(off + d8 * (size_t)B.k * m, kAlign);
+    B.off_vtr = off; off = align_up(off + d8 * (size_t)B.k * m, kAlign);
+    B.off_useed = off; off = align_up(off + d8 * n, kAlign);
+    B.off_abar = off; off = align_up(off + d8 * n, kAlign);
+    B.off_gsum = off; off = align_up(off + d8 * n, kAlign);
+    B.off_gy = off; off = align_up(off + d8 * n * (dim > 0 ? dim : 1), kAlign);
+    B.off_bbar = off; off = align_up(off + d8 * m, kAlign);
+    B.off_cbar = off; off = align_up(off + d8 * m, kAlign);
+    B.off_wfin = off; off = align_up(off + d8 * m, kAlign);
+    B.off_avec = off; off = align_up(off + d8 * m, kAlign);
+    B.total = off;
+    return UOT_OK;
+}
+
+uot_status run_backward(const uot_problem* p, const uot_options* o, const double* uT, const double* vT,
+                        const double* ckpt, const double* grad_loss, double* grad_a, double* grad_b,
+                        const double* x, const double* y, int64_t dim, double* grad_x, void* ws, size_t ws_bytes,
+                        hipStream_t stream) {
+    BwdPlan B;
+    uot_status st = make_bwd_plan(p, o, dim, B);
+    if (st != UOT_OK) return st;
+    if (!uT || !vT || !ckpt || !grad_loss) return fail(UOT_ERR_ARG, "u, v, ckpt and grad_loss are required");
+    if (grad_x && (dim == 0 || !x)) return fail(UOT_ERR_ARG, "grad_x needs x and dim > 0");
+    if (dim > 0 && !y) return fail(UOT_ERR_ARG, "dim > 0 needs the target points y");
+    if (ws_bytes < B.total || !ws) return fail(UOT_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", B.total, ws_bytes);
+    if (!aligned(ws, kAlign)) return fail(UOT_ERR_ALIGN, "workspace must be 256-byte aligned");
+    const Plan& P = B.F;
+    const int64_t n = p->n, m = p->m;
+    char* base = (char*)ws;
+    char* fw = base + B.off_fwd;
+    Ctrl* ctrl = (Ctrl*)(fw + P.off_ctrl);
+    double* cprev = (double*)(fw + P.off_cprev);
+    double* bp = (double*)(fw + P.off_bp);
+    void* fpart = fw + P.off_part;
+    double* str = (double*)(base + B.off_str);
+    double* utr = (double*)(base + B.off_utr);
+    double* wtr = (double*)(base + B.off_wtr);
+    double* vtr = (double*)(base + B.off_vtr);
+    double* useed = (double*)(base + B.off_useed);
+    double* abar = (double*)(base + B.off_abar);
+    double* gsum = (double*)(base + B.off_gsum);
+    double* gy = (double*)(base + B.off_gy);
+    double* bbar = (double*)(base + B.off_bbar);
+    double* cbar = (double*)(base + B.off_cbar);
+    double* wfin = (double*)(base + B.off_wfin);
+    double* avec = (double*)(base + B.off_avec);
+    const void* K = p->K;
+    int64_t ldk = p->ldk;
+    if (P.build_k) {
+        K = fw + P.off_k;
+        ldk = P.ldk_ws;
+        UOT_HIP(launch_kernel_build(p->C, p->ldc, n, m, p->eps, nullptr, nullptr, p->k_dtype, (void*)K, ldk, stream),
+                "kernel build");
+    }
+    UOT_HIP(launch_init(nullptr, 0, nullptr, nullptr, 0, nullptr, nullptr, ctrl, stream), "init");
+    const double fi = fi_of(p->eps, p->tau);
+    const int tau_inf = isinf(p->tau) ? 1 : 0;
+
+    // Forward pass parameters (recompute and the K^T u_T column pass).
+    PassLaunch L;
+    memset(&L, 0, sizeof(L));
+    L.K = K;
+    L.ldk = ldk;
+    L.n = n;
+    L.m = m;
+    L.rows_per_wg = P.rows_per_wg;
+    L.grid = P.G;
+    L.a = p->a;
+    L.partials = fpart;
+    L.ldp = P.ldp;
+    L.fi = fi;
+    L.fi_is_one = (fi == 1.0);
+    L.inv_eps = 1.0 / p->eps;
+    L.ctrl = ctrl;
+    L.ldv_bytes = P.ldv_bytes;
+    L.fin_blocks = finalize_blocks(m);
+    L.blockpart = bp;
+    FinLaunch F;
+    memset(&F, 0, sizeof(F));
+    F.partials = fpart;
+    F.ldp = P.ldp;
+    F.G = P.G;
+    F.m = m;
+    F.b = p->b;
+    F.cprev = cprev;
+    F.fi = fi;
+    F.fi_is_one = (fi == 1.0);
+    F.inv_eps = 1.0 / p->eps;
+    F.ctrl = ctrl;
+    F.blockpart = bp;
+    F.acc64 = P.acc64;
+
+    AdjLaunch A;
+    memset(&A, 0, sizeof(A));
+    A.K = K;
+    A.ldk = ldk;
+    A.n = n;
+    A.m = m;
+    A.rows_per_wg = B.rows_per_wg;
+    A.grid = B.G;
+    A.y = y;
+    A.a = p->a;
+    A.useed = useed;
+    A.abar = abar;
+    A.gsum = gsum;
+    A.gy = gy;
+    A.partials = base + B.off_part;
+    A.ldp = P.ldp;
+    A.fi = fi;
+    A.eps = p->eps;
+    A.tau = p->tau;
+    A.tau_inf = tau_inf;
+    AdjColLaunch Cc;
+    memset(&Cc, 0, sizeof(Cc));
+    Cc.ldp = P.ldp;
+    Cc.m = m;
+    Cc.b = p->b;
+    Cc.cbar = cbar;
+    Cc.bbar = bbar;
+    Cc.out = avec;
+    Cc.fi = fi;
+    Cc.eps = p->eps;
+    Cc.tau = p->tau;
+    Cc.tau_inf = tau_inf;
+
+    // 1. w_T = K^T u_T (forward column pass), then cbar, bbar and the seed's A = cbar v_T.
+    {
+        PassLaunch LC = L;
+        LC.u = (double*)uT;
+        UOT_HIP(launch_pass(P.k_dtype, P.acc64, MODE_COL, P.shape, LC, stream), "column pass");
+        AdjColLaunch C1 = Cc;
+        C1.partials = fpart;
+        C1.G = P.G;
+        C1.acc64 = P.acc64;
+        C1.mode = ADJ_COL_PREP;
+        C1.v = vT;
+        C1.w = wfin;
+        UOT_HIP(launch_adj_col(C1, stream), "adjoint columns");
+    }
+    // 2. seed pass, 3. vbar_T and wbar_T
+    {
+        AdjLaunch S = A;
+        S.A = avec;
+        S.B = vT;
+        S.u = uT;
+        UOT_HIP(launch_adj(p->k_dtype, B.nc, ADJ_SEED, (int)dim, S, stream), "adjoint seed pass");
+        AdjColLaunch C2 = Cc;
+        C2.partials = A.partials;
+        C2.G = B.G;
+        C2.acc64 = (p->k_dtype == UOT_F64);
+        C2.mode = ADJ_COL_SEED;
+        C2.v = vT;
+        C2.w = wfin;
+        UOT_HIP(launch_adj_col(C2, stream), "adjoint columns");
+    }
+    // 4. segments, newest first: recompute the forward iterates, then reverse.
+    const int T = o->max_iter;
+    for (int c = B.nseg - 1; c >= 0; --c) {
+        const int t0 = c * B.k;
+        const int len = std::min(B.k, T - t0);
+        const double* v0 = ckpt + (size_t)c * 2 * m;
+        const double* w0 = v0 + m;
+        for (int q = 0; q < len; ++q) {
+            PassLaunch LF = L;
+            LF.v = (q == 0) ? v0 : vtr + (size_t)(q - 1) * m;
+            LF.u = utr + (size_t)q * n;
+            LF.s_trace = str + (size_t)q * n;
+            UOT_HIP(launch_pass(P.k_dtype, P.acc64, MODE_FUSED, P.shape, LF, stream), "recompute pass");
+            FinLaunch FF = F;
+            FF.v = vtr + (size_t)q * m;
+            FF.w_out = wtr + (size_t)q * m;
+            UOT_HIP(launch_finalize(FF, stream), "recompute finalize");
+        }
+        for (int q = len - 1; q >= 0; --q) {
+            const int t = t0 + q + 1;
+            const double* vprev = (q == 0) ? v0 : vtr + (size_t)(q - 1) * m;
+            AdjLaunch S = A;
+            S.A = avec;
+            S.B = vprev;
+            S.u = utr + (size_t)q * n;
+            S.s = str + (size_t)q * n;
+            S.add_seed = (t == T) ? 1 : 0;
+            UOT_HIP(launch_adj(p->k_dtype, B.nc, ADJ_STEP, (int)dim, S, stream), "adjoint step pass");
+            if (t > 1) {
+                AdjColLaunch C3 = Cc;
+                C3.partials = A.partials;
+                C3.G = B.G;
+                C3.acc64 = (p->k_dtype == UOT_F64);
+                C3.mode = ADJ_COL_STEP;
+                C3.v = vprev;
+                C3.w = (double*)((q == 0) ? w0 : wtr + (size_t)(q - 1) * m);
+                UOT_HIP(launch_adj_col(C3, stream), "adjoint columns");
+            }
+        }
+    }
+    AdjFinish Fin;
+    memset(&Fin, 0, sizeof(Fin));
+    Fin.grad_loss = grad_loss;
+    Fin.abar = abar;
+    Fin.bbar = bbar;
+    Fin.gsum = gsum;
+    Fin.gy = gy;
+    Fin.x = x;
+    Fin.grad_a = grad_a;
+    Fin.grad_b = grad_b;
+    Fin.grad_x = grad_x;
+    Fin.n = n;
+    Fin.m = m;
+    Fin.dim = (int32_t)dim;
+    UOT_HIP(launch_adj_finish(Fin, stream), "adjoint finish");
     return UOT_OK;
 }
 
@@ -492,6 +766,20 @@ uot_status uot_sinkhorn_profiled(const uot_problem* prob, const uot_options* opt
                                  void* ws, size_t ws_bytes, void* stream, uot_profile* prof) {
     if (!prof) return fail(UOT_ERR_ARG, "prof must not be NULL");
     return run_sinkhorn(prob, opt, out, ws, ws_bytes, (hipStream_t)stream, prof);
+}
+
+size_t uot_sinkhorn_backward_workspace_size(const uot_problem* prob, const uot_options* opt, int64_t dim) {
+    BwdPlan B;
+    if (make_bwd_plan(prob, opt, dim, B) != UOT_OK) return 0;
+    return B.total;
+}
+
+uot_status uot_sinkhorn_backward(const uot_problem* prob, const uot_options* opt, const double* u, const double* v,
+                                 const double* ckpt, const double* grad_loss, double* grad_a, double* grad_b,
+                                 const double* x, const double* y, int64_t dim, double* grad_x, void* ws,
+                                 size_t ws_bytes, void* stream) {
+    return run_backward(prob, opt, u, v, ckpt, grad_loss, grad_a, grad_b, x, y, dim, grad_x, ws, ws_bytes,
+                        (hipStream_t)stream);
 }
 
 }  // extern "C"

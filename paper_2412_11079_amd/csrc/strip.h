@@ -1,0 +1,245 @@
+// One workgroup's streaming pass over a strip of rows of K (shared by the
+// forward pass kernels and the adjoint pass).
+#pragma once
+
+#include "uot_common.h"
+
+namespace uot {
+
+// Word 3 of a raw buffer resource on gfx9-class parts (untyped 32-bit data).
+constexpr int kBufferWord3 = 0x00020000;
+// Cache-policy bits of the K loads.
+// 2 = non-temporal: K is streamed once per pass and should not displace v,
+// the partials or other workgroups' lines in L2 / the memory-side cache.
+#ifndef UOT_K_LOAD_AUX
+#define UOT_K_LOAD_AUX 2
+#endif
+constexpr int kLoadAux = UOT_K_LOAD_AUX;
+
+// ---------------------------------------------------------------------------
+// One workgroup's streaming pass over its strip of rows.  Shared by the
+// per-iteration pass kernel and the persistent kernel.
+// ---------------------------------------------------------------------------
+template <typename KT, typename AT, int WG, int NC, int D, bool VLDS, int MODE>
+struct Strip {
+    using KV = KVec<KT>;
+    using Raw = typename KV::raw;
+    static constexpr int V = KV::N;
+    static constexpr int E = NC * V;
+    static constexpr int NW = WG / 64;
+    static constexpr bool kDot = (MODE != MODE_COL);
+    static constexpr bool kAcc = (MODE != MODE_ROW);
+    static constexpr bool kVreg = kDot && !VLDS;
+
+    __amdgpu_buffer_rsrc_t rsrc;
+    uint32_t row_bytes;
+    int64_t m;
+    int64_t r0;
+    int nrows;
+    bool ragged;
+    int64_t col[NC];
+    uint32_t voff[NC];
+    Raw buf[D][NC];
+    AT vv[kVreg ? E : 1];
+    AT acc[kAcc ? E : 1];
+
+    __device__ __forceinline__ void setup(const PassLaunch& L, int64_t r0_, int nrows_) {
+        m = L.m;
+        r0 = r0_;
+        nrows = nrows_;
+        row_bytes = (uint32_t)(L.ldk * (int64_t)sizeof(KT));
+        // Buffer resource over the strip: loads past its last row and the
+        // chunks of lanes beyond column m (offset set to the strip size) read 0.
+        const uint32_t strip_bytes = (uint32_t)((int64_t)nrows * L.ldk * (int64_t)sizeof(KT));
+        const KT* strip = (const KT*)L.K + r0 * L.ldk;
+        rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)strip, (short)0, (int)strip_bytes, kBufferWord3);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            col[c] = ((int64_t)c * WG + threadIdx.x) * V;
+            voff[c] = col[c] < m ? (uint32_t)(col[c] * (int64_t)sizeof(KT)) : strip_bytes;
+        }
+        ragged = (m % V) != 0;
+    }
+
+    template <int Q>
+    __device__ __forceinline__ void load_row(int k) {
+        const uint32_t soff = (uint32_t)k * row_bytes;
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            buf[Q][c] = __builtin_bit_cast(
+                Raw, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)voff[c], (int)soff, kLoadAux));
+    }
+
+    // Rows 0 .. D-2 in flight (issued before anything the pass waits on).
+    __device__ __forceinline__ void prime() {
+        if constexpr (D >= 2) load_row<0>(0);
+        if constexpr (D >= 3) load_row<1>(1);
+        if constexpr (D >= 4) load_row<2>(2);
+    }
+
+    __device__ __forceinline__ void load_v_regs(const double* v) {
+        if constexpr (kVreg) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    int64_t j = col[c] + e;
+                    vv[c * V + e] = (j < m) ? (AT)v[j] : (AT)0;
+                }
+        }
+    }
+
+    __device__ __forceinline__ void clear_acc() {
+#pragma unroll
+        for (int e = 0; e < (kAcc ? E : 1); ++e) acc[e] = (AT)0;
+    }
+
+    // One row: dot with v (FUSED/ROW/MARG), cross-wave reduction, scaling,
+    // accumulation of the column partials (FUSED/COL/MARG).
+    template <int Q>
+    __device__ __forceinline__ void process(const PassLaunch& L, int k, const AT* vl, const double* row_in,
+                                            const double* row_sh, double (*red)[NW], int& slot) {
+        const int tid = threadIdx.x;
+        const int lane = tid & 63;
+        const int wave = tid >> 6;
+        AT ur;
+        if constexpr (kDot) {
+            AT s = (AT)0;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                AT x[V];
+                unpack<AT>(buf[Q][c], x);
+                if (ragged) {
+#pragma unroll
+                    for (int e = 0; e < V; ++e)
+                        if (col[c] + e >= m) x[e] = (AT)0;
+                }
+                if constexpr (VLDS) {
+                    if (col[c] < m) {
+#pragma unroll
+                        for (int e = 0; e < V; ++e) s = fma(x[e], vl[col[c] + e], s);
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < V; ++e) s = fma(x[e], vv[c * V + e], s);
+                }
+            }
+            double d = wave_sum_f64((double)s);
+            if (lane == 0) red[slot][wave] = d;
+            __syncthreads();
+            // Every lane forms the row total in the same fixed order.
+            double tot = 0.0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) tot += red[slot][w];
+            slot ^= 1;
+            double uval;
+            if constexpr (MODE == MODE_MARG) {
+                uval = row_in[k];
+                if (tid == 0) L.s_out[r0 + k] = tot;
+            } else {
+                const double ai = row_in[k];
+                uval = scale_factor(ai, tot, L.fi, L.fi_is_one, row_sh[k]);
+                if (tid == 0) {
+                    L.u[r0 + k] = uval;
+                    if (L.s_trace) L.s_trace[r0 + k] = tot;
+                    if (ai > 0.0 && !(tot > 0.0)) atomicOr(&L.ctrl->flags, UOT_FLAG_ZERO_SUM);
+                    if (!isfinite(uval)) atomicOr(&L.ctrl->flags, UOT_FLAG_NONFINITE);
+                }
+            }
+            ur = (AT)uval;
+        } else {
+            ur = (AT)row_in[k];
+        }
+        if constexpr (kAcc) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                AT x[V];
+                unpack<AT>(buf[Q][c], x);
+#pragma unroll
+                for (int e = 0; e < V; ++e) acc[c * V + e] = fma(x[e], ur, acc[c * V + e]);
+            }
+        }
+    }
+
+    template <int Q>
+    __device__ __forceinline__ bool step(const PassLaunch& L, int k0, const AT* vl, const double* row_in,
+                                         const double* row_sh, double (*red)[NW], int& slot) {
+        const int k = k0 + Q;
+        if (k >= nrows) return false;
+        load_row<(Q + D - 1) % D>(k + D - 1);
+        process<Q>(L, k, vl, row_in, row_sh, red, slot);
+        return true;
+    }
+
+    // All rows of the strip; expects prime() to have been called.
+    __device__ __forceinline__ void stream(const PassLaunch& L, const AT* vl, const double* row_in,
+                                           const double* row_sh, double (*red)[NW]) {
+        int slot = 0;
+        for (int k0 = 0; k0 < nrows; k0 += D) {
+            if (!step<0>(L, k0, vl, row_in, row_sh, red, slot)) break;
+            if constexpr (D >= 2) if (!step<1 % D>(L, k0, vl, row_in, row_sh, red, slot)) break;
+            if constexpr (D >= 3) if (!step<2 % D>(L, k0, vl, row_in, row_sh, red, slot)) break;
+            if constexpr (D >= 4) if (!step<3 % D>(L, k0, vl, row_in, row_sh, red, slot)) break;
+        }
+    }
+
+    __device__ __forceinline__ void store_partials(AT* P) {
+        if constexpr (kAcc) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                if (col[c] >= m) continue;
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    // ldp is a multiple of 64 >= m, so the chunk lies inside the partial
+                    // row; streaming stores: the partials are read once, elsewhere.
+                    __builtin_nontemporal_store(acc[c * V + e], &P[col[c] + e]);
+                }
+            }
+        }
+    }
+};
+
+// Stage the strip's per-row inputs (a and the stabilised shift, or u) and,
+// for shapes that keep v in LDS, v itself.
+template <typename S, int MODE, bool VLDS, typename AT>
+__device__ __forceinline__ void stage_rows(const PassLaunch& L, int64_t r0, int nrows, double* row_in,
+                                           double* row_sh) {
+    for (int k = threadIdx.x; k < nrows; k += blockDim.x) {
+        if constexpr (MODE == MODE_FUSED || MODE == MODE_ROW) {
+            row_in[k] = L.a[r0 + k];
+            row_sh[k] = L.fpot ? -(1.0 - L.fi) * L.fpot[r0 + k] * L.inv_eps : 0.0;
+        } else {
+            row_in[k] = L.u[r0 + k];
+        }
+    }
+}
+
+template <int V, typename AT>
+__device__ __forceinline__ void stage_v(const double* v, int64_t m, AT* vl) {
+    const int64_t mv = (m + V - 1) / V * V;
+    for (int64_t j = threadIdx.x; j < mv; j += blockDim.x) vl[j] = (j < m) ? (AT)v[j] : (AT)0;
+}
+
+// Stopping test of the previous iteration (see PassLaunch): identical in
+// every workgroup.  Returns true when the loop is to stop.
+__device__ __forceinline__ bool stop_test(const PassLaunch& L, int64_t iter, double* err_sh) {
+    if (!(L.tol > 0.0) || iter <= 1) return false;
+    if ((threadIdx.x >> 6) == 0) {
+        double err = stop_error(L.blockpart, L.fin_blocks, threadIdx.x & 63);
+        if ((threadIdx.x & 63) == 0) *err_sh = err;
+    }
+    __syncthreads();
+    const double err = *err_sh;
+    __syncthreads();
+    if (err <= L.tol) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            L.ctrl->iters = iter - 1;
+            L.ctrl->err = err;
+            L.ctrl->done = 1;
+        }
+        return true;
+    }
+    return false;
+}
+
+}  // namespace uot

@@ -82,24 +82,42 @@ constexpr uint32_t kBarrierSpinLimit = 1u << 24;
 // ---------------------------------------------------------------------------
 // Cross-lane helpers (wave64).
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ double readlane_f64(double x, int lane) {
+    int lo = __double2loint(x), hi = __double2hiint(x);
+    lo = __builtin_amdgcn_readlane(lo, lane);
+    hi = __builtin_amdgcn_readlane(hi, lane);
+    return __hiloint2double(hi, lo);
+}
+
+// DPP move of a double (both halves with the same lane pattern).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+    int lo = __double2loint(x), hi = __double2hiint(x);
+    lo = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xf, 0xf, false);
+    hi = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wave; every lane returns the same bits.
+// Within each row of 16 lanes: partner exchanges (lane ^ 1, lane ^ 2 via
+// quad permutes, then the half-row and row mirrors, which pair each lane with
+// one holding the other 4- and 8-lane sum), so all 16 lanes of a row hold
+// the row sum; the four row sums are then read from lanes 0, 16, 32, 48 and
+// added in that order.  Must be called with all 64 lanes active.
 __device__ __forceinline__ double wave_sum_f64(double x) {
-    // Butterfly: every lane ends with the same, order-fixed sum.
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
-    return x;
+    x += dpp_f64<0xB1>(x);    // quad_perm [1,0,3,2]
+    x += dpp_f64<0x4E>(x);    // quad_perm [2,3,0,1]
+    x += dpp_f64<0x141>(x);   // row_half_mirror
+    x += dpp_f64<0x140>(x);   // row_mirror
+    double r0 = readlane_f64(x, 0), r1 = readlane_f64(x, 16);
+    double r2 = readlane_f64(x, 32), r3 = readlane_f64(x, 48);
+    return ((r0 + r1) + r2) + r3;
 }
 
 __device__ __forceinline__ double wave_max_f64(double x) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) x = fmax(x, __shfl_xor(x, off, 64));
     return x;
-}
-
-__device__ __forceinline__ double readlane_f64(double x, int lane) {
-    int lo = __double2loint(x), hi = __double2hiint(x);
-    lo = __builtin_amdgcn_readlane(lo, lane);
-    hi = __builtin_amdgcn_readlane(hi, lane);
-    return __hiloint2double(hi, lo);
 }
 
 __device__ __forceinline__ float readlane_f32(float x, int lane) {
@@ -171,6 +189,7 @@ struct PassLaunch {
     int32_t fin_blocks;
     const double* blockpart;   // 2 x fin_blocks: sum|c - c_prev|, sum|c| per block
     double tol;
+    double* s_trace;           // optional (FUSED/ROW): row sums K v written per row
 };
 
 struct PassShape {
@@ -223,6 +242,66 @@ struct PersistLaunch {
     int32_t fin_cols;         // columns finalized per workgroup (multiple of 4, <= workgroup size)
     int64_t scratch_bytes;    // LDS bytes before the row staging: max(v, finalize scratch)
 };
+// ---------------------------------------------------------------------------
+// Adjoint kernels (adj.hip).
+// ---------------------------------------------------------------------------
+enum AdjPhase { ADJ_SEED = 0, ADJ_STEP = 1 };
+struct AdjLaunch {
+    const void* K;
+    int64_t ldk;
+    int64_t n, m;
+    int64_t rows_per_wg;
+    int32_t grid;
+    const double* A;          // m: step: wbar_t; seed: cbar * v_T
+    const double* B;          // m: step: v_{t-1}; seed: v_T
+    const double* y;          // m x dim target points (dim > 0)
+    const double* u;          // n: u_t (step) / u_T (seed)
+    const double* s;          // n: s_t (step)
+    const double* a;          // n
+    double* useed;            // n: written by the seed pass, added at step T
+    int32_t add_seed;
+    double* abar;             // n
+    double* gsum;             // n: sum_j dL/dC_ij
+    double* gy;               // n x dim: sum_j dL/dC_ij y_j
+    void* partials;           // grid x ldp (AT)
+    int64_t ldp;
+    double fi, eps, tau;
+    int32_t tau_inf;
+};
+size_t adj_lds_bytes(int64_t rows_per_wg, int dim, int64_t m, int elem);
+int adj_chunks_max(int k_dtype);
+int adj_wg();
+hipError_t launch_adj(int k_dtype, int nc, int phase, int dim, const AdjLaunch& L, hipStream_t stream);
+
+enum AdjColMode { ADJ_COL_PREP = 0, ADJ_COL_SEED = 1, ADJ_COL_STEP = 2 };
+struct AdjColLaunch {
+    const void* partials;
+    int64_t ldp;
+    int32_t G;
+    int64_t m;
+    int32_t mode;
+    int32_t acc64;
+    const double* v;          // v_t of the step (v_T for PREP/SEED)
+    const double* b;
+    double* w;                // PREP writes K^T u_T; others read w_t
+    double* cbar;             // PREP writes, SEED reads
+    double* bbar;             // PREP writes, others accumulate
+    double* out;              // PREP: cbar * v; SEED/STEP: wbar for the next step
+    double fi, eps, tau;
+    int32_t tau_inf;
+};
+hipError_t launch_adj_col(const AdjColLaunch& C, hipStream_t stream);
+
+struct AdjFinish {
+    const double* grad_loss;
+    const double* abar; const double* bbar; const double* gsum; const double* gy;
+    const double* x;
+    double* grad_a; double* grad_b; double* grad_x;
+    int64_t n, m;
+    int32_t dim;
+};
+hipError_t launch_adj_finish(const AdjFinish& F, hipStream_t stream);
+
 // Largest co-resident grid for the shape (0 when the shape cannot run persistently).
 int persist_max_grid(int k_dtype, int acc64, int shape_idx, size_t lds);
 hipError_t launch_persist(int k_dtype, int acc64, int shape_idx, const PersistLaunch& P, size_t lds,
