@@ -28,7 +28,8 @@ sys.path.insert(0, ROOT)
 METRIC = "Sinkhorn iters/s + achieved HBM TB/s at N=M=16384 FP32; fwd+bwd ms"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_pass_headline_traffic.txt")
-PASS_SRC = os.path.join(ROOT, "paper_2412_11079_amd", "csrc", "pass.hip")
+# sources of the fused pass kernel: counter results are tied to their hash
+PASS_SRC = [os.path.join(ROOT, "paper_2412_11079_amd", "csrc", f) for f in ("pass.hip", "strip.h", "uot_common.h")]
 
 
 def parse():
@@ -42,14 +43,18 @@ def parse():
     p.add_argument("--tune", type=int, default=0)
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     p.add_argument("--no-plain", action="store_true", help="skip the plain two-pass comparison")
+    p.add_argument("--no-grad", action="store_true", help="skip the forward+backward timing")
     p.add_argument("--calib-copy", action="store_true",
                    help="only run a plain device copy of known size (counter calibration)")
     return p.parse_args()
 
 
 def src_hash() -> str:
-    with open(PASS_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in PASS_SRC:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def traffic_from_counters():
@@ -169,9 +174,56 @@ def main():
                         "pass_us": round(plain["pass_us"], 2),
                         "hbm_tb_s": round(nbytes / (plain["pass_us"] * 1e-6) / 1e12, 3),
                         "speedup_fused_over_plain": round(fused["iters_per_s"] / plain["iters_per_s"], 3)}
+    if not args.no_grad:
+        out["fwd_bwd"] = fwd_bwd(uot, workloads, torch, dev, args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)
+
+
+def fwd_bwd(uot, workloads, torch, dev, args):
+    """Differentiation workload (8192^2 FP32 K, 500 iterations, checkpoints
+    every 50): forward (cost, kernel, loop, objective) and reverse pass with
+    gradients for the source points, a and b, timed with events on the stream."""
+    prob = workloads.grad()
+    x = torch.from_numpy(prob.x).to(dev)
+    y = torch.from_numpy(prob.y).to(dev)
+    a = torch.from_numpy(prob.a).to(dev)
+    b = torch.from_numpy(prob.b).to(dev)
+    g = torch.ones((), dtype=torch.float64, device=dev)
+
+    def fwd():
+        C = uot.cost_from_points(x, y)
+        K = uot.kernel_from_cost(C, prob.eps, torch.float32)
+        del C
+        return uot.sinkhorn(a, b, K, eps=prob.eps, tau=prob.tau, max_iter=prob.max_iter,
+                            checkpoint_every=prob.checkpoint_every)
+
+    for _ in range(max(args.warmup, 1)):
+        r = fwd()
+        uot.sinkhorn_backward(r, g, x=x, y=y)
+    torch.cuda.synchronize()
+    reps = max(min(args.steps, 5), 1)
+    f_ms = b_ms = 0.0
+    for _ in range(reps):
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record()
+        r = fwd()
+        e1.record()
+        ga, gb, gx = uot.sinkhorn_backward(r, g, x=x, y=y)
+        e2.record()
+        torch.cuda.synchronize()
+        f_ms += e0.elapsed_time(e1)
+        b_ms += e1.elapsed_time(e2)
+    f_ms /= reps
+    b_ms /= reps
+    kb = prob.n * prob.m * 4
+    # forward: T passes; reverse: T recompute + T adjoint passes + 1 column + 1 seed pass
+    passes = prob.max_iter * 3 + 3
+    return {"workload": f"grad: N=M={prob.n} FP32 K, {prob.max_iter} iterations, checkpoints every "
+                        f"{prob.checkpoint_every}, gradients for x, a, b",
+            "fwd_ms": round(f_ms, 3), "bwd_ms": round(b_ms, 3), "fwd_bwd_ms": round(f_ms + b_ms, 3),
+            "k_passes": passes, "k_bytes_tb_s": round(passes * kb / ((f_ms + b_ms) * 1e-3) / 1e12, 3)}
 
 
 def cpu_baseline(prob):

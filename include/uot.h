@@ -100,6 +100,8 @@ typedef struct uot_problem {
     int64_t ldc;
     double eps;
     double tau;
+    double k_scale;           /* given K only: the kernel is k_scale * K (0 = 1); use 1/448 for an
+                                 FP8 K from uot_kernel_from_cost */
 } uot_problem;
 
 typedef struct uot_options {
@@ -108,7 +110,7 @@ typedef struct uot_options {
     double tol;               /* > 0: stop when the error is <= tol; <= 0: run exactly max_iter */
     int32_t fused;            /* 1: single pass over K per iteration; 0: plain row pass + column pass */
     int32_t accum;            /* uot_accum */
-    double absorb_log_threshold;  /* reserved, must be 0 */
+    double absorb_log_threshold;  /* > 0: log-domain absorption (needs C; see uot_sinkhorn); 0: off */
     int32_t checkpoint_every; /* k > 0: write v and K^T u every k iterations to outputs.ckpt
                                  (needs tol <= 0 and persistent = 0); 0 = none */
     int32_t tune;             /* 0: default launch shape; k > 0: use tuned shape index k-1 */
@@ -130,6 +132,8 @@ typedef struct uot_outputs {
     double* ckpt;             /* with options.checkpoint_every = k > 0: device buffer of
                                  (ceil(max_iter/k) + 1) x 2m doubles; slot c holds v and K^T u
                                  after iteration c*k (slot 0: the starting v) */
+    double* f;                /* optional: device n, eps * log(u_T) (finite where u_T overflows) */
+    double* g;                /* optional: device m, eps * log(v_T) */
 } uot_outputs;
 
 /* Per-kernel durations of one uot_sinkhorn_profiled call, measured with HIP
@@ -168,8 +172,11 @@ uot_status uot_cost_from_points(const double* x, const double* y, int64_t n, int
 /*
  * Gibbs kernel K_ij = exp((f_i + g_j - C_ij)/eps) (Section 2.1's matrix A,
  * built from its cost), evaluated in FP64 and rounded to nearest-even into
- * k_dtype (UOT_F64 or UOT_F32).  f, g: optional FP64 potentials (NULL = 0).
- * C: n x ldc FP64.  K: n x ldk output.
+ * k_dtype (F64, F32, BF16; FP8 stores RNE(448 K) saturated at 448, so pass
+ * k_scale = 1/448 with it).  f, g: optional FP64 potentials (NULL = 0).
+ * C: n x ldc FP64.  K: n x ldk output; padding columns [m, ldk) are 0.
+ * BF16 values below 2^-126 are stored as 0; FP8 keeps its subnormals
+ * (multiples of 2^-9), so only 448 K below 2^-10 becomes 0.
  * Errors: UOT_ERR_ARG, UOT_ERR_DTYPE, UOT_ERR_ALIGN.
  */
 uot_status uot_kernel_from_cost(const double* C, int64_t ldc, int64_t n, int64_t m,
@@ -192,16 +199,32 @@ size_t uot_sinkhorn_workspace_size(const uot_problem* prob, const uot_options* o
  * (KL~(x|y) = sum x log(x/y) - x + y; the KL terms are dropped for
  * tau = inf) in FP64 from O(n+m) quantities.
  *
- * K dtypes: UOT_F64, UOT_F32.  Scalings and all reductions across lanes
- * and workgroups are FP64 (opt->accum picks the per-lane type for FP32 K).
+ * K dtypes: UOT_F64, UOT_F32, UOT_BF16, UOT_FP8_E4M3 (BF16 and FP8: fused,
+ * FP32 lane arithmetic).  Scalings and all reductions across lanes and
+ * workgroups are FP64 (opt->accum picks the per-lane type for FP32 K).
  * Results are bitwise reproducible for a fixed problem and launch shape.
  * With tol > 0 the host synchronises on `stream` every check_every
  * iterations; with tol <= 0 the call only enqueues work.
  *
+ * Log-domain absorption (opt->absorb_log_threshold > 0; needs C): the state
+ * is (f, g, u, v) with totals u e^{f/eps}, v e^{g/eps}, and the stored
+ * kernel is Kt_ij = exp((f_i + g_j - C_ij)/eps).  Whenever Kt is built, f
+ * and g are normalised, f_i = min_j (C_ij - g_j) and then
+ * g_j = min_i (C_ij - f_i), so every row's and every column's largest entry
+ * is exactly 1 (u, v are rescaled to keep the totals).  The updates become
+ *     u = (a / (Kt v))^fi e^{-(1-fi) f/eps},  v = (b / (Kt^T u))^fi e^{-(1-fi) g/eps},
+ * the same iterates in exact arithmetic.  Every check_every iterations, if
+ * max |log u| or max |log v| exceeds the threshold, v is absorbed (g += eps
+ * log v, v = 1), f, g are normalised again and Kt is rebuilt from C.  Kt
+ * lives in the workspace in k_dtype (FP8: 448 Kt).  outputs->u, v then receive
+ * the totals (inf where they overflow FP64) and outputs->f, g the finite
+ * potentials eps log(total); info->absorptions counts the absorptions.
+ *
  * Errors: UOT_ERR_ARG (n or m < 1, NULL a/b/u/v, eps <= 0, tau <= 0,
- * max_iter < 0, neither K nor C), UOT_ERR_DTYPE, UOT_ERR_ALIGN,
- * UOT_ERR_WORKSPACE, UOT_ERR_UNSUPPORTED (m above the row length one
- * workgroup holds: 16384 FP32, 8192 FP64), UOT_ERR_HIP.
+ * max_iter < 0, neither K nor C, absorption without C), UOT_ERR_DTYPE,
+ * UOT_ERR_ALIGN, UOT_ERR_WORKSPACE, UOT_ERR_UNSUPPORTED (m above the row
+ * length one workgroup holds: 16384 FP32, 8192 FP64, 32768 BF16, 65536 FP8;
+ * combinations outside the envelope stated at each option), UOT_ERR_HIP.
  */
 uot_status uot_sinkhorn(const uot_problem* prob, const uot_options* opt,
                         const uot_outputs* out, void* ws, size_t ws_bytes, void* stream);
@@ -237,6 +260,15 @@ uot_status uot_sinkhorn_profiled(const uot_problem* prob, const uot_options* opt
  * Errors: UOT_ERR_ARG, UOT_ERR_UNSUPPORTED, UOT_ERR_WORKSPACE, UOT_ERR_ALIGN,
  * UOT_ERR_HIP.  Workspace: uot_sinkhorn_backward_workspace_size bytes.
  */
+/*
+ * Decode `count` stored kernel entries (a multiple of 16 bytes' worth) to
+ * FP32 exactly as the streaming passes read them, times k_scale.  For
+ * inspecting a stored K (e.g. checking the FP8 decoding).
+ * Errors: UOT_ERR_ARG, UOT_ERR_DTYPE, UOT_ERR_ALIGN, UOT_ERR_HIP.
+ */
+uot_status uot_kernel_to_f32(const void* K, int32_t k_dtype, int64_t count, double k_scale, float* out,
+                             void* stream);
+
 size_t uot_sinkhorn_backward_workspace_size(const uot_problem* prob, const uot_options* opt, int64_t dim);
 uot_status uot_sinkhorn_backward(const uot_problem* prob, const uot_options* opt,
                                  const double* u, const double* v, const double* ckpt,

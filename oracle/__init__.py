@@ -72,6 +72,13 @@ def _load():
         lib.orc_adjoint.restype = None
         lib.orc_grad_points_sqeuclid.argtypes = [_dp, _dp, _dp, _i64, _i64, _i64, _dp]
         lib.orc_grad_points_sqeuclid.restype = None
+        lib.orc_round_storage.argtypes = [_dp, _i64, ctypes.c_int, _dp]
+        lib.orc_round_storage.restype = None
+        lib.orc_sinkhorn_absorbed.argtypes = [_dp, _dp, _dp, _i64, _i64, ctypes.c_double,
+                                              ctypes.c_double, _i64, ctypes.c_double, _i64,
+                                              ctypes.c_int, ctypes.c_double, _dp, _dp, _dp, _dp,
+                                              _dp, ctypes.POINTER(_i64), _dp]
+        lib.orc_sinkhorn_absorbed.restype = _i64
         _lib = lib
     return _lib
 
@@ -220,6 +227,55 @@ def grad_points_sqeuclid(G, x, y) -> np.ndarray:
     gx = np.empty((n, d))
     _load().orc_grad_points_sqeuclid(_p(G), _p(x), _p(y), n, m, d, _p(gx))
     return gx
+
+
+_STORAGE_KINDS = {"bf16": 1, "e4m3": 2, "f32": 3}
+
+
+def round_storage(x, kind: str) -> np.ndarray:
+    """Values of non-negative ``x`` once stored as bfloat16 (``"bf16"``), OCP
+    E4M3FN (``"e4m3"``) or binary32 (``"f32"``), round to nearest even,
+    returned in FP64."""
+    x = _f64(x)
+    out = np.empty_like(x)
+    _load().orc_round_storage(_p(x), x.size, _STORAGE_KINDS[kind], _p(out))
+    return out
+
+
+@dataclass
+class AbsorbedResult:
+    f: np.ndarray          # potentials of the total scalings: u_tot = e^{f/eps}
+    g: np.ndarray
+    r: np.ndarray          # row marginal with the stored kernel
+    c: np.ndarray          # column marginal with the stored kernel
+    loss: float
+    absorptions: int
+    checks: np.ndarray     # compared maximum |log| at each check (0 elsewhere)
+
+
+def sinkhorn_absorbed(C, a, b, eps: float, tau: float, max_iter: int, threshold: float,
+                      check_every: int = 1, storage: Optional[str] = None,
+                      store_scale: float = 1.0) -> AbsorbedResult:
+    """Absorbed iteration with row- and column-normalised kernel, optionally
+    held in a narrow storage format (``None``, ``"f32"``, ``"bf16"`` or ``"e4m3"``)."""
+    C = _f64(C)
+    a = _f64(a)
+    b = _f64(b)
+    n, m = C.shape
+    f = np.empty(n)
+    g = np.empty(m)
+    r = np.empty(n)
+    c = np.empty(m)
+    loss = ctypes.c_double(0.0)
+    nabs = _i64(0)
+    checks = np.zeros(max(int(max_iter), 1))
+    kind = 0 if storage is None else _STORAGE_KINDS[storage]
+    _load().orc_sinkhorn_absorbed(_p(C), _p(a), _p(b), n, m, float(eps), float(tau), int(max_iter),
+                                  float(threshold), int(check_every), kind, float(store_scale),
+                                  _p(f), _p(g), _p(r), _p(c), ctypes.byref(loss), ctypes.byref(nabs),
+                                  _p(checks))
+    return AbsorbedResult(f=f, g=g, r=r, c=c, loss=float(loss.value), absorptions=int(nabs.value),
+                          checks=checks[:max_iter])
 
 
 def fi_exponent(eps: float, tau: float) -> float:

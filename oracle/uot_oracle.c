@@ -458,3 +458,168 @@ ORC_EXPORT void orc_grad_points_sqeuclid(const double* G, const double* x, const
         }
     }
 }
+
+/* ------------------------------------------------------------------ */
+/* Low-precision storage of the kernel                                  */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Value that a non-negative FP64 number takes once stored in a narrow
+ * format, returned as FP64 (kind 1: bfloat16, kind 2: OCP E4M3FN, kind 3:
+ * binary32 through the C conversion).  All round to nearest with ties to
+ * even; the first two are written from the format definitions:
+ *   bfloat16: 8 significant bits, exponent range of binary32; values below
+ *             the smallest normal 2^-126 are stored as 0 (no subnormals);
+ *   E4M3FN:   4 exponent bits (bias 7) and 3 fraction bits; normal values
+ *             (1 + k/8) 2^e for e = -6 .. 8, subnormals k 2^-9 (k = 0 .. 7),
+ *             largest finite 448; anything larger saturates to 448.
+ * x = m 2^e with m in [1, 2): the stored value is rint(m 2^(p-1)) 2^(e-p+1)
+ * with p significant bits (rint rounds ties to even in the default mode).
+ */
+ORC_EXPORT void orc_round_storage(const double* x, int64_t count, int kind, double* out) {
+    #pragma omp parallel for schedule(static)
+    for (int64_t t = 0; t < count; ++t) {
+        double xv = x[t];
+        double r;
+        if (!(xv > 0.0)) {
+            r = 0.0;
+        } else if (kind == 3) {
+            r = (double)(float)xv;
+        } else if (kind == 1) {
+            if (xv < ldexp(1.0, -126)) {
+                r = 0.0;
+            } else {
+                int e2;
+                double mfr = frexp(xv, &e2);            /* xv = mfr 2^e2, mfr in [0.5, 1) */
+                r = ldexp(rint(ldexp(mfr, 8)), e2 - 8);  /* 8 significant bits */
+            }
+        } else {
+            if (xv >= 448.0) {
+                r = 448.0;
+            } else if (xv < ldexp(1.0, -6)) {
+                r = ldexp(rint(ldexp(xv, 9)), -9);      /* subnormal grid k 2^-9 */
+            } else {
+                int e2;
+                double mfr = frexp(xv, &e2);
+                r = ldexp(rint(ldexp(mfr, 4)), e2 - 4);  /* 4 significant bits */
+                if (r > 448.0) r = 448.0;
+            }
+        }
+        out[t] = r;
+    }
+}
+
+/*
+ * Absorbed iteration with a normalised, optionally low-precision kernel.
+ *
+ * Same iterates as orc_sinkhorn_stabilized on (f, g, u, v), with two
+ * differences that define how a kernel of limited range and precision is
+ * kept usable:
+ *   - normalisation: whenever the kernel is (re)built, the potentials are
+ *     first set to   f_i = min_j (C_ij - g_j),   then   g_j = min_i (C_ij - f_i),
+ *     so every exponent (f_i + g_j - C_ij)/eps is <= 0 and every row and
+ *     every column of Kt reaches exactly 1; u and v are rescaled so that the
+ *     totals u e^{f/eps} and v e^{g/eps} do not change;
+ *   - storage: Kt is held as the value its entries take in the stored
+ *     format (kind 0: FP64 itself; 1: bfloat16; 2: E4M3FN of store_scale*Kt,
+ *     divided back by store_scale; 3: binary32), see orc_round_storage.
+ * Start: u = v = 1, f = g = 0, then normalise.  After iteration t (t =
+ * check_every, 2 check_every, ... and t < max_iter) the largest of
+ * |log u_i|, |log v_j| (over positive entries) is compared with threshold;
+ * above it, v is absorbed (g += eps log v, v = 1) and the kernel is
+ * normalised and rebuilt (u does not need absorbing: the next half-step
+ * recomputes it against the new f).
+ * Outputs: f_tot, g_tot = f + eps log u, g + eps log v (-inf where the
+ * scaling is 0); r = u * (Kt v), c = v * (Kt^T u) for the final scalings
+ * (the plan's marginals, with the stored kernel); *loss the objective from
+ * those (the identity form of orc_loss_identity on log scalings);
+ * *absorptions the count; checks (optional, length max_iter) the compared
+ * maximum at each check (0 elsewhere).  Returns iterations.
+ */
+ORC_EXPORT int64_t orc_sinkhorn_absorbed(const double* C, const double* a, const double* b,
+                                         int64_t n, int64_t m, double eps, double tau,
+                                         int64_t max_iter, double threshold, int64_t check_every,
+                                         int kind, double store_scale,
+                                         double* f_tot, double* g_tot, double* r, double* c,
+                                         double* loss, int64_t* absorptions, double* checks) {
+    double fi = orc_fi(eps, tau);
+    double* Kt = (double*)malloc(sizeof(double) * (size_t)(n * m));
+    double* f = (double*)malloc(sizeof(double) * (size_t)n);
+    double* g = (double*)malloc(sizeof(double) * (size_t)m);
+    double* u = (double*)malloc(sizeof(double) * (size_t)n);
+    double* v = (double*)malloc(sizeof(double) * (size_t)m);
+    double* s = (double*)malloc(sizeof(double) * (size_t)n);
+    double* w = (double*)malloc(sizeof(double) * (size_t)m);
+    for (int64_t i = 0; i < n; ++i) { f[i] = 0.0; u[i] = 1.0; }
+    for (int64_t j = 0; j < m; ++j) { g[j] = 0.0; v[j] = 1.0; }
+    if (checks) for (int64_t t = 0; t < max_iter; ++t) checks[t] = 0.0;
+    int64_t nabs = 0;
+    for (int64_t t = 0; t <= max_iter; ++t) {
+        int rebuild = (t == 0);
+        if (t > 0 && threshold > 0.0 && t % check_every == 0 && t < max_iter) {
+            double mx = 0.0;
+            for (int64_t i = 0; i < n; ++i) if (u[i] > 0.0 && fabs(log(u[i])) > mx) mx = fabs(log(u[i]));
+            for (int64_t j = 0; j < m; ++j) if (v[j] > 0.0 && fabs(log(v[j])) > mx) mx = fabs(log(v[j]));
+            if (checks) checks[t - 1] = mx;
+            if (mx > threshold) {
+                for (int64_t j = 0; j < m; ++j) if (v[j] > 0.0) { g[j] += eps * log(v[j]); v[j] = 1.0; }
+                rebuild = 1;
+                ++nabs;
+            }
+        }
+        if (rebuild) {
+            /* normalise: new f from the current g, then new g from the new f */
+            for (int64_t i = 0; i < n; ++i) {
+                double mn = INFINITY;
+                for (int64_t j = 0; j < m; ++j) if (C[i * m + j] - g[j] < mn) mn = C[i * m + j] - g[j];
+                if (u[i] > 0.0) u[i] = exp(log(u[i]) + (f[i] - mn) / eps);
+                f[i] = mn;
+            }
+            for (int64_t j = 0; j < m; ++j) {
+                double mn = INFINITY;
+                for (int64_t i = 0; i < n; ++i) if (C[i * m + j] - f[i] < mn) mn = C[i * m + j] - f[i];
+                if (v[j] > 0.0) v[j] = exp(log(v[j]) + (g[j] - mn) / eps);
+                g[j] = mn;
+            }
+            orc_kernel(C, n, m, eps, f, g, Kt);
+            if (kind == 1 || kind == 3) {
+                orc_round_storage(Kt, n * m, kind, Kt);
+            } else if (kind == 2) {
+                for (int64_t k = 0; k < n * m; ++k) Kt[k] *= store_scale;
+                orc_round_storage(Kt, n * m, 2, Kt);
+                for (int64_t k = 0; k < n * m; ++k) Kt[k] /= store_scale;
+            }
+        }
+        if (t == max_iter) break;
+        orc_Kv(Kt, v, n, m, s);
+        for (int64_t i = 0; i < n; ++i)
+            u[i] = (a[i] == 0.0) ? 0.0 : pow(a[i] / s[i], fi) * exp(-(1.0 - fi) * f[i] / eps);
+        orc_KTu(Kt, u, n, m, w);
+        for (int64_t j = 0; j < m; ++j)
+            v[j] = (b[j] == 0.0) ? 0.0 : pow(b[j] / w[j], fi) * exp(-(1.0 - fi) * g[j] / eps);
+    }
+    orc_Kv(Kt, v, n, m, s);
+    orc_KTu(Kt, u, n, m, w);
+    double sr = 0.0, sc = 0.0, mass = 0.0, kr = 0.0, kc = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        r[i] = u[i] * s[i];
+        f_tot[i] = (u[i] > 0.0) ? f[i] + eps * log(u[i]) : -INFINITY;
+        if (r[i] > 0.0) sr += r[i] * (f_tot[i] / eps);
+        mass += r[i];
+    }
+    for (int64_t j = 0; j < m; ++j) {
+        c[j] = v[j] * w[j];
+        g_tot[j] = (v[j] > 0.0) ? g[j] + eps * log(v[j]) : -INFINITY;
+        if (c[j] > 0.0) sc += c[j] * (g_tot[j] / eps);
+    }
+    double L = eps * (sr + sc - mass);
+    if (!isinf(tau)) {
+        for (int64_t i = 0; i < n; ++i) kr += orc_kl_term(r[i], a[i]);
+        for (int64_t j = 0; j < m; ++j) kc += orc_kl_term(c[j], b[j]);
+        L += tau * (kr + kc);
+    }
+    *loss = L;
+    if (absorptions) *absorptions = nabs;
+    free(Kt); free(f); free(g); free(u); free(v); free(s); free(w);
+    return max_iter;
+}

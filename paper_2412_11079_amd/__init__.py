@@ -18,10 +18,13 @@ from ._lib import (UOT_ACC_F32, UOT_ACC_F64, UOT_BF16, UOT_COST_COSINE, UOT_COST
                    UOT_FLAG_NONFINITE, UOT_FLAG_NOT_CONVERGED, UOT_FLAG_ZERO_SUM, UOT_FP8_E4M3, UOTError)
 
 __all__ = ["sinkhorn", "sinkhorn_backward", "UOTLoss", "uot_loss", "cost_from_points", "kernel_from_cost",
+           "kernel_to_f32",
            "SinkhornResult", "UOTError", "lib_path",
            "UOT_F64", "UOT_F32", "UOT_BF16", "UOT_FP8_E4M3", "UOT_COST_SQEUCLID", "UOT_COST_COSINE"]
 
-_DTYPES = {torch.float64: UOT_F64, torch.float32: UOT_F32}
+_DTYPES = {torch.float64: UOT_F64, torch.float32: UOT_F32, torch.bfloat16: UOT_BF16,
+           torch.float8_e4m3fn: UOT_FP8_E4M3}
+FP8_STORE_SCALE = 448.0   # an FP8 kernel from kernel_from_cost holds 448 * K
 _ELEM = {UOT_F64: 8, UOT_F32: 4, UOT_BF16: 2, UOT_FP8_E4M3: 1}
 
 
@@ -89,6 +92,18 @@ def kernel_from_cost(C: torch.Tensor, eps: float, dtype: torch.dtype = torch.flo
     return K
 
 
+def kernel_to_f32(K: torch.Tensor, scale: float = 1.0) -> torch.Tensor:
+    """Decode a stored kernel (any supported dtype, contiguous, a multiple of
+    16 bytes) to FP32 exactly as the streaming passes read it, times scale."""
+    if K.dtype not in _DTYPES:
+        raise ValueError(f"unsupported K dtype {K.dtype}")
+    K = K.contiguous()
+    out = torch.empty(K.shape, dtype=torch.float32, device=K.device)
+    _lib.check(_lib.lib().uot_kernel_to_f32(_ptr(K), _DTYPES[K.dtype], K.numel(), float(scale), _ptr(out),
+                                            _stream(K.device)))
+    return out
+
+
 @dataclass
 class SinkhornResult:
     u: torch.Tensor
@@ -98,6 +113,8 @@ class SinkhornResult:
     loss: torch.Tensor            # device FP64 scalar
     info_raw: torch.Tensor        # device bytes of uot_info
     profile: Optional[dict] = None
+    f: Optional[torch.Tensor] = None    # eps log u (finite where u overflows)
+    g: Optional[torch.Tensor] = None    # eps log v
 
     def info(self) -> dict:
         """Synchronises and decodes the device-resident report."""
@@ -127,6 +144,7 @@ def _problem(a, b, K, C, m_logical, eps, tau, device):
         prob.k_dtype = _DTYPES[K.dtype]
         prob.K = K.data_ptr()
         prob.ldk = ldk
+        prob.k_scale = 1.0 / FP8_STORE_SCALE if K.dtype == torch.float8_e4m3fn else 1.0
     else:
         prob.k_dtype = UOT_F32
         prob.K = None
@@ -146,7 +164,8 @@ def sinkhorn(a: torch.Tensor, b: torch.Tensor, K: Optional[torch.Tensor] = None,
              fused: bool = True, accum: str = "f32", check_every: int = 1, tune: int = 0,
              k_dtype: Optional[torch.dtype] = None, u0: Optional[torch.Tensor] = None,
              v0: Optional[torch.Tensor] = None, persistent: bool = False,
-             checkpoint_every: int = 0, profile: bool = False) -> SinkhornResult:
+             checkpoint_every: int = 0, absorb_log_threshold: float = 0.0,
+             profile: bool = False) -> SinkhornResult:
     """UOT Sinkhorn scaling loop on the GPU (see include/uot.h, uot_sinkhorn).
 
     ``K`` is an (n, ldk) FP32/FP64 kernel (as returned by kernel_from_cost);
@@ -167,7 +186,7 @@ def sinkhorn(a: torch.Tensor, b: torch.Tensor, K: Optional[torch.Tensor] = None,
     opt.tol = float(tol)
     opt.fused = 1 if fused else 0
     opt.accum = UOT_ACC_F64 if accum == "f64" else UOT_ACC_F32
-    opt.absorb_log_threshold = 0.0
+    opt.absorb_log_threshold = float(absorb_log_threshold)
     opt.checkpoint_every = int(checkpoint_every)
     opt.tune = int(tune)
     opt.u0 = None if u0 is None else _vec64(u0, "u0", n, device).data_ptr()
@@ -188,8 +207,10 @@ def sinkhorn(a: torch.Tensor, b: torch.Tensor, K: Optional[torch.Tensor] = None,
     if checkpoint_every > 0:
         slots = (int(max_iter) + int(checkpoint_every) - 1) // int(checkpoint_every) + 1
         ckpt = torch.zeros(slots * 2 * m, dtype=torch.float64, device=device)
+    fpot = torch.empty(n, dtype=torch.float64, device=device)
+    gpot = torch.empty(m, dtype=torch.float64, device=device)
     out = _lib.Outputs(u.data_ptr(), v.data_ptr(), r.data_ptr(), c.data_ptr(), loss.data_ptr(), info.data_ptr(),
-                       None if ckpt is None else ckpt.data_ptr())
+                       None if ckpt is None else ckpt.data_ptr(), fpot.data_ptr(), gpot.data_ptr())
     prof = None
     if profile:
         p = _lib.Profile()
@@ -199,7 +220,7 @@ def sinkhorn(a: torch.Tensor, b: torch.Tensor, K: Optional[torch.Tensor] = None,
     else:
         _lib.check(L.uot_sinkhorn(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(out), _ptr(ws), ws.numel(),
                                   _stream(device)))
-    res = SinkhornResult(u=u, v=v, r=r, c=c, loss=loss, info_raw=info, profile=prof)
+    res = SinkhornResult(u=u, v=v, r=r, c=c, loss=loss, info_raw=info, profile=prof, f=fpot, g=gpot)
     res._keepalive = (ws, K, C, a, b)  # buffers must outlive the enqueued work
     res._problem = prob
     res._options = opt

@@ -26,7 +26,7 @@ class Info(ctypes.Structure):
 
 class Problem(ctypes.Structure):
     _fields_ = [("n", _i64), ("m", _i64), ("a", _vp), ("b", _vp), ("k_dtype", _i32), ("K", _vp),
-                ("ldk", _i64), ("C", _vp), ("ldc", _i64), ("eps", _dbl), ("tau", _dbl)]
+                ("ldk", _i64), ("C", _vp), ("ldc", _i64), ("eps", _dbl), ("tau", _dbl), ("k_scale", _dbl)]
 
 
 class Options(ctypes.Structure):
@@ -36,7 +36,8 @@ class Options(ctypes.Structure):
 
 
 class Outputs(ctypes.Structure):
-    _fields_ = [("u", _vp), ("v", _vp), ("r", _vp), ("c", _vp), ("loss", _vp), ("info", _vp), ("ckpt", _vp)]
+    _fields_ = [("u", _vp), ("v", _vp), ("r", _vp), ("c", _vp), ("loss", _vp), ("info", _vp), ("ckpt", _vp),
+                ("f", _vp), ("g", _vp)]
 
 
 class Profile(ctypes.Structure):
@@ -59,6 +60,7 @@ SIGNATURES = {
                      _i32),
     "uot_sinkhorn_profiled": ([ctypes.POINTER(Problem), ctypes.POINTER(Options), ctypes.POINTER(Outputs), _vp,
                                _sz, _vp, ctypes.POINTER(Profile)], _i32),
+    "uot_kernel_to_f32": ([_vp, _i32, _i64, _dbl, _vp, _vp], _i32),
     "uot_sinkhorn_backward_workspace_size": ([ctypes.POINTER(Problem), ctypes.POINTER(Options), _i64], _sz),
     "uot_sinkhorn_backward": ([ctypes.POINTER(Problem), ctypes.POINTER(Options), _vp, _vp, _vp, _vp, _vp, _vp,
                                _vp, _vp, _i64, _vp, _vp, _sz, _vp], _i32),

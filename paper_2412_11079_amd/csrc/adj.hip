@@ -113,7 +113,7 @@ __global__ __launch_bounds__(WG) void adj_kernel(AdjLaunch L) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             AT x[V];
-            unpack<AT>(b[c], x);
+            Unpack<KT, AT>::run(b[c], x);
             if (st.ragged) {
 #pragma unroll
                 for (int e = 0; e < V; ++e)
@@ -205,7 +205,7 @@ __global__ __launch_bounds__(WG) void adj_kernel(AdjLaunch L) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             AT x[V];
-            unpack<AT>(b[c], x);
+            Unpack<KT, AT>::run(b[c], x);
 #pragma unroll
             for (int e = 0; e < V; ++e) st.acc[c * V + e] = fma(x[e], qa, st.acc[c * V + e]);
         }

@@ -66,6 +66,12 @@ uint32_t* pinned_flag() {
     return g_pinned;
 }
 
+// Two doubles of the same pinned allocation, for the absorption check.
+double* pinned_vals() {
+    uint32_t* p = pinned_flag();
+    return p ? (double*)(p + 4) : nullptr;
+}
+
 // Event pool for profiled runs (grown on demand, kept for the process).
 std::mutex g_ev_mu;
 std::vector<hipEvent_t> g_events;
@@ -99,8 +105,9 @@ struct Plan {
     int64_t scratch_bytes;  // persistent: LDS before the row strips
     int32_t fin_blocks;   // blocks that write stopping-test sums
     bool build_k;
+    bool stab;            // log-domain absorption (state u, v, f, g in the workspace)
     // workspace offsets
-    size_t off_ctrl, off_cprev, off_w, off_s, off_bp, off_part, off_k, total;
+    size_t off_ctrl, off_cprev, off_w, off_s, off_bp, off_part, off_k, off_stab, total;
 };
 
 uot_status check_problem(const uot_problem* p, const uot_options* o) {
@@ -111,13 +118,20 @@ uot_status check_problem(const uot_problem* p, const uot_options* o) {
     if (!(p->eps > 0.0) || !isfinite(p->eps)) return fail(UOT_ERR_ARG, "eps must be finite and > 0");
     if (!(p->tau > 0.0)) return fail(UOT_ERR_ARG, "tau must be > 0 (or +inf)");
     if (o->max_iter < 0) return fail(UOT_ERR_ARG, "max_iter must be >= 0");
-    if (o->absorb_log_threshold != 0.0)
-        return fail(UOT_ERR_UNSUPPORTED, "log-domain absorption is not available in this entry point");
+    if (o->absorb_log_threshold < 0.0 || !(o->absorb_log_threshold == o->absorb_log_threshold))
+        return fail(UOT_ERR_ARG, "absorb_log_threshold must be >= 0");
+    const bool stab = o->absorb_log_threshold > 0.0;
+    if (stab && !p->C) return fail(UOT_ERR_ARG, "log-domain absorption rebuilds K from C: C is required");
+    if (stab && (o->persistent || o->checkpoint_every > 0))
+        return fail(UOT_ERR_UNSUPPORTED, "log-domain absorption runs with per-iteration launches and no checkpoints");
     if (o->checkpoint_every < 0) return fail(UOT_ERR_ARG, "checkpoint_every must be >= 0");
     if (o->checkpoint_every > 0 && (o->tol > 0.0 || o->persistent))
         return fail(UOT_ERR_UNSUPPORTED, "checkpoints need a fixed iteration count (tol <= 0) and per-iteration launches");
-    if (p->k_dtype != UOT_F64 && p->k_dtype != UOT_F32)
-        return fail(UOT_ERR_DTYPE, "K dtype %d not supported (FP64, FP32)", (int)p->k_dtype);
+    if (p->k_dtype != UOT_F64 && p->k_dtype != UOT_F32 && p->k_dtype != UOT_BF16 && p->k_dtype != UOT_FP8_E4M3)
+        return fail(UOT_ERR_DTYPE, "K dtype %d not supported", (int)p->k_dtype);
+    if ((p->k_dtype == UOT_BF16 || p->k_dtype == UOT_FP8_E4M3) && (!o->fused || o->persistent))
+        return fail(UOT_ERR_UNSUPPORTED, "BF16 and FP8 K run the fused per-iteration pass only");
+    if (!(p->k_scale >= 0.0) || !isfinite(p->k_scale)) return fail(UOT_ERR_ARG, "k_scale must be finite and >= 0");
     const int es = elem_size(p->k_dtype);
     const int vec = 16 / es;
     if (p->K) {
@@ -156,7 +170,7 @@ uot_status make_plan(const uot_problem* p, const uot_options* o, Plan& P) {
     uot_status st = check_problem(p, o);
     if (st != UOT_OK) return st;
     P.k_dtype = p->k_dtype;
-    P.acc64 = (p->k_dtype == UOT_F64) || (o->accum == UOT_ACC_F64);
+    P.acc64 = (p->k_dtype == UOT_F64) || (p->k_dtype == UOT_F32 && o->accum == UOT_ACC_F64);
     P.vec = 16 / elem_size(p->k_dtype);
     const int64_t nv = (p->m + P.vec - 1) / P.vec;
     if (o->tune > 0) {
@@ -204,7 +218,8 @@ uot_status make_plan(const uot_problem* p, const uot_options* o, Plan& P) {
     }
     if ((int64_t)P.lds_bytes > max_lds_bytes())
         return fail(UOT_ERR_UNSUPPORTED, "launch shape %d needs %zu bytes of LDS", P.shape, P.lds_bytes);
-    P.build_k = (p->K == nullptr);
+    P.stab = o->absorb_log_threshold > 0.0;
+    P.build_k = (p->K == nullptr) || P.stab;
     P.ldk_ws = round_up(p->m, 64);
     const size_t acc_size = P.acc64 ? 8 : 4;
     size_t off = 0;
@@ -217,6 +232,8 @@ uot_status make_plan(const uot_problem* p, const uot_options* o, Plan& P) {
     P.off_part = off; off = align_up(off + acc_size * (size_t)P.G * P.ldp, kAlign);
     P.off_k = off;
     if (P.build_k) off = align_up(off + (size_t)elem_size(p->k_dtype) * p->n * P.ldk_ws, kAlign);
+    P.off_stab = off;
+    if (P.stab) off = align_up(off + sizeof(double) * (2 * (size_t)p->n + 3 * (size_t)p->m + 4), kAlign);
     P.total = off;
     return UOT_OK;
 }
@@ -248,16 +265,49 @@ uot_status run_sinkhorn(const uot_problem* p, const uot_options* o, const uot_ou
     void* part = base + P.off_part;
     const void* K = p->K;
     int64_t ldk = p->ldk;
+    // FP8 stores 448 K (its largest finite value maps to the row maximum 1).
+    const double store_scale = (p->k_dtype == UOT_FP8_E4M3) ? 448.0 : 1.0;
+    double k_scale = (p->K && p->k_scale > 0.0) ? p->k_scale : 1.0;
     if (P.build_k) {
         K = base + P.off_k;
         ldk = P.ldk_ws;
-        UOT_HIP(launch_kernel_build(p->C, p->ldc, p->n, p->m, p->eps, nullptr, nullptr, p->k_dtype,
-                                    (void*)K, ldk, stream),
-                "kernel build");
+        k_scale = 1.0 / store_scale;
     }
+    // Scaling state: the outputs themselves, or (with absorption) workspace
+    // vectors u, v next to the potentials f, g; the outputs then get the totals.
+    double* su = out->u;
+    double* sv = out->v;
+    double* fpot = nullptr;
+    double* gpot = nullptr;
+    double* absorb_vals = nullptr;
+    double* gmin_scratch = nullptr;
+    if (P.stab) {
+        double* sb = (double*)(base + P.off_stab);
+        su = sb;
+        sv = su + p->n;
+        fpot = sv + p->m;
+        gpot = fpot + p->n;
+        absorb_vals = gpot + p->m;
+        gmin_scratch = absorb_vals + 4;
+    }
+    if (P.build_k && !P.stab)
+        UOT_HIP(launch_kernel_build(p->C, p->ldc, p->n, p->m, p->eps, nullptr, nullptr, p->k_dtype, (void*)K, ldk,
+                                    store_scale, stream),
+                "kernel build");
 
     const double fi = fi_of(p->eps, p->tau);
-    UOT_HIP(launch_init(out->u, p->n, o->u0, out->v, p->m, o->v0, cprev, ctrl, stream), "init");
+    UOT_HIP(launch_init(su, p->n, o->u0, sv, p->m, o->v0, cprev, ctrl, stream), "init");
+    int32_t absorptions = 0;
+    double* host_vals = nullptr;
+    if (P.stab) {
+        // g = 0 (zeroed through the init kernel's cprev path is not available: reuse it on g)
+        UOT_HIP(launch_init(nullptr, 0, nullptr, nullptr, p->m, nullptr, gpot, ctrl, stream), "init");
+        UOT_HIP(launch_rebuild(p->C, p->ldc, p->n, p->m, p->eps, fpot, gpot, su, sv, gmin_scratch, p->k_dtype,
+                               (void*)K, ldk, store_scale, 1, stream),
+                "kernel rebuild");
+        host_vals = pinned_vals();
+        if (!host_vals) return hip_fail(g_pinned_err, "hipHostMalloc");
+    }
     // Checkpoint slot c holds v and K^T u after iteration c*k (slot 0: the start v).
     const int ck = o->checkpoint_every;
     if (ck > 0) {
@@ -274,19 +324,20 @@ uot_status run_sinkhorn(const uot_problem* p, const uot_options* o, const uot_ou
     L.m = p->m;
     L.rows_per_wg = P.rows_per_wg;
     L.grid = P.G;
-    L.v = out->v;
+    L.v = sv;
     L.a = p->a;
-    L.u = out->u;
+    L.u = su;
     L.s_out = sbuf;
     L.partials = part;
     L.ldp = P.ldp;
     L.fi = fi;
     L.fi_is_one = (fi == 1.0);
-    L.fpot = nullptr;
+    L.fpot = fpot;
     L.inv_eps = 1.0 / p->eps;
     L.ctrl = ctrl;
     L.check_done = 1;
     L.ldv_bytes = P.ldv_bytes;
+    L.k_scale = k_scale;
 
     FinLaunch F;
     memset(&F, 0, sizeof(F));
@@ -295,9 +346,11 @@ uot_status run_sinkhorn(const uot_problem* p, const uot_options* o, const uot_ou
     F.G = P.G;
     F.m = p->m;
     F.b = p->b;
-    F.v = out->v;
+    F.v = sv;
     F.w_out = wbuf;
     F.cprev = cprev;
+    F.gpot = gpot;
+    F.k_scale = k_scale;
     F.fi = fi;
     F.fi_is_one = (fi == 1.0);
     F.inv_eps = 1.0 / p->eps;
@@ -372,6 +425,21 @@ uot_status run_sinkhorn(const uot_problem* p, const uot_options* o, const uot_ou
         }
         UOT_HIP(timed(K_FIN, [&] { return launch_finalize(F, stream); }), "column finalize");
         iters_run = t + 1;
+        if (P.stab && (t + 1) % check_every == 0 && t + 1 < o->max_iter) {
+            // Absorb when a scaling's log leaves [-threshold, threshold]: v goes
+            // into g, then f and Kt are rebuilt from C (u keeps its total).
+            UOT_HIP(launch_absorb_check(su, p->n, sv, p->m, absorb_vals, stream), "absorb check");
+            UOT_HIP(hipMemcpyAsync(host_vals, absorb_vals, 2 * sizeof(double), hipMemcpyDeviceToHost, stream),
+                    "absorb copy");
+            UOT_HIP(hipStreamSynchronize(stream), "absorb sync");
+            if (host_vals[0] > o->absorb_log_threshold || host_vals[1] > o->absorb_log_threshold) {
+                UOT_HIP(launch_absorb_apply(sv, gpot, p->m, p->eps, stream), "absorb");
+                UOT_HIP(launch_rebuild(p->C, p->ldc, p->n, p->m, p->eps, fpot, gpot, su, sv, gmin_scratch,
+                                       p->k_dtype, (void*)K, ldk, store_scale, 0, stream),
+                        "kernel rebuild");
+                ++absorptions;
+            }
+        }
         if (ck > 0 && (t + 1) % ck == 0 && t + 1 < o->max_iter) {
             double* slot = out->ckpt + (size_t)((t + 1) / ck) * 2 * p->m;
             UOT_HIP(hipMemcpyAsync(slot, out->v, sizeof(double) * p->m, hipMemcpyDeviceToDevice, stream),
@@ -402,8 +470,8 @@ uot_status run_sinkhorn(const uot_problem* p, const uot_options* o, const uot_ou
 
     ObjLaunch O;
     memset(&O, 0, sizeof(O));
-    O.u = out->u;
-    O.v = out->v;
+    O.u = su;
+    O.v = sv;
     O.s = sbuf;
     O.w = wbuf;
     O.a = p->a;
@@ -420,6 +488,13 @@ uot_status run_sinkhorn(const uot_problem* p, const uot_options* o, const uot_ou
     O.ctrl = ctrl;
     O.tol = o->tol;
     O.iters_run = iters_run;
+    O.fpot = fpot;
+    O.gpot = gpot;
+    O.f_out = out->f;
+    O.g_out = out->g;
+    O.u_tot = P.stab ? out->u : nullptr;
+    O.v_tot = P.stab ? out->v : nullptr;
+    O.absorptions = absorptions;
     O.blockpart = bp;
     O.fin_blocks = P.fin_blocks;
     UOT_HIP(launch_objective(O, stream), "objective");
@@ -464,6 +539,8 @@ uot_status make_bwd_plan(const uot_problem* p, const uot_options* o, int64_t dim
     if (o->max_iter < 1) return fail(UOT_ERR_ARG, "the reverse pass needs max_iter >= 1");
     if (o->checkpoint_every < 1) return fail(UOT_ERR_ARG, "the reverse pass needs checkpoint_every >= 1");
     if (o->tol > 0.0) return fail(UOT_ERR_UNSUPPORTED, "the reverse pass differentiates a fixed iteration count (tol <= 0)");
+    if (p->k_dtype != UOT_F32 && p->k_dtype != UOT_F64)
+        return fail(UOT_ERR_DTYPE, "the reverse pass runs with FP32 or FP64 K");
     if (dim != 0 && dim != 2 && dim != 3) return fail(UOT_ERR_UNSUPPORTED, "point dimension %lld (0, 2 or 3)", (long long)dim);
     const int64_t nv = (p->m + B.F.vec - 1) / B.F.vec;
     const int awg = adj_wg();
@@ -537,7 +614,7 @@ uot_status run_backward(const uot_problem* p, const uot_options* o, const double
     if (P.build_k) {
         K = fw + P.off_k;
         ldk = P.ldk_ws;
-        UOT_HIP(launch_kernel_build(p->C, p->ldc, n, m, p->eps, nullptr, nullptr, p->k_dtype, (void*)K, ldk, stream),
+        UOT_HIP(launch_kernel_build(p->C, p->ldc, n, m, p->eps, nullptr, nullptr, p->k_dtype, (void*)K, ldk, 1.0, stream),
                 "kernel build");
     }
     UOT_HIP(launch_init(nullptr, 0, nullptr, nullptr, 0, nullptr, nullptr, ctrl, stream), "init");
@@ -563,8 +640,10 @@ uot_status run_backward(const uot_problem* p, const uot_options* o, const double
     L.ldv_bytes = P.ldv_bytes;
     L.fin_blocks = finalize_blocks(m);
     L.blockpart = bp;
+    L.k_scale = 1.0;
     FinLaunch F;
     memset(&F, 0, sizeof(F));
+    F.k_scale = 1.0;
     F.partials = fpart;
     F.ldp = P.ldp;
     F.G = P.G;
@@ -743,11 +822,14 @@ uot_status uot_kernel_from_cost(const double* C, int64_t ldc, int64_t n, int64_t
     if (!C || !K) return fail(UOT_ERR_ARG, "C and K must not be NULL");
     if (!(eps > 0.0) || !isfinite(eps)) return fail(UOT_ERR_ARG, "eps must be finite and > 0");
     if (ldc < m || ldk < m) return fail(UOT_ERR_ARG, "leading dimensions must be >= m");
-    if (k_dtype != UOT_F64 && k_dtype != UOT_F32) return fail(UOT_ERR_DTYPE, "K dtype %d not supported here", k_dtype);
+    if (k_dtype != UOT_F64 && k_dtype != UOT_F32 && k_dtype != UOT_BF16 && k_dtype != UOT_FP8_E4M3)
+        return fail(UOT_ERR_DTYPE, "K dtype %d not supported", k_dtype);
     int vec = 16 / elem_size(k_dtype);
     if (!aligned(K, 16) || ldk % vec != 0) return fail(UOT_ERR_ALIGN, "K must be 16-byte aligned, ldk a multiple of %d", vec);
     if (!aligned(C, 8)) return fail(UOT_ERR_ALIGN, "C must be 8-byte aligned");
-    UOT_HIP(launch_kernel_build(C, ldc, n, m, eps, f, g, k_dtype, K, ldk, (hipStream_t)stream), "kernel build");
+    UOT_HIP(launch_kernel_build(C, ldc, n, m, eps, f, g, k_dtype, K, ldk, k_dtype == UOT_FP8_E4M3 ? 448.0 : 1.0,
+                                (hipStream_t)stream),
+            "kernel build");
     return UOT_OK;
 }
 
@@ -766,6 +848,17 @@ uot_status uot_sinkhorn_profiled(const uot_problem* prob, const uot_options* opt
                                  void* ws, size_t ws_bytes, void* stream, uot_profile* prof) {
     if (!prof) return fail(UOT_ERR_ARG, "prof must not be NULL");
     return run_sinkhorn(prob, opt, out, ws, ws_bytes, (hipStream_t)stream, prof);
+}
+
+uot_status uot_kernel_to_f32(const void* K, int32_t k_dtype, int64_t count, double k_scale, float* out,
+                             void* stream) {
+    if (!K || !out || count < 0) return fail(UOT_ERR_ARG, "K and out must not be NULL, count >= 0");
+    const int es = elem_size(k_dtype);
+    if (es == 0) return fail(UOT_ERR_DTYPE, "unknown dtype %d", k_dtype);
+    if (count % (16 / es) != 0) return fail(UOT_ERR_ALIGN, "count must be a multiple of %d", 16 / es);
+    if (!aligned(K, 16)) return fail(UOT_ERR_ALIGN, "K must be 16-byte aligned");
+    UOT_HIP(launch_decode(K, k_dtype, count, k_scale, out, (hipStream_t)stream), "decode");
+    return UOT_OK;
 }
 
 size_t uot_sinkhorn_backward_workspace_size(const uot_problem* prob, const uot_options* opt, int64_t dim) {

@@ -14,10 +14,11 @@ __global__ void init_kernel(double* u, int64_t n, const double* u0, double* v, i
                             const double* v0, double* cprev, Ctrl* ctrl) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = t; i < n; i += stride) u[i] = u0 ? u0[i] : 1.0;
+    if (u)
+        for (int64_t i = t; i < n; i += stride) u[i] = u0 ? u0[i] : 1.0;
     for (int64_t j = t; j < m; j += stride) {
-        v[j] = v0 ? v0[j] : 1.0;
-        cprev[j] = 0.0;
+        if (v) v[j] = v0 ? v0[j] : 1.0;
+        if (cprev) cprev[j] = 0.0;
     }
     if (t == 0) {
         ctrl->done = 0;
@@ -99,6 +100,7 @@ __global__ __launch_bounds__(FIN_THREADS) void finalize_kernel(FinLaunch F) {
     if (lane < FIN_COLS) {
 #pragma unroll 16
         for (int k = 0; k < FIN_PHASES; ++k) w += part[k][lane];
+        w *= F.k_scale;
     }
 
     double dsum = 0.0, csum = 0.0;
@@ -156,17 +158,26 @@ __global__ __launch_bounds__(1024) void objective_kernel(ObjLaunch O) {
     const int lane = tid & 63;
     const int wave = tid >> 6;
     double sr = 0.0, sc = 0.0, mass = 0.0, kr = 0.0, kc = 0.0;
+    // With potentials, the total scalings are u e^{f/eps}, v e^{g/eps} and
+    // log(total) = log u + f/eps; r = u * (Kt v), c = v * (Kt^T u) as before.
+    const double inv_eps = 1.0 / O.eps;
     for (int64_t i = tid; i < O.n; i += 1024) {
         double r = O.u[i] * O.s[i];
         if (O.r_out) O.r_out[i] = r;
-        if (r > 0.0) sr += r * log(O.u[i]);
+        double lu = (O.u[i] > 0.0) ? log(O.u[i]) + (O.fpot ? O.fpot[i] * inv_eps : 0.0) : -INFINITY;
+        if (r > 0.0) sr += r * lu;
+        if (O.f_out) O.f_out[i] = O.eps * lu;
+        if (O.u_tot) O.u_tot[i] = (O.u[i] > 0.0) ? exp(lu) : 0.0;
         mass += r;
         kr += kl_term(r, O.a[i]);
     }
     for (int64_t j = tid; j < O.m; j += 1024) {
         double c = O.v[j] * O.w[j];
         if (O.c_out) O.c_out[j] = c;
-        if (c > 0.0) sc += c * log(O.v[j]);
+        double lv = (O.v[j] > 0.0) ? log(O.v[j]) + (O.gpot ? O.gpot[j] * inv_eps : 0.0) : -INFINITY;
+        if (c > 0.0) sc += c * lv;
+        if (O.g_out) O.g_out[j] = O.eps * lv;
+        if (O.v_tot) O.v_tot[j] = (O.v[j] > 0.0) ? exp(lv) : 0.0;
         kc += kl_term(c, O.b[j]);
     }
     double stop_err = 0.0;
@@ -194,7 +205,7 @@ __global__ __launch_bounds__(1024) void objective_kernel(ObjLaunch O) {
             // all enqueued iterations ran; the last one may still meet tol.
             O.info->iters = stopped ? O.ctrl->iters : O.iters_run;
             O.info->err = stopped ? O.ctrl->err : stop_err;
-            O.info->absorptions = 0;
+            O.info->absorptions = O.absorptions;
             uint32_t fl = O.ctrl->flags;
             if (O.tol > 0.0 && !stopped && !(O.iters_run > 0 && stop_err <= O.tol)) fl |= UOT_FLAG_NOT_CONVERGED;
             if (!isfinite(L)) fl |= UOT_FLAG_NONFINITE;
@@ -318,21 +329,35 @@ hipError_t launch_cost(const double* x, const double* y, int64_t n, int64_t m, i
 // columns [m, ldk) written as 0.
 // ---------------------------------------------------------------------------
 // grid.y strides over rows, grid.x * 256 threads over the columns of a row.
+template <typename KT> struct Store;
+template <> struct Store<double> {
+    static __device__ __forceinline__ double cv(double x) { return x; }
+};
+template <> struct Store<float> {
+    static __device__ __forceinline__ float cv(double x) { return (float)x; }
+};
+template <> struct Store<bf16_t> {
+    static __device__ __forceinline__ bf16_t cv(double x) { return bf16_t{f64_to_bf16(x)}; }
+};
+template <> struct Store<fp8_t> {
+    static __device__ __forceinline__ fp8_t cv(double x) { return fp8_t{f64_to_e4m3(x)}; }
+};
+
 template <typename KT>
 __global__ void kernel_build(const double* __restrict__ C, int64_t ldc, int64_t n, int64_t m, double eps,
                              const double* __restrict__ f, const double* __restrict__ g,
-                             KT* __restrict__ K, int64_t ldk) {
+                             KT* __restrict__ K, int64_t ldk, double store_scale) {
     for (int64_t i = blockIdx.y; i < n; i += gridDim.y) {
         const double fi_ = f ? f[i] : 0.0;
         for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < ldk;
              j += (int64_t)gridDim.x * blockDim.x) {
-            KT val = (KT)0;
+            double val = 0.0;
             if (j < m) {
                 double e = fi_ - C[i * ldc + j];
                 if (g) e += g[j];
-                val = (KT)exp(e / eps);
+                val = store_scale * exp(e / eps);
             }
-            K[i * ldk + j] = val;
+            K[i * ldk + j] = Store<KT>::cv(val);
         }
     }
 }
@@ -348,14 +373,198 @@ static dim3 row_grid(int64_t n, int64_t cols) {
 
 hipError_t launch_kernel_build(const double* C, int64_t ldc, int64_t n, int64_t m, double eps,
                                const double* f, const double* g, int k_dtype, void* K, int64_t ldk,
-                               hipStream_t stream) {
+                               double store_scale, hipStream_t stream) {
     dim3 grid = row_grid(n, ldk), block(256);
-    if (k_dtype == UOT_F64)
-        hipLaunchKernelGGL(kernel_build<double>, grid, block, 0, stream, C, ldc, n, m, eps, f, g, (double*)K, ldk);
-    else if (k_dtype == UOT_F32)
-        hipLaunchKernelGGL(kernel_build<float>, grid, block, 0, stream, C, ldc, n, m, eps, f, g, (float*)K, ldk);
-    else
-        return hipErrorInvalidValue;
+    switch (k_dtype) {
+        case UOT_F64:
+            hipLaunchKernelGGL(kernel_build<double>, grid, block, 0, stream, C, ldc, n, m, eps, f, g, (double*)K, ldk,
+                               store_scale);
+            break;
+        case UOT_F32:
+            hipLaunchKernelGGL(kernel_build<float>, grid, block, 0, stream, C, ldc, n, m, eps, f, g, (float*)K, ldk,
+                               store_scale);
+            break;
+        case UOT_BF16:
+            hipLaunchKernelGGL(kernel_build<bf16_t>, grid, block, 0, stream, C, ldc, n, m, eps, f, g, (bf16_t*)K,
+                               ldk, store_scale);
+            break;
+        case UOT_FP8_E4M3:
+            hipLaunchKernelGGL(kernel_build<fp8_t>, grid, block, 0, stream, C, ldc, n, m, eps, f, g, (fp8_t*)K, ldk,
+                               store_scale);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Stabilised (absorbed) kernel rebuild.  With
+//   f_i = min_j (C_ij - g_j)      then      g_j <- min_i (C_ij - f_i)  (>= g_j)
+// every exponent f_i + g_j - C_ij is <= 0, every column reaches 0 and every
+// row still does (at its own minimum), so Kt = exp((f + g - C)/eps) has
+// row and column maxima exactly 1: each stored type keeps each row's and
+// column's largest entries at full precision and no column is flushed
+// whole.  u and v are rescaled so the totals u e^{f/eps}, v e^{g/eps} are
+// unchanged (on the first build u and v hold the totals: f_old = g_old = 0).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void rowmin_kernel(const double* __restrict__ C, int64_t ldc, int64_t n,
+                                                     int64_t m, double eps, double* __restrict__ f,
+                                                     const double* __restrict__ g, double* __restrict__ u,
+                                                     int first) {
+    __shared__ double wmin[4];
+    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+        const double* Ci = C + i * ldc;
+        double mn = INFINITY;
+        for (int64_t j = threadIdx.x; j < m; j += 256) mn = fmin(mn, Ci[j] - g[j]);
+        // min is order independent: any reduction order gives the same bits
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) mn = fmin(mn, __shfl_xor(mn, off, 64));
+        if ((threadIdx.x & 63) == 0) wmin[threadIdx.x >> 6] = mn;
+        __syncthreads();
+        const double fnew = fmin(fmin(wmin[0], wmin[1]), fmin(wmin[2], wmin[3]));
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const double fold = first ? 0.0 : f[i];
+            if (u[i] > 0.0) u[i] = exp(log(u[i]) + (fold - fnew) / eps);
+            f[i] = fnew;
+        }
+    }
+}
+
+// Order-preserving map of a double to an unsigned key (negative values:
+// all bits flipped; others: the sign bit set), so that an integer atomic
+// min over keys is the exact FP64 minimum, independent of arrival order.
+__device__ __forceinline__ unsigned long long min_key(double d) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(d);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double min_key_value(unsigned long long k) {
+    const unsigned long long b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+    return __longlong_as_double((long long)b);
+}
+
+// Column minima of C_ij - f_i (of either sign: g takes absorbed values).
+__global__ __launch_bounds__(256) void colmin_kernel(const double* __restrict__ C, int64_t ldc, int64_t n,
+                                                     int64_t m, const double* __restrict__ f,
+                                                     unsigned long long* __restrict__ gmin_keys, int64_t rows_per_block) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= m) return;
+    const int64_t i0 = (int64_t)blockIdx.y * rows_per_block;
+    int64_t i1 = i0 + rows_per_block;
+    if (i1 > n) i1 = n;
+    double mn = INFINITY;
+    for (int64_t i = i0; i < i1; ++i) mn = fmin(mn, C[i * ldc + j] - f[i]);
+    atomicMin(&gmin_keys[j], min_key(mn));
+}
+
+__global__ void fill_bits_kernel(unsigned long long* p, int64_t count, unsigned long long bits) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x)
+        p[t] = bits;
+}
+
+// g_j <- the column minimum, v_j rescaled to keep v e^{g/eps}.
+__global__ void gshift_kernel(const unsigned long long* __restrict__ gmin_keys, double* __restrict__ g,
+                              double* __restrict__ v, int64_t m, double eps, int first) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += (int64_t)gridDim.x * blockDim.x) {
+        const double gnew = min_key_value(gmin_keys[j]);
+        const double gold = first ? 0.0 : g[j];
+        if (v[j] > 0.0) v[j] = exp(log(v[j]) + (gold - gnew) / eps);
+        g[j] = gnew;
+    }
+}
+
+hipError_t launch_rebuild(const double* C, int64_t ldc, int64_t n, int64_t m, double eps, double* f, double* g,
+                          double* u, double* v, void* gmin_scratch, int k_dtype, void* K, int64_t ldk,
+                          double store_scale, int first, hipStream_t stream) {
+    const int rblocks = (int)(n < 65536 ? n : 65536);
+    hipLaunchKernelGGL(rowmin_kernel, dim3(rblocks), dim3(256), 0, stream, C, ldc, n, m, eps, f, g, u, first);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    unsigned long long* gb = (unsigned long long*)gmin_scratch;
+    const unsigned long long inf_bits = 0xfff0000000000000ull;   // min_key(+inf)
+    int fb = (int)((m + 255) / 256);
+    if (fb > 1024) fb = 1024;
+    hipLaunchKernelGGL(fill_bits_kernel, dim3(fb), dim3(256), 0, stream, gb, m, inf_bits);
+    const int64_t rows_per_block = 256;
+    dim3 cgrid((unsigned)((m + 255) / 256), (unsigned)((n + rows_per_block - 1) / rows_per_block));
+    hipLaunchKernelGGL(colmin_kernel, cgrid, dim3(256), 0, stream, C, ldc, n, m, f, gb, rows_per_block);
+    hipLaunchKernelGGL(gshift_kernel, dim3(fb), dim3(256), 0, stream, gb, g, v, m, eps, first);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_kernel_build(C, ldc, n, m, eps, f, g, k_dtype, K, ldk, store_scale, stream);
+}
+
+__global__ __launch_bounds__(1024) void absorb_check_kernel(const double* u, int64_t n, const double* v, int64_t m,
+                                                           double* out) {
+    __shared__ double red[2][16];
+    double mu = 0.0, mv = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 1024)
+        if (u[i] > 0.0) mu = fmax(mu, fabs(log(u[i])));
+    for (int64_t j = threadIdx.x; j < m; j += 1024)
+        if (v[j] > 0.0) mv = fmax(mv, fabs(log(v[j])));
+    mu = wave_max_f64(mu);
+    mv = wave_max_f64(mv);
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = mu;
+        red[1][threadIdx.x >> 6] = mv;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, b = 0.0;
+        for (int w = 0; w < 16; ++w) {
+            a = fmax(a, red[0][w]);
+            b = fmax(b, red[1][w]);
+        }
+        out[0] = a;
+        out[1] = b;
+    }
+}
+
+hipError_t launch_absorb_check(const double* u, int64_t n, const double* v, int64_t m, double* out,
+                               hipStream_t stream) {
+    hipLaunchKernelGGL(absorb_check_kernel, dim3(1), dim3(1024), 0, stream, u, n, v, m, out);
+    return hipGetLastError();
+}
+
+__global__ void absorb_apply_kernel(double* v, double* g, int64_t m, double eps) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += (int64_t)gridDim.x * blockDim.x) {
+        if (v[j] > 0.0) {
+            g[j] += eps * log(v[j]);
+            v[j] = 1.0;
+        }
+    }
+}
+
+hipError_t launch_absorb_apply(double* v, double* g, int64_t m, double eps, hipStream_t stream) {
+    int blocks = (int)((m + 255) / 256);
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(absorb_apply_kernel, dim3(blocks), dim3(256), 0, stream, v, g, m, eps);
+    return hipGetLastError();
+}
+
+// Decode stored K (16-byte chunks, count a multiple of the chunk size) to FP32.
+template <typename KT>
+__global__ void decode_kernel(const KT* K, int64_t chunks, double scale, float* out) {
+    using Raw = typename KVec<KT>::raw;
+    constexpr int V = KVec<KT>::N;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < chunks; t += (int64_t)gridDim.x * blockDim.x) {
+        Raw r = ((const Raw*)K)[t];
+        float x[V];
+        Unpack<KT, float>::run(r, x);
+#pragma unroll
+        for (int e = 0; e < V; ++e) out[t * V + e] = (float)(scale * x[e]);
+    }
+}
+
+hipError_t launch_decode(const void* K, int k_dtype, int64_t count, double scale, float* out, hipStream_t stream) {
+    dim3 grid(1024), block(256);
+    switch (k_dtype) {
+        case UOT_F64: hipLaunchKernelGGL(decode_kernel<double>, grid, block, 0, stream, (const double*)K, count / 2, scale, out); break;
+        case UOT_F32: hipLaunchKernelGGL(decode_kernel<float>, grid, block, 0, stream, (const float*)K, count / 4, scale, out); break;
+        case UOT_BF16: hipLaunchKernelGGL(decode_kernel<bf16_t>, grid, block, 0, stream, (const bf16_t*)K, count / 8, scale, out); break;
+        case UOT_FP8_E4M3: hipLaunchKernelGGL(decode_kernel<fp8_t>, grid, block, 0, stream, (const fp8_t*)K, count / 16, scale, out); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -158,6 +158,7 @@ __global__ __launch_bounds__(WG) void persist_kernel(PersistLaunch P) {
             const int64_t j = cb0 + tid;
             double w = 0.0;
             for (int q = 0; q < phases; ++q) w += fin[q * P.fin_cols + tid];
+            w *= P.F.k_scale;
             if (j < L.m) {
                 const FinLaunch& F = P.F;
                 const double bj = F.b[j];
@@ -271,6 +272,8 @@ hipError_t launch_pass(int k_dtype, int acc64, int mode, int shape_idx, const Pa
         if (acc64) return launch_typed<float, double>(mode, shape_idx, L, lds, stream);
         return launch_typed<float, float>(mode, shape_idx, L, lds, stream);
     }
+    if (k_dtype == UOT_BF16) return launch_typed<bf16_t, float>(mode, shape_idx, L, lds, stream);
+    if (k_dtype == UOT_FP8_E4M3) return launch_typed<fp8_t, float>(mode, shape_idx, L, lds, stream);
     return hipErrorInvalidValue;
 }
 

@@ -108,7 +108,7 @@ struct Strip {
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 AT x[V];
-                unpack<AT>(buf[Q][c], x);
+                Unpack<KT, AT>::run(buf[Q][c], x);
                 if (ragged) {
 #pragma unroll
                     for (int e = 0; e < V; ++e)
@@ -131,6 +131,7 @@ struct Strip {
             double tot = 0.0;
 #pragma unroll
             for (int w = 0; w < NW; ++w) tot += red[slot][w];
+            tot *= L.k_scale;
             slot ^= 1;
             double uval;
             if constexpr (MODE == MODE_MARG) {
@@ -154,7 +155,7 @@ struct Strip {
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 AT x[V];
-                unpack<AT>(buf[Q][c], x);
+                Unpack<KT, AT>::run(buf[Q][c], x);
 #pragma unroll
                 for (int e = 0; e < V; ++e) acc[c * V + e] = fma(x[e], ur, acc[c * V + e]);
             }

@@ -44,18 +44,82 @@ __device__ __forceinline__ T zero_raw() {
     return z;
 }
 
-// Expand one 16-byte vector into N arithmetic values.
-template <typename AT>
-__device__ __forceinline__ void unpack(const f64x2& r, AT* o) {
-    o[0] = (AT)r[0];
-    o[1] = (AT)r[1];
+// Expand one 16-byte vector of stored K into N arithmetic values.
+template <typename KT, typename AT> struct Unpack;
+template <typename AT> struct Unpack<double, AT> {
+    static __device__ __forceinline__ void run(const f64x2& r, AT* o) {
+        o[0] = (AT)r[0];
+        o[1] = (AT)r[1];
+    }
+};
+template <typename AT> struct Unpack<float, AT> {
+    static __device__ __forceinline__ void run(const f32x4& r, AT* o) {
+        o[0] = (AT)r[0];
+        o[1] = (AT)r[1];
+        o[2] = (AT)r[2];
+        o[3] = (AT)r[3];
+    }
+};
+// bfloat16: the upper 16 bits of an FP32 value.
+template <typename AT> struct Unpack<bf16_t, AT> {
+    static __device__ __forceinline__ void run(const u32x4& r, AT* o) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            o[2 * q] = (AT)__uint_as_float(r[q] << 16);
+            o[2 * q + 1] = (AT)__uint_as_float(r[q] & 0xffff0000u);
+        }
+    }
+};
+// OCP E4M3FN through the gfx950 packed conversion (two values per instruction).
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+template <typename AT> struct Unpack<fp8_t, AT> {
+    static __device__ __forceinline__ void run(const u32x4& r, AT* o) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            f32x2 lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)r[q], false);
+            f32x2 hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)r[q], true);
+            o[4 * q] = (AT)lo[0];
+            o[4 * q + 1] = (AT)lo[1];
+            o[4 * q + 2] = (AT)hi[0];
+            o[4 * q + 3] = (AT)hi[1];
+        }
+    }
+};
+
+// FP64 -> bfloat16, round to nearest even: truncate to FP32 and mark
+// inexactness in the last FP32 bit (round to odd), then round the FP32 bits
+// to 16 (FP32 keeps 16 more mantissa bits, so no double rounding occurs).
+// Finite inputs only; results below the normal range are flushed to zero.
+__device__ __forceinline__ uint16_t f64_to_bf16(double d) {
+    float f = __double2float_rz(d);
+    uint32_t u = __float_as_uint(f);
+    if ((double)f != d) u |= 1u;
+    if ((u & 0x7f800000u) == 0) return (uint16_t)((u >> 16) & 0x8000u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
 }
-template <typename AT>
-__device__ __forceinline__ void unpack(const f32x4& r, AT* o) {
-    o[0] = (AT)r[0];
-    o[1] = (AT)r[1];
-    o[2] = (AT)r[2];
-    o[3] = (AT)r[3];
+
+// FP64 x >= 0 -> OCP E4M3FN (bias 7, max 448, subnormals 2^-9 .. 7 * 2^-9),
+// round to nearest even, saturating at 448.
+__device__ __forceinline__ uint8_t f64_to_e4m3(double x) {
+    if (!(x > 0.0)) return 0;
+    if (x >= 448.0) return 0x7e;
+    int e;
+    (void)frexp(x, &e);      // x = f * 2^e, f in [0.5, 1): floor(log2 x) = e - 1
+    int ex = e - 1;
+    if (ex < -6) {            // subnormal: multiples of 2^-9
+        double q = rint(ldexp(x, 9));
+        return (uint8_t)q;    // q = 8 is the smallest normal's code (0x08)
+    }
+    double mant = rint(ldexp(x, 3 - ex));   // in [8, 16]
+    if (mant >= 16.0) {
+        mant = 8.0;
+        ex += 1;
+    }
+    if (ex > 8) return 0x7e;
+    int code = ((ex + 7) << 3) | ((int)mant - 8);
+    if (code > 0x7e) code = 0x7e;
+    return (uint8_t)code;
 }
 
 // Four adjacent column partials (one 16-byte FP32 chunk or two FP64 chunks)
@@ -190,6 +254,7 @@ struct PassLaunch {
     const double* blockpart;   // 2 x fin_blocks: sum|c - c_prev|, sum|c| per block
     double tol;
     double* s_trace;           // optional (FUSED/ROW): row sums K v written per row
+    double k_scale;            // K = k_scale * stored values (1 except FP8)
 };
 
 struct PassShape {
@@ -230,6 +295,7 @@ struct FinLaunch {
     double* blockpart;        // 2 x nblocks
     int32_t marginal_only;    // 1: only w and c are formed
     int32_t acc64;
+    double k_scale;           // K = k_scale * stored values
 };
 
 hipError_t launch_finalize(const FinLaunch& F, hipStream_t stream);
@@ -325,8 +391,29 @@ struct ObjLaunch {
     int64_t iters_run;        // iterations enqueued (used when the stopping test never passed)
     const double* blockpart;  // block sums of the last finalize (error when not stopped)
     int32_t fin_blocks;
+    const double* fpot;       // optional row potentials: total scaling u * e^{f/eps}
+    const double* gpot;       // optional column potentials
+    double* f_out;            // optional eps log(total u)
+    double* g_out;            // optional eps log(total v)
+    double* u_tot;            // optional total u (may overflow to inf)
+    double* v_tot;            // optional total v
+    int32_t absorptions;      // absorptions performed (counted on the host)
 };
 hipError_t launch_objective(const ObjLaunch& O, hipStream_t stream);
+
+// Stabilised kernel: f_i = min_j (C_ij - g_j), then g_j = min_i (C_ij - f_i),
+// Kt_ij = store(scale exp((f_i + g_j - C_ij)/eps)); u and v rescaled so the
+// totals u e^{f/eps}, v e^{g/eps} are unchanged.  gmin_scratch: m x 8 bytes.
+hipError_t launch_rebuild(const double* C, int64_t ldc, int64_t n, int64_t m, double eps, double* f, double* g,
+                          double* u, double* v, void* gmin_scratch, int k_dtype, void* K, int64_t ldk,
+                          double store_scale, int first, hipStream_t stream);
+// out[0] = max_i |log u_i| (u_i > 0), out[1] = max_j |log v_j| (v_j > 0).
+hipError_t launch_absorb_check(const double* u, int64_t n, const double* v, int64_t m, double* out,
+                               hipStream_t stream);
+// g_j += eps log v_j, v_j = 1 (v_j > 0).
+hipError_t launch_absorb_apply(double* v, double* g, int64_t m, double eps, hipStream_t stream);
+// Decode stored K to FP32 as the passes read it.
+hipError_t launch_decode(const void* K, int k_dtype, int64_t count, double scale, float* out, hipStream_t stream);
 
 hipError_t launch_cost(const double* x, const double* y, int64_t n, int64_t m, int64_t d, int kind,
                        int normalize, double* C, int64_t ldc, double* blockmax, hipStream_t stream);
@@ -334,6 +421,6 @@ int64_t cost_blocks(int64_t n, int64_t m);
 
 hipError_t launch_kernel_build(const double* C, int64_t ldc, int64_t n, int64_t m, double eps,
                                const double* f, const double* g, int k_dtype, void* K, int64_t ldk,
-                               hipStream_t stream);
+                               double store_scale, hipStream_t stream);
 
 }  // namespace uot

@@ -275,6 +275,50 @@ def test_stabilized_equals_plain():
             assert nabs > 0
 
 
+def test_absorbed_normalised_equals_plain():
+    """The normalised absorbed iteration is a reparameterisation: in FP64 it
+    reproduces the plain iterates, marginals and objective for any
+    threshold and check interval, also where the plain kernel underflows
+    nowhere but exp(-C/eps) spans many decades."""
+    prob = workloads.random_small(17, 11, seed=29, eps=0.01, tau=0.2)
+    C, K = _problem_arrays(prob)
+    T = 60
+    res = oracle.sinkhorn(K, prob.a, prob.b, prob.eps, prob.tau, T)
+    counts = []
+    for thr, ce in ((0.0, 1), (0.5, 1), (8.0, 1), (3.0, 7), (1e9, 1)):
+        R = oracle.sinkhorn_absorbed(C, prob.a, prob.b, prob.eps, prob.tau, T, thr, ce)
+        np.testing.assert_allclose(R.f / prob.eps, np.log(res.u), rtol=0, atol=1e-10)
+        np.testing.assert_allclose(R.g / prob.eps, np.log(res.v), rtol=0, atol=1e-10)
+        np.testing.assert_allclose(R.r, res.r, rtol=1e-10)
+        np.testing.assert_allclose(R.c, res.c, rtol=1e-10)
+        assert R.loss == pytest.approx(res.loss, rel=1e-12)
+        counts.append(R.absorptions)
+    # 0.5 is below the scale of log a: every check absorbs; 8 only some
+    assert counts[0] == 0 and counts[-1] == 0 and counts[1] == T - 1 and 0 < counts[2] < counts[1]
+    assert counts[3] == (T - 1) // 7
+
+
+def test_absorbed_storage_error_scales_with_unit_roundoff():
+    """Holding the normalised kernel in binary32 / bfloat16 / E4M3 moves the
+    result by an amount that tracks each format's unit roundoff (2^-24,
+    2^-8, 2^-4): well below it times the fixed point's amplification and
+    ordered like the formats."""
+    prob = workloads.random_small(40, 30, seed=31, eps=0.05, tau=0.5)
+    C, K = _problem_arrays(prob)
+    T = 200
+    res = oracle.sinkhorn(K, prob.a, prob.b, prob.eps, prob.tau, T)
+    fi = prob.tau / (prob.tau + prob.eps)
+    amp = fi / (1 - fi)                 # infinity-norm bound of the log fixed point
+    errs = {}
+    for st, urd, scale in (("f32", 2.0 ** -24, 1.0), ("bf16", 2.0 ** -8, 1.0), ("e4m3", 2.0 ** -4, 448.0)):
+        R = oracle.sinkhorn_absorbed(C, prob.a, prob.b, prob.eps, prob.tau, T, 5.0, 1, st, scale)
+        e = max(np.max(np.abs(R.f / prob.eps - np.log(res.u))), np.max(np.abs(R.g / prob.eps - np.log(res.v))))
+        errs[st] = e
+        assert e <= 2 * amp * urd, (st, e)
+    assert errs["f32"] < errs["bf16"] < errs["e4m3"]
+    assert errs["bf16"] > 1e-5         # the storage really is applied
+
+
 # ---------------------------------------------------------------- special cases
 def test_zero_mass_entries_and_zero_iterations():
     prob = workloads.random_small(10, 8, seed=24, eps=0.1, tau=0.5)
@@ -317,3 +361,68 @@ def test_cost_points_kinds():
     np.testing.assert_allclose(Cn * C.max(), C, rtol=1e-15)
     Cc = oracle.cost_points(x, y, 1, False)
     assert Cc[1, 3] == pytest.approx(1.0 - float(x[1] @ y[3]), rel=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# Low-precision storage: every representable value and every midpoint
+# ---------------------------------------------------------------------------
+
+def _bf16_positive_normals():
+    """All positive finite normal bfloat16 values: bit patterns 0x0080..0x7F7F
+    placed in the top half of a binary32 word."""
+    codes = np.arange(0x0080, 0x7F80, dtype=np.uint32)
+    return (codes << 16).view(np.float32).astype(np.float64), codes
+
+
+def _e4m3_positive_values():
+    """All non-negative finite E4M3FN values from the bit layout (bias 7,
+    3 fraction bits, subnormals k 2^-9, code 0x7F is NaN)."""
+    vals = []
+    for code in range(0x00, 0x7F):
+        e, k = code >> 3, code & 7
+        vals.append(k * 2.0 ** -9 if e == 0 else (1 + k / 8) * 2.0 ** (e - 7))
+    return np.array(vals), np.arange(0x00, 0x7F)
+
+
+def test_round_storage_bf16_grid_and_midpoints():
+    vals, codes = _bf16_positive_normals()
+    assert np.array_equal(oracle.round_storage(vals, "bf16"), vals)
+    lo, hi = vals[:-1], vals[1:]
+    mid = (lo + hi) / 2                      # exact in FP64
+    even = np.where(codes[:-1] % 2 == 0, lo, hi)
+    assert np.array_equal(oracle.round_storage(mid, "bf16"), even)
+    assert np.array_equal(oracle.round_storage(np.nextafter(mid, 0), "bf16"), lo)
+    assert np.array_equal(oracle.round_storage(np.nextafter(mid, np.inf), "bf16"), hi)
+    below = np.array([0.0, 2.0 ** -127, np.nextafter(2.0 ** -126, 0)])
+    assert np.all(oracle.round_storage(below, "bf16") == 0.0)
+
+
+def test_round_storage_bf16_matches_torch_on_binary32_inputs():
+    import torch
+    rng = np.random.default_rng(11)
+    x = np.exp(rng.uniform(-80, 80, 200000)).astype(np.float32)
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(oracle.round_storage(x.astype(np.float64), "bf16"), ref)
+
+
+def test_round_storage_e4m3_grid_midpoints_and_saturation():
+    vals, codes = _e4m3_positive_values()
+    assert vals[-1] == 448.0 and vals[1] == 2.0 ** -9
+    assert np.array_equal(oracle.round_storage(vals, "e4m3"), vals)
+    lo, hi = vals[:-1], vals[1:]
+    mid = (lo + hi) / 2
+    even = np.where(codes[:-1] % 2 == 0, lo, hi)
+    assert np.array_equal(oracle.round_storage(mid, "e4m3"), even)
+    assert np.array_equal(oracle.round_storage(np.nextafter(mid, 0), "e4m3"), lo)
+    assert np.array_equal(oracle.round_storage(np.nextafter(mid, np.inf), "e4m3"), hi)
+    big = np.array([448.0, 460.0, 464.0, 1e6])
+    assert np.all(oracle.round_storage(big, "e4m3") == 448.0)
+
+
+def test_round_storage_e4m3_matches_torch_in_range():
+    import torch
+    rng = np.random.default_rng(12)
+    x = np.concatenate([rng.uniform(0, 448, 100000), np.exp(rng.uniform(-14, 6, 100000))])
+    x = x[x <= 448].astype(np.float32)
+    ref = torch.from_numpy(x).to(torch.float8_e4m3fn).to(torch.float64).numpy()
+    assert np.array_equal(oracle.round_storage(x.astype(np.float64), "e4m3"), ref)
