@@ -151,6 +151,14 @@ typedef struct uot_profile {
     float loop_ms;            /* whole iteration loop (all iterations) */
 } uot_profile;
 
+/* Tail of a packed batch descriptor block (host memory; see uot_batched_pack). */
+typedef struct uot_batched_meta {
+    int32_t count;            /* problems in the block */
+    int32_t k_dtype;          /* their common K dtype */
+    int64_t m_lds;            /* FP64 values per LDS vector the launch needs */
+    int64_t reserved[2];
+} uot_batched_meta;
+
 /* Status text, and a thread-local description of the last error. */
 const char* uot_status_string(uot_status s);
 const char* uot_last_error(void);
@@ -275,6 +283,68 @@ uot_status uot_sinkhorn_backward(const uot_problem* prob, const uot_options* opt
                                  const double* grad_loss, double* grad_a, double* grad_b,
                                  const double* x, const double* y, int64_t dim, double* grad_x,
                                  void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Many independent problems of uneven size, solved in ONE persistent launch
+ * (each problem is an independent application of the loop of Section 2.1;
+ * the single-pass interleave of Section 4.1 is applied inside one
+ * workgroup per problem).
+ *
+ * Each workgroup takes problems from a device queue in longest-first order
+ * (work n*m*sizeof(K) per iteration) and runs all of a problem's iterations
+ * by itself; no grid-wide synchronisation, no host round trip.  Products,
+ * row sums and column sums are FP64 on the widened stored K.  Every problem
+ * runs exactly opt->max_iter iterations, or stops after the first check
+ * (every check_every iterations) whose relative L1 change of the column
+ * marginal is <= opt->tol, then forms r = u*(K v), c = v*(K^T u) and the
+ * objective (as uot_sinkhorn) into its outputs.
+ *
+ * probs[i]: K (required; all problems share one k_dtype; n*ldk*sizeof(K)
+ *   below 2 GiB; m at most 2048 for FP64/FP32/BF16 and 4096 for FP8),
+ *   a, b, eps, tau, k_scale.  C is ignored.
+ * outs[i]: u, v, r, c (FP64 device vectors), loss, info (required); ckpt,
+ *   f, g ignored.
+ * opt: max_iter, tol, check_every, tune (> 0: time the candidate tile
+ *   shapes of each column-count bucket first, see uot_batched_tune); the
+ *   absorption, checkpoint, warm-start and cooperative options must be off
+ *   (else UOT_ERR_UNSUPPORTED).
+ * Workspace: uot_sinkhorn_batched_workspace_size(count) bytes, 256-byte
+ * aligned.  This call copies the descriptors from pageable host memory and
+ * synchronises `stream` once before launching; use the packed form below
+ * to capture the launch in a HIP graph.
+ * Errors: UOT_ERR_ARG, UOT_ERR_DTYPE, UOT_ERR_ALIGN, UOT_ERR_WORKSPACE,
+ * UOT_ERR_UNSUPPORTED, UOT_ERR_HIP.
+ */
+size_t uot_sinkhorn_batched_workspace_size(int32_t count);
+uot_status uot_sinkhorn_batched(const uot_problem* probs, int32_t count, const uot_options* opt,
+                                const uot_outputs* outs, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Two-step form of uot_sinkhorn_batched whose launch step makes no host
+ * synchronisation and no host-to-device copy, so that it can be captured
+ * in a HIP graph and replayed.
+ * uot_batched_pack (host only) validates the problems and writes the
+ * descriptor block into desc_host (uot_batched_desc_bytes(count) bytes):
+ * first the device descriptors (copy those uot_batched_desc_bytes(count) -
+ * sizeof(uot_batched_meta) bytes to 16-byte aligned device memory), then a
+ * uot_batched_meta.  The descriptors hold the problems' device pointers:
+ * they must stay valid while the block is used.
+ * uot_sinkhorn_batched_packed enqueues the queue reset and the persistent
+ * launch.  trace (optional, device, 2*count uint64): per problem (in queue
+ * order) the device wall clock when a workgroup took it and when it
+ * finished; uot_device_wall_clock_khz gives the clock's rate.
+ * uot_batched_tune runs only the autotuning step (results are kept for the
+ * process, per K dtype and column-count bucket, and used by later packs).
+ */
+size_t uot_batched_desc_bytes(int32_t count);
+uot_status uot_batched_pack(const uot_problem* probs, int32_t count, const uot_options* opt,
+                            const uot_outputs* outs, void* desc_host, size_t desc_bytes);
+uot_status uot_sinkhorn_batched_packed(const void* desc_dev, const uot_batched_meta* meta,
+                                       const uot_options* opt, void* ws, size_t ws_bytes,
+                                       uint64_t* trace, void* stream);
+uot_status uot_batched_tune(const uot_problem* probs, int32_t count, const uot_options* opt,
+                            const uot_outputs* outs, void* ws, size_t ws_bytes, void* stream);
+int64_t uot_device_wall_clock_khz(void);
 
 #ifdef __cplusplus
 }

@@ -18,7 +18,7 @@ from ._lib import (UOT_ACC_F32, UOT_ACC_F64, UOT_BF16, UOT_COST_COSINE, UOT_COST
                    UOT_FLAG_NONFINITE, UOT_FLAG_NOT_CONVERGED, UOT_FLAG_ZERO_SUM, UOT_FP8_E4M3, UOTError)
 
 __all__ = ["sinkhorn", "sinkhorn_backward", "UOTLoss", "uot_loss", "cost_from_points", "kernel_from_cost",
-           "kernel_to_f32",
+           "kernel_to_f32", "sinkhorn_batched", "BatchedSolver", "BatchedResult",
            "SinkhornResult", "UOTError", "lib_path",
            "UOT_F64", "UOT_F32", "UOT_BF16", "UOT_FP8_E4M3", "UOT_COST_SQEUCLID", "UOT_COST_COSINE"]
 
@@ -305,3 +305,6 @@ def uot_loss(x, y, a, b, eps: float, tau: float, max_iter: int, checkpoint_every
              k_dtype: torch.dtype = torch.float32) -> torch.Tensor:
     """Differentiable UOT objective (see UOTLoss)."""
     return UOTLoss.apply(x, y, a, b, eps, tau, max_iter, checkpoint_every, k_dtype)
+
+
+from .batched import BatchedResult, BatchedSolver, sinkhorn_batched  # noqa: E402

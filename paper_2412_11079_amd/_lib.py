@@ -48,6 +48,10 @@ class Profile(ctypes.Structure):
                 ("loop_ms", ctypes.c_float)]
 
 
+class BatchedMeta(ctypes.Structure):
+    _fields_ = [("count", _i32), ("k_dtype", _i32), ("m_lds", _i64), ("reserved", _i64 * 2)]
+
+
 # Every symbol that include/uot.h declares, with its ctypes signature.
 SIGNATURES = {
     "uot_status_string": ([_i32], ctypes.c_char_p),
@@ -64,6 +68,17 @@ SIGNATURES = {
     "uot_sinkhorn_backward_workspace_size": ([ctypes.POINTER(Problem), ctypes.POINTER(Options), _i64], _sz),
     "uot_sinkhorn_backward": ([ctypes.POINTER(Problem), ctypes.POINTER(Options), _vp, _vp, _vp, _vp, _vp, _vp,
                                _vp, _vp, _i64, _vp, _vp, _sz, _vp], _i32),
+    "uot_sinkhorn_batched_workspace_size": ([_i32], _sz),
+    "uot_sinkhorn_batched": ([ctypes.POINTER(Problem), _i32, ctypes.POINTER(Options), ctypes.POINTER(Outputs), _vp,
+                              _sz, _vp], _i32),
+    "uot_batched_desc_bytes": ([_i32], _sz),
+    "uot_batched_pack": ([ctypes.POINTER(Problem), _i32, ctypes.POINTER(Options), ctypes.POINTER(Outputs), _vp,
+                          _sz], _i32),
+    "uot_sinkhorn_batched_packed": ([_vp, ctypes.POINTER(BatchedMeta), ctypes.POINTER(Options), _vp, _sz, _vp,
+                                     _vp], _i32),
+    "uot_batched_tune": ([ctypes.POINTER(Problem), _i32, ctypes.POINTER(Options), ctypes.POINTER(Outputs), _vp,
+                          _sz, _vp], _i32),
+    "uot_device_wall_clock_khz": ([], _i64),
 }
 
 _lib = None

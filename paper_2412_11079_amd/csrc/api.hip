@@ -5,10 +5,12 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
 
+#include "batch.h"
 #include "uot_common.h"
 
 using namespace uot;
@@ -778,6 +780,242 @@ uot_status run_backward(const uot_problem* p, const uot_options* o, const double
     return UOT_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// Batched problems
+// ---------------------------------------------------------------------------
+
+uot_status check_batch_options(const uot_options* o) {
+    if (!o) return fail(UOT_ERR_ARG, "options must not be NULL");
+    if (o->max_iter < 0) return fail(UOT_ERR_ARG, "max_iter must be >= 0");
+    if (o->tol > 0.0 && o->check_every < 1) return fail(UOT_ERR_ARG, "check_every must be >= 1");
+    if (o->absorb_log_threshold != 0.0 || o->checkpoint_every != 0 || o->persistent || o->u0 || o->v0)
+        return fail(UOT_ERR_UNSUPPORTED,
+                    "batched problems run the plain iteration: no absorption, checkpoints, warm start or "
+                    "cooperative loop");
+    return UOT_OK;
+}
+
+uot_status check_batch_problem(const uot_problem* p, const uot_outputs* out, int32_t idx) {
+    if (p->n < 1 || p->m < 1) return fail(UOT_ERR_ARG, "problem %d: empty (n=%lld, m=%lld)", idx, (long long)p->n, (long long)p->m);
+    if (!p->a || !p->b) return fail(UOT_ERR_ARG, "problem %d: a and b must not be NULL", idx);
+    if (!aligned(p->a, 8) || !aligned(p->b, 8)) return fail(UOT_ERR_ALIGN, "problem %d: a, b must be 8-byte aligned", idx);
+    if (!(p->eps > 0.0) || !isfinite(p->eps)) return fail(UOT_ERR_ARG, "problem %d: eps must be finite and > 0", idx);
+    if (!(p->tau > 0.0)) return fail(UOT_ERR_ARG, "problem %d: tau must be > 0 (or +inf)", idx);
+    const int es = elem_size(p->k_dtype);
+    if (es == 0) return fail(UOT_ERR_DTYPE, "problem %d: K dtype %d not supported", idx, (int)p->k_dtype);
+    if (!p->K) return fail(UOT_ERR_ARG, "problem %d: batched problems take K (build it with uot_kernel_from_cost)", idx);
+    if (p->ldk < p->m) return fail(UOT_ERR_ARG, "problem %d: ldk (%lld) < m (%lld)", idx, (long long)p->ldk, (long long)p->m);
+    if (!aligned(p->K, 16) || p->ldk % (16 / es) != 0)
+        return fail(UOT_ERR_ALIGN, "problem %d: K must be 16-byte aligned with ldk a multiple of %d", idx, 16 / es);
+    if (p->n * p->ldk * es >= (int64_t)1 << 31)
+        return fail(UOT_ERR_UNSUPPORTED, "problem %d: K of a batched problem must be below 2 GiB", idx);
+    if (!(p->k_scale >= 0.0) || !isfinite(p->k_scale)) return fail(UOT_ERR_ARG, "problem %d: k_scale must be finite and >= 0", idx);
+    if (!out) return fail(UOT_ERR_ARG, "outputs must not be NULL");
+    if (!out->u || !out->v || !out->r || !out->c || !out->loss || !out->info)
+        return fail(UOT_ERR_ARG, "problem %d: outputs u, v, r, c, loss and info are required", idx);
+    if (!aligned(out->u, 8) || !aligned(out->v, 8) || !aligned(out->r, 8) || !aligned(out->c, 8) ||
+        !aligned(out->loss, 8) || !aligned(out->info, 8))
+        return fail(UOT_ERR_ALIGN, "problem %d: outputs must be 8-byte aligned", idx);
+    return UOT_OK;
+}
+
+// Default tile shape: the smallest row-group capacity that covers m (lanes
+// per row group x chunks), preferring more row groups (fewer barriers).
+int batch_default_shape(int64_t m, int k_dtype) {
+    int best = -1;
+    int64_t best_cap = 0;
+    for (int s = 0; s < batch_shape_count(); ++s) {
+        if (!batch_shape_ok(s, k_dtype)) continue;
+        const int64_t cap = batch_shape_max_m(s, k_dtype);
+        if (cap < m) continue;
+        if (best < 0 || cap < best_cap || (cap == best_cap && batch_shape_rows(s) > batch_shape_rows(best))) {
+            best = s;
+            best_cap = cap;
+        }
+    }
+    return best;
+}
+
+int size_bucket(int64_t m) {
+    int b = 0;
+    while (((int64_t)1 << b) < m) ++b;
+    return b;
+}
+
+// Autotuned shapes per (K dtype, column-count bucket), filled by timing runs.
+std::mutex g_tune_mu;
+std::map<std::pair<int, int>, int> g_tuned;
+
+int batch_shape_for(int64_t m, int k_dtype) {
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tuned.find({k_dtype, size_bucket(m)});
+        if (it != g_tuned.end() && batch_shape_max_m(it->second, k_dtype) >= m) return it->second;
+    }
+    return batch_default_shape(m, k_dtype);
+}
+
+size_t batch_desc_bytes(int32_t count) { return align_up(sizeof(BatchDesc) * (size_t)std::max(count, 1), kAlign); }
+
+// Descriptors in longest-first order (work n*m*sizeof(K) per iteration).
+uot_status pack_batch(const uot_problem* probs, int32_t count, const uot_options* o, const uot_outputs* outs,
+                      std::vector<BatchDesc>& d, int64_t& m_lds) {
+    uot_status st = check_batch_options(o);
+    if (st != UOT_OK) return st;
+    if (count < 0) return fail(UOT_ERR_ARG, "count must be >= 0");
+    if (count > 0 && (!probs || !outs)) return fail(UOT_ERR_ARG, "probs and outs must not be NULL");
+    std::vector<int32_t> order(count);
+    for (int32_t i = 0; i < count; ++i) {
+        st = check_batch_problem(&probs[i], &outs[i], i);
+        if (st != UOT_OK) return st;
+        order[i] = i;
+    }
+    auto work = [&](int32_t i) { return probs[i].n * probs[i].m * (int64_t)elem_size(probs[i].k_dtype); };
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return work(x) > work(y); });
+    d.assign(count, BatchDesc{});
+    m_lds = 0;
+    const int kd = count > 0 ? probs[0].k_dtype : UOT_F32;
+    for (int32_t q = 0; q < count; ++q) {
+        const uot_problem& p = probs[order[q]];
+        const uot_outputs& out = outs[order[q]];
+        if (p.k_dtype != kd) return fail(UOT_ERR_DTYPE, "all batched problems must share one K dtype");
+        const int shape = batch_shape_for(p.m, kd);
+        if (shape < 0)
+            return fail(UOT_ERR_UNSUPPORTED, "problem %d: m = %lld exceeds the batched row capacity (%lld)",
+                        order[q], (long long)p.m, (long long)batch_shape_max_m(batch_shape_count() - 1, kd));
+        BatchDesc& b = d[q];
+        b.K = p.K;
+        b.ldk = p.ldk;
+        b.n = p.n;
+        b.m = p.m;
+        b.a = p.a;
+        b.b = p.b;
+        b.u = (double*)out.u;
+        b.v = (double*)out.v;
+        b.r = out.r;
+        b.c = out.c;
+        b.loss = out.loss;
+        b.info = out.info;
+        b.fi = fi_of(p.eps, p.tau);
+        b.fi_is_one = isinf(p.tau) ? 1 : 0;
+        b.k_scale = p.k_scale > 0.0 ? p.k_scale : 1.0;
+        b.eps = p.eps;
+        b.tau = p.tau;
+        b.shape = shape;
+        b.index = order[q];
+        m_lds = std::max(m_lds, batch_shape_max_m(shape, kd));
+    }
+    return UOT_OK;
+}
+
+struct BatchRun {
+    int k_dtype;
+    int grid;
+    size_t lds;
+};
+
+uot_status batch_launch_config(int k_dtype, int64_t m_lds, int32_t count, BatchRun& R) {
+    R.k_dtype = k_dtype;
+    R.lds = batch_lds_bytes(m_lds);
+    if ((int64_t)R.lds > max_lds_bytes()) return fail(UOT_ERR_UNSUPPORTED, "batched LDS need exceeds the device");
+    const int g = batch_max_grid(k_dtype, R.lds);
+    if (g <= 0) return fail(UOT_ERR_HIP, "occupancy query failed for the batched kernel");
+    R.grid = std::max(1, std::min(g, count));
+    return UOT_OK;
+}
+
+uot_status run_batch_packed(const BatchDesc* desc_dev, int32_t count, int k_dtype, int64_t m_lds,
+                            const uot_options* o, void* ws, size_t ws_bytes, uint64_t* trace, hipStream_t stream) {
+    if (count == 0) return UOT_OK;
+    if (!ws || ws_bytes < kAlign || !aligned(ws, kAlign)) return fail(UOT_ERR_WORKSPACE, "workspace too small or misaligned");
+    BatchRun R;
+    uot_status st = batch_launch_config(k_dtype, m_lds, count, R);
+    if (st != UOT_OK) return st;
+    BatchLaunch B;
+    memset(&B, 0, sizeof(B));
+    B.desc = desc_dev;
+    B.count = count;
+    B.max_iter = o->max_iter;
+    B.tol = o->tol;
+    B.check_every = std::max(o->check_every, 1);
+    B.m_lds = m_lds;
+    B.next = (uint32_t*)ws;
+    B.trace = trace;
+    UOT_HIP(launch_batch(k_dtype, B, R.grid, R.lds, stream), "batched launch");
+    return UOT_OK;
+}
+
+// Timing runs that pick the tile shape of each column-count bucket present
+// in the batch (a few iterations of up to 8 of its problems per candidate).
+uot_status autotune_batch(const uot_problem* probs, int32_t count, const uot_options* o, const uot_outputs* outs,
+                          void* ws, size_t ws_bytes, hipStream_t stream) {
+    const int kd = probs[0].k_dtype;
+    std::map<int, std::vector<int32_t>> buckets;
+    for (int32_t i = 0; i < count; ++i) buckets[size_bucket(probs[i].m)].push_back(i);
+    const size_t dbytes = batch_desc_bytes(8);
+    if (ws_bytes < kAlign + dbytes) return fail(UOT_ERR_WORKSPACE, "workspace too small for tuning");
+    BatchDesc* ddev = (BatchDesc*)((char*)ws + kAlign);
+    hipEvent_t e0, e1;
+    UOT_HIP(hipEventCreate(&e0), "hipEventCreate");
+    UOT_HIP(hipEventCreate(&e1), "hipEventCreate");
+    uot_options t = *o;
+    t.max_iter = std::min(o->max_iter, 3);
+    t.tol = 0.0;
+    uot_status st = UOT_OK;
+    for (auto& kv : buckets) {
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            if (g_tuned.count({kd, kv.first})) continue;
+        }
+        std::vector<int32_t>& ids = kv.second;
+        if (ids.size() > 8) ids.resize(8);
+        int64_t mmax = 0;
+        for (int32_t i : ids) mmax = std::max(mmax, probs[i].m);
+        int best = -1;
+        float best_ms = 0.0f;
+        for (int s = 0; s < batch_shape_count() && st == UOT_OK; ++s) {
+            if (!batch_shape_ok(s, kd) || batch_shape_max_m(s, kd) < mmax) continue;
+            std::vector<BatchDesc> d;
+            int64_t m_lds = 0;
+            std::vector<uot_problem> ps;
+            std::vector<uot_outputs> os;
+            for (int32_t i : ids) {
+                ps.push_back(probs[i]);
+                os.push_back(outs[i]);
+            }
+            st = pack_batch(ps.data(), (int32_t)ps.size(), &t, os.data(), d, m_lds);
+            if (st != UOT_OK) break;
+            for (auto& b : d) b.shape = s;
+            m_lds = batch_shape_max_m(s, kd);
+            hipError_t e = hipMemcpy(ddev, d.data(), sizeof(BatchDesc) * d.size(), hipMemcpyHostToDevice);
+            if (e != hipSuccess) { st = hip_fail(e, "tuning copy"); break; }
+            float ms = 0.0f;
+            for (int rep = 0; rep < 2 && st == UOT_OK; ++rep) {       // first run warms up
+                e = hipEventRecord(e0, stream);
+                if (e == hipSuccess) st = run_batch_packed(ddev, (int32_t)d.size(), kd, m_lds, &t, ws, ws_bytes, nullptr, stream);
+                if (st == UOT_OK && e == hipSuccess) e = hipEventRecord(e1, stream);
+                if (st == UOT_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+                if (st == UOT_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e != hipSuccess && st == UOT_OK) st = hip_fail(e, "tuning run");
+            }
+            if (st != UOT_OK) break;
+            if (best < 0 || ms < best_ms) {
+                best = s;
+                best_ms = ms;
+            }
+        }
+        if (st != UOT_OK) break;
+        if (best >= 0) {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tuned[{kd, kv.first}] = best;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
+}
+
 }  // namespace
 
 extern "C" {
@@ -873,6 +1111,85 @@ uot_status uot_sinkhorn_backward(const uot_problem* prob, const uot_options* opt
                                  size_t ws_bytes, void* stream) {
     return run_backward(prob, opt, u, v, ckpt, grad_loss, grad_a, grad_b, x, y, dim, grad_x, ws, ws_bytes,
                         (hipStream_t)stream);
+}
+
+size_t uot_batched_desc_bytes(int32_t count) { return count < 0 ? 0 : batch_desc_bytes(count) + sizeof(uot_batched_meta); }
+
+uot_status uot_batched_pack(const uot_problem* probs, int32_t count, const uot_options* opt,
+                            const uot_outputs* outs, void* desc_host, size_t desc_bytes) {
+    if (!desc_host) return fail(UOT_ERR_ARG, "desc_host must not be NULL");
+    if (count < 0 || desc_bytes < uot_batched_desc_bytes(count)) return fail(UOT_ERR_ARG, "desc_bytes too small");
+    std::vector<BatchDesc> d;
+    int64_t m_lds = 0;
+    uot_status st = pack_batch(probs, count, opt, outs, d, m_lds);
+    if (st != UOT_OK) return st;
+    memset(desc_host, 0, desc_bytes);
+    if (count > 0) memcpy(desc_host, d.data(), sizeof(BatchDesc) * d.size());
+    uot_batched_meta meta;
+    memset(&meta, 0, sizeof(meta));
+    meta.count = count;
+    meta.k_dtype = count > 0 ? probs[0].k_dtype : UOT_F32;
+    meta.m_lds = m_lds;
+    memcpy((char*)desc_host + batch_desc_bytes(count), &meta, sizeof(meta));
+    return UOT_OK;
+}
+
+size_t uot_sinkhorn_batched_workspace_size(int32_t count) {
+    if (count < 0) return 0;
+    return kAlign + batch_desc_bytes(count);
+}
+
+uot_status uot_sinkhorn_batched_packed(const void* desc_dev, const uot_batched_meta* meta, const uot_options* opt,
+                                       void* ws, size_t ws_bytes, uint64_t* trace, void* stream) {
+    if (!meta) return fail(UOT_ERR_ARG, "meta must not be NULL");
+    uot_status st = check_batch_options(opt);
+    if (st != UOT_OK) return st;
+    if (meta->count < 0 || (meta->count > 0 && !desc_dev)) return fail(UOT_ERR_ARG, "bad descriptor block");
+    if (!aligned(desc_dev, 16)) return fail(UOT_ERR_ALIGN, "descriptors must be 16-byte aligned");
+    if (elem_size(meta->k_dtype) == 0) return fail(UOT_ERR_DTYPE, "bad K dtype in meta");
+    if (trace && !aligned(trace, 8)) return fail(UOT_ERR_ALIGN, "trace must be 8-byte aligned");
+    return run_batch_packed((const BatchDesc*)desc_dev, meta->count, meta->k_dtype, meta->m_lds, opt, ws, ws_bytes,
+                            trace, (hipStream_t)stream);
+}
+
+uot_status uot_sinkhorn_batched(const uot_problem* probs, int32_t count, const uot_options* opt,
+                                const uot_outputs* outs, void* ws, size_t ws_bytes, void* stream) {
+    if (count < 0) return fail(UOT_ERR_ARG, "count must be >= 0");
+    if (count == 0) return check_batch_options(opt);
+    if (!ws || ws_bytes < uot_sinkhorn_batched_workspace_size(count) || !aligned(ws, kAlign))
+        return fail(UOT_ERR_WORKSPACE, "workspace too small or misaligned");
+    hipStream_t s = (hipStream_t)stream;
+    if (opt && opt->tune > 0 && probs) {
+        uot_status st = autotune_batch(probs, count, opt, outs, ws, ws_bytes, s);
+        if (st != UOT_OK) return st;
+    }
+    std::vector<BatchDesc> d;
+    int64_t m_lds = 0;
+    uot_status st = pack_batch(probs, count, opt, outs, d, m_lds);
+    if (st != UOT_OK) return st;
+    BatchDesc* ddev = (BatchDesc*)((char*)ws + kAlign);
+    // pageable source: the copy has consumed it when the call returns
+    UOT_HIP(hipMemcpyAsync(ddev, d.data(), sizeof(BatchDesc) * d.size(), hipMemcpyHostToDevice, s), "descriptor copy");
+    UOT_HIP(hipStreamSynchronize(s), "descriptor copy");
+    return run_batch_packed(ddev, count, probs[0].k_dtype, m_lds, opt, ws, ws_bytes, nullptr, s);
+}
+
+uot_status uot_batched_tune(const uot_problem* probs, int32_t count, const uot_options* opt, const uot_outputs* outs,
+                            void* ws, size_t ws_bytes, void* stream) {
+    if (count <= 0) return UOT_OK;
+    if (!probs || !outs) return fail(UOT_ERR_ARG, "probs and outs must not be NULL");
+    uot_status st = check_batch_options(opt);
+    if (st != UOT_OK) return st;
+    if (!ws || ws_bytes < uot_sinkhorn_batched_workspace_size(std::min(count, 8)) || !aligned(ws, kAlign))
+        return fail(UOT_ERR_WORKSPACE, "workspace too small or misaligned");
+    return autotune_batch(probs, count, opt, outs, ws, ws_bytes, (hipStream_t)stream);
+}
+
+int64_t uot_device_wall_clock_khz(void) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeWallClockRate, dev) != hipSuccess) return 0;
+    return v;
 }
 
 }  // extern "C"

@@ -1,0 +1,423 @@
+// Batched UOT Sinkhorn: many independent problems of uneven size in one
+// persistent launch.
+//
+// Every workgroup (256 lanes, four waves) takes problems from a queue in
+// longest-first order and runs all iterations of a problem by itself: the
+// row half-step and the column accumulation happen in one pass over the
+// problem's K per iteration (the single-pass interleave of the paper's
+// Section 4.1, here inside one workgroup), the column sums never leave the
+// workgroup, and v lives in LDS between iterations.  No grid-wide
+// synchronisation exists, so the launch is a plain kernel that a HIP graph
+// can hold.
+//
+// Tile shape of a problem (BatchDesc::shape, chosen per problem on the
+// host): rg row groups of 256/rg lanes work on rg rows at once (rg = 4: one
+// wave per row and no barrier per row), and each lane covers nc 16-byte
+// chunks of a row (at most kLaneCols values).  The shape is a run-time
+// value, so one code path serves every problem.  Arithmetic: products, row
+// sums and column sums in FP64 (the stored K is widened), so a problem's
+// result is the FP64 iteration on its stored K up to summation order.
+#include <math.h>
+
+#include "batch.h"
+#include "strip.h"
+
+namespace uot {
+
+namespace {
+
+constexpr int kBatchWG = 256;
+constexpr int kBatchNW = kBatchWG / 64;
+
+struct BatchShapeDef {
+    int rg;
+    int nc;
+};
+constexpr BatchShapeDef kBatchShapes[] = {{4, 1}, {4, 2}, {4, 4}, {2, 1}, {2, 2}, {2, 4}, {1, 1}, {1, 2}, {1, 4}};
+constexpr int kNumBatchShapes = sizeof(kBatchShapes) / sizeof(kBatchShapes[0]);
+constexpr int kLaneCols = 8;            // FP64 column sums a lane holds
+
+template <typename KT>
+constexpr int nc_max() {
+    return KVec<KT>::N >= kLaneCols ? 1 : kLaneCols / KVec<KT>::N;
+}
+
+// Block-wide FP64 sum in a fixed order; every thread receives the result.
+__device__ __forceinline__ double block_sum(double x, double* scratch) {
+    x = wave_sum_f64(x);
+    const int wave = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) scratch[wave] = x;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kBatchNW; ++w) t += scratch[w];
+    return t;
+}
+
+__device__ __forceinline__ double kl_term(double x, double y) {
+    // x log(x/y) - x + y with 0 log 0 = 0
+    if (x > 0.0) return x * log(x / y) - x + y;
+    return y;
+}
+
+struct BatchShared {
+    double red[2][kBatchNW];
+    double scratch[kBatchNW];
+    int32_t idx;
+    uint32_t flags;
+};
+
+template <typename KT>
+struct BatchSolve {
+    using KV = KVec<KT>;
+    using Raw = typename KV::raw;
+    static constexpr int V = KV::N;
+    static constexpr int NCM = nc_max<KT>();
+    static constexpr int E = NCM * V;
+
+    __amdgpu_buffer_rsrc_t rsrc;
+    uint32_t row_bytes;
+    int rg, nc, lr, wpr, grp, gl;
+    int col[NCM];                       // first column of each chunk (m < 2^31)
+    uint32_t voff[NCM];
+    Raw buf[2][NCM];
+    double acc[E];
+
+    template <int Q>
+    __device__ __forceinline__ void load_row(int64_t i) {
+        const uint32_t soff = (uint32_t)i * row_bytes;
+#pragma unroll
+        for (int c = 0; c < NCM; ++c)
+            buf[Q][c] = __builtin_bit_cast(
+                Raw, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)voff[c], (int)soff, 2));
+    }
+
+    // The lane's chunk c of the row in buffer Q, widened; columns >= m read
+    // as 0 (chunks beyond the shape's nc point past the buffer and read 0).
+    template <int Q>
+    __device__ __forceinline__ void unpack(int c, int m, bool ragged, double* x) const {
+        Unpack<KT, double>::run(buf[Q][c], x);
+        if (ragged) {
+#pragma unroll
+            for (int e = 0; e < V; ++e)
+                if (col[c] + e >= m) x[e] = 0.0;
+        }
+    }
+
+    template <int Q>
+    __device__ __forceinline__ double lane_dot(const double* vl, int m, bool ragged) const {
+        double s = 0.0;
+#pragma unroll
+        for (int c = 0; c < NCM; ++c) {
+            if (c < nc) {
+                double x[V];
+                unpack<Q>(c, m, ragged, x);
+#pragma unroll
+                for (int e = 0; e < V; ++e) s = fma(x[e], vl[col[c] + e], s);
+            }
+        }
+        return s;
+    }
+
+    // Row total over the group's waves: wave sums, then (several waves per
+    // row) an LDS exchange among all waves.  Every lane of the group gets it.
+    __device__ __forceinline__ double row_total(double s, BatchShared& sh, int& slot) const {
+        const double d = wave_sum_f64(s);
+        if (wpr == 1) return d;
+        const int wave = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) sh.red[slot][wave] = d;
+        __syncthreads();
+        double t = 0.0;
+        for (int w = 0; w < wpr; ++w) t += sh.red[slot][grp * wpr + w];
+        slot ^= 1;
+        return t;
+    }
+
+    // One row of an iteration: dot, u_i, column accumulation (the group's
+    // next row is requested into the other buffer first).
+    template <int Q>
+    __device__ __forceinline__ void sweep_row(const BatchDesc& P, int64_t i, const double* vl, int m, bool ragged,
+                                              BatchShared& sh, int& slot, uint32_t& fl) {
+        load_row<Q ^ 1>(i + rg);                     // beyond the last row: reads 0
+        const double tot = row_total(lane_dot<Q>(vl, m, ragged), sh, slot) * P.k_scale;
+        double ui = 0.0;
+        if (i < P.n) {
+            const double ai = P.a[i];
+            ui = scale_factor(ai, tot, P.fi, P.fi_is_one, 0.0);
+            if (gl == 0) {
+                P.u[i] = ui;
+                if (ai > 0.0 && !(tot > 0.0)) fl |= UOT_FLAG_ZERO_SUM;
+                if (!isfinite(ui)) fl |= UOT_FLAG_NONFINITE;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NCM; ++c) {
+            if (c < nc) {
+                double x[V];
+                unpack<Q>(c, m, ragged, x);
+#pragma unroll
+                for (int e = 0; e < V; ++e) acc[c * V + e] = fma(x[e], ui, acc[c * V + e]);
+            }
+        }
+    }
+
+    // One row of the final sweep: r_i = u_i (K v)_i and the objective's row terms.
+    template <int Q>
+    __device__ __forceinline__ void marg_row(const BatchDesc& P, int64_t i, const double* vl, int m, bool ragged,
+                                             BatchShared& sh, int& slot, double& rlu, double& rsum, double& klr) {
+        load_row<Q ^ 1>(i + rg);
+        const double tot = row_total(lane_dot<Q>(vl, m, ragged), sh, slot) * P.k_scale;
+        if (i < P.n && gl == 0) {
+            const double ui = P.u[i];
+            const double ri = ui * tot;
+            P.r[i] = ri;
+            if (ri > 0.0) rlu += ri * log(ui);
+            rsum += ri;
+            klr += kl_term(ri, P.a[i]);
+        }
+    }
+
+    __device__ void run(const BatchDesc& P, const BatchLaunch& B, double* vl, double* wl, BatchShared& sh) {
+        const int tid = threadIdx.x;
+        const BatchShapeDef sd = kBatchShapes[P.shape];
+        rg = sd.rg;
+        nc = sd.nc;
+        lr = kBatchWG / rg;
+        wpr = lr / 64;
+        grp = tid / lr;
+        gl = tid % lr;
+        const int64_t n = P.n;
+        const int m = (int)P.m;
+        row_bytes = (uint32_t)(P.ldk * (int64_t)sizeof(KT));
+        const uint32_t total = (uint32_t)(n * row_bytes);
+        rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)P.K, (short)0, (int)total, kBufferWord3);
+#pragma unroll
+        for (int c = 0; c < NCM; ++c) {
+            col[c] = (c * lr + gl) * V;
+            voff[c] = (c < nc && col[c] < m) ? (uint32_t)col[c] * (uint32_t)sizeof(KT) : total;
+        }
+        const int mpad = nc * lr * V;
+        for (int j = tid; j < mpad; j += kBatchWG) vl[j] = (j < m) ? 1.0 : 0.0;
+        const double tol = B.tol;
+        // previous column marginal of the stopping test: c_0 = 0
+        if (tol > 0.0)
+            for (int j = tid; j < m; j += kBatchWG) P.c[j] = 0.0;
+        if (tid == 0) sh.flags = 0u;
+        __syncthreads();
+
+        const bool ragged = (m % V) != 0;
+        uint32_t fl = 0;
+        // rows of a group: i = grp + rg k, k < kmax (the same count for every
+        // group: groups that exchange row totals step together)
+        const int64_t kmax = (n + rg - 1) / rg;
+        int slot = 0;
+        int64_t it = 0;
+        double err = 0.0;
+        bool stopped = false;
+        for (int64_t t = 1; t <= B.max_iter; ++t) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) acc[e] = 0.0;
+            load_row<0>(grp);
+            for (int64_t k = 0; k < kmax; k += 2) {
+                sweep_row<0>(P, grp + rg * k, vl, m, ragged, sh, slot, fl);
+                if (k + 1 < kmax) sweep_row<1>(P, grp + rg * (k + 1), vl, m, ragged, sh, slot, fl);
+            }
+            // Column sums: the groups' partials added in group order.
+            if (rg > 1) {
+                for (int g = 0; g < rg; ++g) {
+                    if (grp == g) {
+#pragma unroll
+                        for (int c = 0; c < NCM; ++c)
+#pragma unroll
+                            for (int e = 0; e < V; ++e) {
+                                const int j = col[c] + e;
+                                if (c < nc && j < m) wl[j] = (g == 0) ? acc[c * V + e] : wl[j] + acc[c * V + e];
+                            }
+                    }
+                    __syncthreads();
+                }
+            } else {
+                __syncthreads();     // every row's use of v is complete
+            }
+            // Column half-step (group 0 owns each column once), marginal c = v w.
+            double dsum = 0.0, csum = 0.0;
+            if (grp == 0) {
+#pragma unroll
+                for (int c = 0; c < NCM; ++c)
+#pragma unroll
+                    for (int e = 0; e < V; ++e) {
+                        const int j = col[c] + e;
+                        if (c < nc && j < m) {
+                            const double w = ((rg > 1) ? wl[j] : acc[c * V + e]) * P.k_scale;
+                            const double bj = P.b[j];
+                            const double vj = scale_factor(bj, w, P.fi, P.fi_is_one, 0.0);
+                            if (bj > 0.0 && !(w > 0.0)) fl |= UOT_FLAG_ZERO_SUM;
+                            if (!isfinite(vj)) fl |= UOT_FLAG_NONFINITE;
+                            vl[j] = vj;
+                            P.v[j] = vj;
+                            const double cj = vj * w;
+                            if (tol > 0.0) {
+                                dsum += fabs(cj - P.c[j]);
+                                csum += fabs(cj);
+                            }
+                            P.c[j] = cj;
+                        }
+                    }
+            }
+            it = t;
+            if (tol > 0.0 && (t % B.check_every) == 0) {
+                const double ds = block_sum(dsum, sh.scratch);
+                const double cs = block_sum(csum, sh.scratch);
+                err = ds / cs;
+                if (err <= tol) stopped = true;
+            }
+            __syncthreads();     // v complete in LDS before the next sweep
+            if (stopped) break;
+        }
+
+        // Row marginal r = u (K v) with the final v, and the objective's terms.
+        double rlu = 0.0, rsum = 0.0, klr = 0.0;
+        load_row<0>(grp);
+        for (int64_t k = 0; k < kmax; k += 2) {
+            marg_row<0>(P, grp + rg * k, vl, m, ragged, sh, slot, rlu, rsum, klr);
+            if (k + 1 < kmax) marg_row<1>(P, grp + rg * (k + 1), vl, m, ragged, sh, slot, rlu, rsum, klr);
+        }
+        double clv = 0.0, klc = 0.0;
+        if (grp == 0) {
+#pragma unroll
+            for (int c = 0; c < NCM; ++c)
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    const int j = col[c] + e;
+                    if (c < nc && j < m) {
+                        const double cj = P.c[j];
+                        if (cj > 0.0) clv += cj * log(vl[j]);
+                        klc += kl_term(cj, P.b[j]);
+                    }
+                }
+        }
+        if (fl) atomicOr(&sh.flags, fl);
+        const double s_rlu = block_sum(rlu, sh.scratch);
+        const double s_r = block_sum(rsum, sh.scratch);
+        const double s_clv = block_sum(clv, sh.scratch);
+        double L = P.eps * (s_rlu + s_clv - s_r);
+        if (!P.fi_is_one) {
+            const double s_klr = block_sum(klr, sh.scratch);
+            const double s_klc = block_sum(klc, sh.scratch);
+            L += P.tau * (s_klr + s_klc);
+        }
+        if (tid == 0) {
+            *P.loss = L;
+            uint32_t flags = sh.flags;
+            if (!isfinite(L)) flags |= UOT_FLAG_NONFINITE;
+            if (tol > 0.0 && !stopped) flags |= UOT_FLAG_NOT_CONVERGED;
+            P.info->iters = it;
+            P.info->err = err;
+            P.info->absorptions = 0;
+            P.info->flags = flags;
+        }
+        __syncthreads();
+    }
+};
+
+template <typename KT>
+__global__ __launch_bounds__(kBatchWG, 2) void batch_kernel(BatchLaunch B) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ BatchShared sh;
+    double* vl = (double*)smem;
+    double* wl = vl + B.m_lds;
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) {
+            const int32_t idx = (int32_t)atomicAdd(B.next, 1u);
+            sh.idx = idx;
+            if (B.trace && idx < B.count) B.trace[2 * idx] = wall_clock64();
+        }
+        __syncthreads();
+        const int32_t idx = __builtin_amdgcn_readfirstlane(sh.idx);   // uniform: descriptor in SGPRs
+        __syncthreads();
+        if (idx >= B.count) break;
+        const BatchDesc P = B.desc[idx];
+        BatchSolve<KT> s;
+        s.run(P, B, vl, wl, sh);
+        if (tid == 0 && B.trace) B.trace[2 * idx + 1] = wall_clock64();
+    }
+}
+
+__global__ void batch_reset_kernel(uint32_t* next) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *next = 0u;
+}
+
+template <typename KT>
+const void* batch_fn() {
+    return (const void*)batch_kernel<KT>;
+}
+
+const void* batch_lookup(int k_dtype) {
+    switch (k_dtype) {
+        case UOT_F64: return batch_fn<double>();
+        case UOT_F32: return batch_fn<float>();
+        case UOT_BF16: return batch_fn<bf16_t>();
+        case UOT_FP8_E4M3: return batch_fn<fp8_t>();
+        default: return nullptr;
+    }
+}
+
+int elem_bytes_of(int k_dtype) {
+    switch (k_dtype) {
+        case UOT_F64: return 8;
+        case UOT_F32: return 4;
+        case UOT_BF16: return 2;
+        default: return 1;
+    }
+}
+
+}  // namespace
+
+int batch_shape_count() { return kNumBatchShapes; }
+
+bool batch_shape_ok(int shape, int k_dtype) {
+    if (shape < 0 || shape >= kNumBatchShapes) return false;
+    const int v = 16 / elem_bytes_of(k_dtype);
+    const int ncm = v >= kLaneCols ? 1 : kLaneCols / v;
+    return kBatchShapes[shape].nc <= ncm;
+}
+
+// Columns a shape covers for a stored type.
+int64_t batch_shape_max_m(int shape, int k_dtype) {
+    const BatchShapeDef d = kBatchShapes[shape];
+    return (int64_t)d.nc * (kBatchWG / d.rg) * (16 / elem_bytes_of(k_dtype));
+}
+
+int batch_shape_rows(int shape) { return kBatchShapes[shape].rg; }
+
+size_t batch_lds_bytes(int64_t m_lds) { return sizeof(double) * 2 * (size_t)m_lds; }
+
+int batch_max_grid(int k_dtype, size_t lds) {
+    const void* fn = batch_lookup(k_dtype);
+    if (!fn) return 0;
+    if (lds > 65536 && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return 0;
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBatchWG, lds) != hipSuccess) return 0;
+    return per_cu * cus;
+}
+
+hipError_t launch_batch(int k_dtype, const BatchLaunch& B, int grid, size_t lds, hipStream_t stream) {
+    const void* fn = batch_lookup(k_dtype);
+    if (!fn) return hipErrorInvalidValue;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, stream, B.next);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    void* args[] = {(void*)&B};
+    return hipLaunchKernel(fn, dim3(grid), dim3(kBatchWG), args, lds, stream);
+}
+
+}  // namespace uot
