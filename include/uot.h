@@ -277,6 +277,50 @@ uot_status uot_sinkhorn_profiled(const uot_problem* prob, const uot_options* opt
 uot_status uot_kernel_to_f32(const void* K, int32_t k_dtype, int64_t count, double k_scale, float* out,
                              void* stream);
 
+/*
+ * The plan P = diag(u) K diag(v) of Section 2.1's rescaled matrix, written
+ * densely on request (n x ldp, row-major, FP64 or FP32; columns [m, ldp)
+ * untouched).  Two forms:
+ *  - prob->K with u, v (e.g. outputs->u, v of uot_sinkhorn):
+ *      P_ij = u_i (k_scale K_ij) v_j, products in FP64;
+ *  - prob->C with f, g (outputs->f, g: potentials of the total scalings,
+ *    finite where u, v overflow, as after absorption):
+ *      P_ij = exp((f_i + g_j - C_ij) / prob->eps), in FP64.
+ * K is used when prob->K, u and v are all given, else C with f and g.
+ * Errors: UOT_ERR_ARG, UOT_ERR_DTYPE, UOT_ERR_ALIGN, UOT_ERR_HIP.
+ */
+uot_status uot_plan(const uot_problem* prob, const double* u, const double* v, const double* f, const double* g,
+                    void* plan, int64_t ldp, int32_t plan_dtype, void* stream);
+
+/*
+ * R histogram pairs sharing one kernel (each pair an independent instance
+ * of Section 2.1's loop): the two half-steps of an iteration become two
+ * matrix products on the matrix cores,
+ *     S = K V,    U = (A / S)^fi,      W = K^T U,   V = (B / W)^fi,
+ * with V = 1 at the start, then r = U (K V), c = V (K^T U) and the
+ * objective of every pair (as uot_sinkhorn) in FP64.
+ * shared: n, m, K (UOT_F32 or UOT_BF16; padding columns [m, ldk) finite),
+ *   ldk, k_scale, eps, tau; a, b and C are ignored.
+ * A: R x n and B: R x m FP64, histogram r in row r (A[r*n + i] = a_r,i).
+ * U: R x n, V: R x m FP64 outputs (same layout); losses: R FP64;
+ * info: one record for all pairs (iters, flags).
+ * Arithmetic: BF16 K with each right-hand side split into a bfloat16 high
+ * part and the bfloat16 rounding of the remainder (two products per tile,
+ * ~16 significant bits of the right-hand side kept); FP32 K with FP32
+ * products.  Each reduction is split over k into chunks summed in FP32 on
+ * the matrix cores and added in FP64 in a fixed order.
+ * opt: max_iter >= 1 iterations exactly; tol, absorption, checkpoints, warm
+ * start and the cooperative loop must be off (else UOT_ERR_UNSUPPORTED).
+ * Workspace (uot_sinkhorn_multi_workspace_size): a transposed copy of K,
+ * the split partial sums and the right-hand-side planes.
+ * Errors: UOT_ERR_ARG, UOT_ERR_DTYPE, UOT_ERR_ALIGN, UOT_ERR_WORKSPACE,
+ * UOT_ERR_UNSUPPORTED, UOT_ERR_HIP.
+ */
+size_t uot_sinkhorn_multi_workspace_size(const uot_problem* shared, int32_t R, const uot_options* opt);
+uot_status uot_sinkhorn_multi(const uot_problem* shared, int32_t R, const double* A, const double* B,
+                              const uot_options* opt, double* U, double* V, double* losses, uot_info* info,
+                              void* ws, size_t ws_bytes, void* stream);
+
 size_t uot_sinkhorn_backward_workspace_size(const uot_problem* prob, const uot_options* opt, int64_t dim);
 uot_status uot_sinkhorn_backward(const uot_problem* prob, const uot_options* opt,
                                  const double* u, const double* v, const double* ckpt,

@@ -18,7 +18,7 @@ from ._lib import (UOT_ACC_F32, UOT_ACC_F64, UOT_BF16, UOT_COST_COSINE, UOT_COST
                    UOT_FLAG_NONFINITE, UOT_FLAG_NOT_CONVERGED, UOT_FLAG_ZERO_SUM, UOT_FP8_E4M3, UOTError)
 
 __all__ = ["sinkhorn", "sinkhorn_backward", "UOTLoss", "uot_loss", "cost_from_points", "kernel_from_cost",
-           "kernel_to_f32", "sinkhorn_batched", "BatchedSolver", "BatchedResult",
+           "kernel_to_f32", "sinkhorn_batched", "BatchedSolver", "BatchedResult", "plan", "sinkhorn_multi",
            "SinkhornResult", "UOTError", "lib_path",
            "UOT_F64", "UOT_F32", "UOT_BF16", "UOT_FP8_E4M3", "UOT_COST_SQEUCLID", "UOT_COST_COSINE"]
 
@@ -225,6 +225,84 @@ def sinkhorn(a: torch.Tensor, b: torch.Tensor, K: Optional[torch.Tensor] = None,
     res._problem = prob
     res._options = opt
     res.ckpt = ckpt
+    return res
+
+
+def plan(res: SinkhornResult, dtype: torch.dtype = torch.float64, from_cost: bool = False) -> torch.Tensor:
+    """Dense plan of a solve (include/uot.h, uot_plan): u_i K_ij v_j from the
+    solve's kernel, or (``from_cost``, needs the solve's C) the form
+    exp((f_i + g_j - C_ij)/eps) from the potentials of the total scalings."""
+    if dtype not in (torch.float64, torch.float32):
+        raise ValueError("plan dtype must be float64 or float32")
+    prob = res._problem
+    n, m = res.u.shape[0], res.v.shape[0]
+    P = torch.empty((n, m), dtype=dtype, device=res.u.device)
+    p = _lib.Problem.from_buffer_copy(prob)
+    L = _lib.lib()
+    if from_cost:
+        if not prob.C:
+            raise ValueError("from_cost needs a solve given C")
+        p.K = None
+        args = (None, None, _ptr(res.f), _ptr(res.g))
+    else:
+        if not prob.K:
+            raise ValueError("the solve built its kernel internally: use from_cost=True")
+        args = (_ptr(res.u), _ptr(res.v), None, None)
+    _lib.check(L.uot_plan(ctypes.byref(p), *args, _ptr(P), m, _DTYPES[dtype], _stream(res.u.device)))
+    return P
+
+
+@dataclass
+class MultiResult:
+    U: torch.Tensor           # (R, n) FP64
+    V: torch.Tensor           # (R, m) FP64
+    loss: torch.Tensor        # (R,) FP64
+    info_raw: torch.Tensor
+
+    def info(self) -> dict:
+        s = _lib.Info.from_buffer_copy(bytes(self.info_raw.cpu().numpy().tobytes()))
+        return {"iters": s.iters, "err": s.err, "absorptions": s.absorptions, "flags": s.flags}
+
+
+def sinkhorn_multi(K: torch.Tensor, A: torch.Tensor, B: torch.Tensor, *, m: Optional[int] = None, eps: float,
+                   tau: float, max_iter: int) -> MultiResult:
+    """R histogram pairs sharing K (include/uot.h, uot_sinkhorn_multi).
+    K: (n, ldk) FP32 or BF16; A: (R, n), B: (R, m) FP64, one histogram per row."""
+    if K.dtype not in (torch.float32, torch.bfloat16):
+        raise ValueError("K must be float32 or bfloat16")
+    if A.dtype != torch.float64 or B.dtype != torch.float64 or A.dim() != 2 or B.dim() != 2:
+        raise ValueError("A and B must be (R, n) and (R, m) float64 matrices")
+    A = A.contiguous()
+    B = B.contiguous()
+    R, n = A.shape
+    m = B.shape[1] if m is None else int(m)
+    if B.shape != (R, m) or K.shape[0] != n or K.shape[1] < m or K.stride(1) != 1:
+        raise ValueError("shapes of K, A and B do not match")
+    device = K.device
+    prob = _lib.Problem()
+    prob.n, prob.m = n, m
+    prob.k_dtype = _DTYPES[K.dtype]
+    prob.K = K.data_ptr()
+    prob.ldk = K.stride(0)
+    prob.eps, prob.tau, prob.k_scale = float(eps), float(tau), 1.0
+    opt = _lib.Options()
+    opt.max_iter = int(max_iter)
+    opt.check_every = 1
+    opt.fused = 1
+    L = _lib.lib()
+    need = L.uot_sinkhorn_multi_workspace_size(ctypes.byref(prob), R, ctypes.byref(opt))
+    if need == 0:
+        _lib.check(L.uot_sinkhorn_multi(ctypes.byref(prob), R, None, None, ctypes.byref(opt), None, None, None, None,
+                                        None, 0, None))
+    ws = _workspace(need, device)
+    U = torch.empty((R, n), dtype=torch.float64, device=device)
+    V = torch.empty((R, m), dtype=torch.float64, device=device)
+    loss = torch.empty(R, dtype=torch.float64, device=device)
+    info = torch.zeros(ctypes.sizeof(_lib.Info), dtype=torch.uint8, device=device)
+    _lib.check(L.uot_sinkhorn_multi(ctypes.byref(prob), R, _ptr(A), _ptr(B), ctypes.byref(opt), _ptr(U), _ptr(V),
+                                    _ptr(loss), _ptr(info), _ptr(ws), ws.numel(), _stream(device)))
+    res = MultiResult(U, V, loss, info)
+    res._keep = (ws, K, A, B)
     return res
 
 

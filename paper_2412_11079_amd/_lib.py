@@ -79,6 +79,10 @@ SIGNATURES = {
     "uot_batched_tune": ([ctypes.POINTER(Problem), _i32, ctypes.POINTER(Options), ctypes.POINTER(Outputs), _vp,
                           _sz, _vp], _i32),
     "uot_device_wall_clock_khz": ([], _i64),
+    "uot_plan": ([ctypes.POINTER(Problem), _vp, _vp, _vp, _vp, _vp, _i64, _i32, _vp], _i32),
+    "uot_sinkhorn_multi_workspace_size": ([ctypes.POINTER(Problem), _i32, ctypes.POINTER(Options)], _sz),
+    "uot_sinkhorn_multi": ([ctypes.POINTER(Problem), _i32, _vp, _vp, ctypes.POINTER(Options), _vp, _vp, _vp, _vp,
+                            _vp, _sz, _vp], _i32),
 }
 
 _lib = None

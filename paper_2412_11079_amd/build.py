@@ -12,7 +12,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libuot.so")
-SOURCES = ["pass.hip", "aux.hip", "adj.hip", "batch.hip", "api.hip"]
+SOURCES = ["pass.hip", "aux.hip", "adj.hip", "batch.hip", "multi.hip", "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are disabled for every device compile.
@@ -31,7 +31,7 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int = 5) -> str:
+def build(jobs: int = 6) -> str:
     """Compile every HIP source and link libuot.so; always rebuilds."""
     os.makedirs(BUILD, exist_ok=True)
     with ThreadPoolExecutor(max_workers=jobs) as ex:

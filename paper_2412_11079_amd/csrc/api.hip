@@ -11,6 +11,8 @@
 #include <vector>
 
 #include "batch.h"
+#include "multi.h"
+#include "plan.h"
 #include "uot_common.h"
 
 using namespace uot;
@@ -1016,6 +1018,194 @@ uot_status autotune_batch(const uot_problem* probs, int32_t count, const uot_opt
     return st;
 }
 
+
+// ---------------------------------------------------------------------------
+// Many right-hand sides sharing one K
+// ---------------------------------------------------------------------------
+
+struct MultiGemmShape {
+    int64_t rows_pad, kdim_pad, kchunk;
+    int32_t splits;
+};
+
+MultiGemmShape multi_gemm_shape(int64_t rows, int64_t kdim_pad, int64_t r_pad) {
+    MultiGemmShape g;
+    g.rows_pad = round_up(rows, kMTileRows);
+    g.kdim_pad = kdim_pad;
+    const int64_t tiles = (r_pad / kMTileCols) * (g.rows_pad / kMTileRows);
+    int64_t splits = std::max<int64_t>(1, std::min<int64_t>(kdim_pad / 256, (1024 + tiles - 1) / tiles));
+    g.kchunk = round_up((kdim_pad + splits - 1) / splits, kMStep);
+    g.splits = (int32_t)((kdim_pad + g.kchunk - 1) / g.kchunk);
+    return g;
+}
+
+struct MultiPlan {
+    bool bf16;
+    int es;
+    int64_t n, m, R, r_pad, ldn, ldm;
+    MultiGemmShape row, col;
+    size_t off_kt, off_part, off_uhi, off_ulo, off_vhi, off_vlo, off_rm, off_cm, off_flags, total;
+};
+
+uot_status make_multi_plan(const uot_problem* p, int32_t R, const uot_options* o, MultiPlan& M) {
+    if (!p || !o) return fail(UOT_ERR_ARG, "problem and options must not be NULL");
+    if (p->n < 1 || p->m < 1) return fail(UOT_ERR_ARG, "empty problem");
+    if (R < 1) return fail(UOT_ERR_ARG, "R must be >= 1");
+    if (!(p->eps > 0.0) || !isfinite(p->eps)) return fail(UOT_ERR_ARG, "eps must be finite and > 0");
+    if (!(p->tau > 0.0)) return fail(UOT_ERR_ARG, "tau must be > 0 (or +inf)");
+    if (o->max_iter < 1) return fail(UOT_ERR_ARG, "max_iter must be >= 1");
+    if (o->tol > 0.0 || o->absorb_log_threshold != 0.0 || o->checkpoint_every != 0 || o->persistent || o->u0 || o->v0)
+        return fail(UOT_ERR_UNSUPPORTED,
+                    "the multi-right-hand-side form runs a fixed iteration count with no absorption, "
+                    "checkpoints or warm start");
+    if (p->k_dtype != UOT_F32 && p->k_dtype != UOT_BF16)
+        return fail(UOT_ERR_DTYPE, "the multi-right-hand-side form takes an FP32 or BF16 K");
+    if (!p->K) return fail(UOT_ERR_ARG, "K is required");
+    M.bf16 = p->k_dtype == UOT_BF16;
+    M.es = elem_size(p->k_dtype);
+    if (p->ldk < p->m || !aligned(p->K, 16) || p->ldk % (16 / M.es) != 0)
+        return fail(UOT_ERR_ALIGN, "K must be 16-byte aligned with ldk >= m a multiple of %d", 16 / M.es);
+    if (!(p->k_scale >= 0.0) || !isfinite(p->k_scale)) return fail(UOT_ERR_ARG, "k_scale must be finite and >= 0");
+    M.n = p->n;
+    M.m = p->m;
+    M.R = R;
+    M.r_pad = round_up(R, kMTileCols);
+    M.ldn = round_up(p->n, 64);
+    M.ldm = round_up(p->m, 64);
+    if ((int64_t)M.n * p->ldk * M.es >= ((int64_t)1 << 31) || M.m * M.ldn * M.es >= ((int64_t)1 << 31) ||
+        M.r_pad * std::max(M.ldn, M.ldm) * M.es >= ((int64_t)1 << 31))
+        return fail(UOT_ERR_UNSUPPORTED, "K and the right-hand sides must each be below 2 GiB");
+    M.row = multi_gemm_shape(M.n, M.ldm, M.r_pad);      // S = K V: rows n, reduction over m
+    M.col = multi_gemm_shape(M.m, M.ldn, M.r_pad);      // W = K^T U: rows m, reduction over n
+    size_t off = 0;
+    M.off_kt = off;
+    off = align_up(off + (size_t)M.m * M.ldn * M.es, kAlign);
+    M.off_part = off;
+    const size_t part = std::max((size_t)M.row.splits * M.r_pad * M.row.rows_pad,
+                                 (size_t)M.col.splits * M.r_pad * M.col.rows_pad) * sizeof(float);
+    off = align_up(off + part, kAlign);
+    const int xe = M.bf16 ? 2 : 4;
+    M.off_uhi = off;
+    off = align_up(off + (size_t)M.r_pad * M.ldn * xe, kAlign);
+    M.off_ulo = off;
+    if (M.bf16) off = align_up(off + (size_t)M.r_pad * M.ldn * xe, kAlign);
+    M.off_vhi = off;
+    off = align_up(off + (size_t)M.r_pad * M.ldm * xe, kAlign);
+    M.off_vlo = off;
+    if (M.bf16) off = align_up(off + (size_t)M.r_pad * M.ldm * xe, kAlign);
+    M.off_rm = off;
+    off = align_up(off + sizeof(double) * (size_t)R * M.n, kAlign);
+    M.off_cm = off;
+    off = align_up(off + sizeof(double) * (size_t)R * M.m, kAlign);
+    M.off_flags = off;
+    off = align_up(off + 64, kAlign);
+    M.total = off;
+    return UOT_OK;
+}
+
+uot_status run_multi(const uot_problem* p, int32_t R, const double* A, const double* B, const uot_options* o,
+                     double* U, double* V, double* losses, uot_info* info, void* ws, size_t ws_bytes,
+                     hipStream_t stream) {
+    MultiPlan M;
+    uot_status st = make_multi_plan(p, R, o, M);
+    if (st != UOT_OK) return st;
+    if (!A || !B || !U || !V || !losses || !info) return fail(UOT_ERR_ARG, "A, B, U, V, losses and info are required");
+    if (!aligned(A, 8) || !aligned(B, 8) || !aligned(U, 8) || !aligned(V, 8) || !aligned(losses, 8) || !aligned(info, 8))
+        return fail(UOT_ERR_ALIGN, "vectors must be 8-byte aligned");
+    if (!ws || ws_bytes < M.total || !aligned(ws, kAlign)) return fail(UOT_ERR_WORKSPACE, "workspace too small or misaligned");
+    char* base = (char*)ws;
+    void* KT = base + M.off_kt;
+    float* part = (float*)(base + M.off_part);
+    void* uhi = base + M.off_uhi;
+    void* ulo = M.bf16 ? (void*)(base + M.off_ulo) : nullptr;
+    void* vhi = base + M.off_vhi;
+    void* vlo = M.bf16 ? (void*)(base + M.off_vlo) : nullptr;
+    double* Rm = (double*)(base + M.off_rm);
+    double* Cm = (double*)(base + M.off_cm);
+    uint32_t* flags = (uint32_t*)(base + M.off_flags);
+    const double fi = fi_of(p->eps, p->tau);
+    const int fi_one = isinf(p->tau) ? 1 : 0;
+    const double ks = p->k_scale > 0.0 ? p->k_scale : 1.0;
+
+    UOT_HIP(launch_multi_info(info, 0, flags, 1, stream), "multi reset");
+    UOT_HIP(launch_transpose(p->k_dtype, p->K, p->ldk, M.n, M.m, KT, M.ldn, stream), "transpose");
+    UOT_HIP(launch_ones_rhs(M.bf16, vhi, vlo, R, M.r_pad, M.m, M.ldm, stream), "initial v");
+
+    MGemm rowg;
+    memset(&rowg, 0, sizeof(rowg));
+    rowg.A = p->K;
+    rowg.lda = p->ldk;
+    rowg.rows = M.n;
+    rowg.rows_pad = M.row.rows_pad;
+    rowg.kdim_pad = M.row.kdim_pad;
+    rowg.x_hi = vhi;
+    rowg.x_lo = vlo;
+    rowg.ldx = M.ldm;
+    rowg.r_pad = M.r_pad;
+    rowg.splits = M.row.splits;
+    rowg.kchunk = M.row.kchunk;
+    rowg.part = part;
+    rowg.ld_part = M.row.rows_pad;
+    MGemm colg = rowg;
+    colg.A = KT;
+    colg.lda = M.ldn;
+    colg.rows = M.m;
+    colg.rows_pad = M.col.rows_pad;
+    colg.kdim_pad = M.col.kdim_pad;
+    colg.x_hi = uhi;
+    colg.x_lo = ulo;
+    colg.ldx = M.ldn;
+    colg.splits = M.col.splits;
+    colg.kchunk = M.col.kchunk;
+    colg.ld_part = M.col.rows_pad;
+
+    MEpi eu;
+    memset(&eu, 0, sizeof(eu));
+    eu.part = part;
+    eu.ld_part = M.row.rows_pad;
+    eu.splits = M.row.splits;
+    eu.rows = M.n;
+    eu.R = R;
+    eu.r_pad = M.r_pad;
+    eu.target = A;
+    eu.y = U;
+    eu.next_hi = uhi;
+    eu.next_lo = ulo;
+    eu.ld_next = M.ldn;
+    eu.bf16 = M.bf16;
+    eu.fi = fi;
+    eu.fi_is_one = fi_one;
+    eu.k_scale = ks;
+    eu.mode = 0;
+    eu.flags = flags;
+    MEpi ev = eu;
+    ev.ld_part = M.col.rows_pad;
+    ev.splits = M.col.splits;
+    ev.rows = M.m;
+    ev.target = B;
+    ev.y = V;
+    ev.next_hi = vhi;
+    ev.next_lo = vlo;
+    ev.ld_next = M.ldm;
+
+    for (int t = 1; t <= o->max_iter; ++t) {
+        UOT_HIP(launch_mgemm(M.bf16, rowg, stream), "row product");
+        UOT_HIP(launch_mepi(eu, stream), "row update");
+        UOT_HIP(launch_mgemm(M.bf16, colg, stream), "column product");
+        ev.marg = (t == o->max_iter) ? Cm : nullptr;      // c = v (K^T u) of the last iteration
+        UOT_HIP(launch_mepi(ev, stream), "column update");
+    }
+    // r = u (K v) with the final v
+    UOT_HIP(launch_mgemm(M.bf16, rowg, stream), "marginal product");
+    MEpi er = eu;
+    er.mode = 1;
+    er.marg = Rm;
+    UOT_HIP(launch_mepi(er, stream), "row marginal");
+    UOT_HIP(launch_multi_loss(U, V, Rm, Cm, A, B, M.n, M.m, R, p->eps, p->tau, fi_one, losses, flags, stream), "objective");
+    UOT_HIP(launch_multi_info(info, o->max_iter, flags, 0, stream), "info");
+    return UOT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1190,6 +1380,49 @@ int64_t uot_device_wall_clock_khz(void) {
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeWallClockRate, dev) != hipSuccess) return 0;
     return v;
+}
+
+uot_status uot_plan(const uot_problem* prob, const double* u, const double* v, const double* f, const double* g,
+                    void* plan, int64_t ldp, int32_t plan_dtype, void* stream) {
+    if (!prob || !plan) return fail(UOT_ERR_ARG, "problem and plan must not be NULL");
+    if (prob->n < 1 || prob->m < 1) return fail(UOT_ERR_ARG, "empty problem");
+    if (plan_dtype != UOT_F64 && plan_dtype != UOT_F32) return fail(UOT_ERR_DTYPE, "plan dtype must be F64 or F32");
+    if (ldp < prob->m) return fail(UOT_ERR_ARG, "ldp (%lld) < m (%lld)", (long long)ldp, (long long)prob->m);
+    if (!aligned(plan, elem_size(plan_dtype))) return fail(UOT_ERR_ALIGN, "plan misaligned");
+    hipStream_t s = (hipStream_t)stream;
+    if (prob->K && u && v) {
+        const int es = elem_size(prob->k_dtype);
+        if (es == 0) return fail(UOT_ERR_DTYPE, "K dtype %d not supported", (int)prob->k_dtype);
+        if (prob->ldk < prob->m) return fail(UOT_ERR_ARG, "ldk < m");
+        if (!aligned(prob->K, 16) || prob->ldk % (16 / es) != 0)
+            return fail(UOT_ERR_ALIGN, "K must be 16-byte aligned with ldk a multiple of %d", 16 / es);
+        if (!aligned(u, 8) || !aligned(v, 8)) return fail(UOT_ERR_ALIGN, "u and v must be 8-byte aligned");
+        const double ks = prob->k_scale > 0.0 ? prob->k_scale : 1.0;
+        UOT_HIP(launch_plan_from_k(prob->K, prob->k_dtype, prob->ldk, prob->n, prob->m, ks, u, v, plan, plan_dtype,
+                                   ldp, s), "plan");
+        return UOT_OK;
+    }
+    if (prob->C && f && g) {
+        if (prob->ldc < prob->m) return fail(UOT_ERR_ARG, "ldc < m");
+        if (!(prob->eps > 0.0)) return fail(UOT_ERR_ARG, "eps must be > 0");
+        if (!aligned(prob->C, 8) || !aligned(f, 8) || !aligned(g, 8)) return fail(UOT_ERR_ALIGN, "C, f, g must be 8-byte aligned");
+        UOT_HIP(launch_plan_from_cost(prob->C, prob->ldc, prob->n, prob->m, prob->eps, f, g, plan, plan_dtype, ldp, s),
+                "plan");
+        return UOT_OK;
+    }
+    return fail(UOT_ERR_ARG, "the plan needs K with u and v, or C with f and g");
+}
+
+size_t uot_sinkhorn_multi_workspace_size(const uot_problem* shared, int32_t R, const uot_options* opt) {
+    MultiPlan M;
+    if (make_multi_plan(shared, R, opt, M) != UOT_OK) return 0;
+    return M.total;
+}
+
+uot_status uot_sinkhorn_multi(const uot_problem* shared, int32_t R, const double* A, const double* B,
+                              const uot_options* opt, double* U, double* V, double* losses, uot_info* info, void* ws,
+                              size_t ws_bytes, void* stream) {
+    return run_multi(shared, R, A, B, opt, U, V, losses, info, ws, ws_bytes, (hipStream_t)stream);
 }
 
 }  // extern "C"

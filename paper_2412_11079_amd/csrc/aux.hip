@@ -3,6 +3,9 @@
 //     reduction of per-workgroup column partials that Algorithm 1 performs
 //     after its thread join), with the stopping test of Section 2.1;
 //   - initialisation, objective, cost from points, Gibbs kernel build.
+#include <algorithm>
+
+#include "plan.h"
 #include "uot_common.h"
 
 namespace uot {
@@ -565,6 +568,85 @@ hipError_t launch_decode(const void* K, int k_dtype, int64_t count, double scale
         case UOT_FP8_E4M3: hipLaunchKernelGGL(decode_kernel<fp8_t>, grid, block, 0, stream, (const fp8_t*)K, count / 16, scale, out); break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Dense plan P = diag(u) K diag(v) (from a stored K and the scalings), or
+// P = exp((f_i + g_j - C_ij)/eps) (from the cost and the potentials of the
+// total scalings, the form that stays finite when u, v overflow).  One
+// 2-D grid: y over rows, x over 16-byte chunks of K / columns.
+// ---------------------------------------------------------------------------
+template <typename KT, typename PT>
+__global__ __launch_bounds__(256) void plan_from_k_kernel(const KT* __restrict__ K, int64_t ldk, int64_t n,
+                                                          int64_t m, double k_scale, const double* __restrict__ u,
+                                                          const double* __restrict__ v, PT* __restrict__ P,
+                                                          int64_t ldp) {
+    using Raw = typename KVec<KT>::raw;
+    constexpr int V = KVec<KT>::N;
+    const int64_t chunks = (m + V - 1) / V;
+    for (int64_t i = blockIdx.y; i < n; i += gridDim.y) {
+        const double ui = u[i] * k_scale;
+        const Raw* row = (const Raw*)(K + i * ldk);
+        for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < chunks; q += (int64_t)gridDim.x * 256) {
+            double x[V];
+            Unpack<KT, double>::run(row[q], x);
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const int64_t j = q * V + e;
+                if (j < m) P[i * ldp + j] = (PT)(ui * x[e] * v[j]);
+            }
+        }
+    }
+}
+
+template <typename PT>
+__global__ __launch_bounds__(256) void plan_from_cost_kernel(const double* __restrict__ C, int64_t ldc, int64_t n,
+                                                             int64_t m, double eps, const double* __restrict__ f,
+                                                             const double* __restrict__ g, PT* __restrict__ P,
+                                                             int64_t ldp) {
+    const double inv_eps = 1.0 / eps;
+    for (int64_t i = blockIdx.y; i < n; i += gridDim.y) {
+        const double fi = f[i];
+        for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < m; j += (int64_t)gridDim.x * 256)
+            P[i * ldp + j] = (PT)exp((fi + g[j] - C[i * ldc + j]) * inv_eps);
+    }
+}
+
+template <typename PT>
+static hipError_t launch_plan_k_typed(const void* K, int k_dtype, int64_t ldk, int64_t n, int64_t m, double k_scale,
+                                      const double* u, const double* v, PT* P, int64_t ldp, hipStream_t stream) {
+    const int64_t chunks_max = (m + 1) / 2;
+    dim3 grid((unsigned)std::min<int64_t>((chunks_max + 255) / 256, 64), (unsigned)std::min<int64_t>(n, 4096));
+    switch (k_dtype) {
+        case UOT_F64: hipLaunchKernelGGL((plan_from_k_kernel<double, PT>), grid, dim3(256), 0, stream, (const double*)K, ldk, n, m, k_scale, u, v, P, ldp); break;
+        case UOT_F32: hipLaunchKernelGGL((plan_from_k_kernel<float, PT>), grid, dim3(256), 0, stream, (const float*)K, ldk, n, m, k_scale, u, v, P, ldp); break;
+        case UOT_BF16: hipLaunchKernelGGL((plan_from_k_kernel<bf16_t, PT>), grid, dim3(256), 0, stream, (const bf16_t*)K, ldk, n, m, k_scale, u, v, P, ldp); break;
+        case UOT_FP8_E4M3: hipLaunchKernelGGL((plan_from_k_kernel<fp8_t, PT>), grid, dim3(256), 0, stream, (const fp8_t*)K, ldk, n, m, k_scale, u, v, P, ldp); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_plan_from_k(const void* K, int k_dtype, int64_t ldk, int64_t n, int64_t m, double k_scale,
+                              const double* u, const double* v, void* P, int plan_dtype, int64_t ldp,
+                              hipStream_t stream) {
+    if (plan_dtype == UOT_F64)
+        return launch_plan_k_typed<double>(K, k_dtype, ldk, n, m, k_scale, u, v, (double*)P, ldp, stream);
+    if (plan_dtype == UOT_F32)
+        return launch_plan_k_typed<float>(K, k_dtype, ldk, n, m, k_scale, u, v, (float*)P, ldp, stream);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_plan_from_cost(const double* C, int64_t ldc, int64_t n, int64_t m, double eps, const double* f,
+                                 const double* g, void* P, int plan_dtype, int64_t ldp, hipStream_t stream) {
+    dim3 grid((unsigned)std::min<int64_t>((m + 255) / 256, 64), (unsigned)std::min<int64_t>(n, 4096));
+    if (plan_dtype == UOT_F64)
+        hipLaunchKernelGGL(plan_from_cost_kernel<double>, grid, dim3(256), 0, stream, C, ldc, n, m, eps, f, g, (double*)P, ldp);
+    else if (plan_dtype == UOT_F32)
+        hipLaunchKernelGGL(plan_from_cost_kernel<float>, grid, dim3(256), 0, stream, C, ldc, n, m, eps, f, g, (float*)P, ldp);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

@@ -1,0 +1,75 @@
+// Internal declarations of the multi-right-hand-side solver (multi.hip).
+#pragma once
+
+#include "uot_common.h"
+
+namespace uot {
+
+// Out^T[r][i] = sum_k A[i][k] X^T[r][k]: A (rows x kdim, row-major, lda)
+// times R right-hand sides held k-contiguous (X^T, R_pad x ldx), split over
+// kdim into `splits` chunks; each chunk's FP32 sum goes to
+// part[s][r][i] (splits x R_pad x ld_part).
+struct MGemm {
+    const void* A;
+    int64_t lda;
+    int64_t rows;        // valid rows of A (rows beyond read 0)
+    int64_t rows_pad;    // multiple of the row tile
+    int64_t kdim_pad;    // multiple of the k step; A columns and X entries beyond kdim must be finite / 0
+    const void* x_hi;    // BF16 form: high parts; FP32 form: the values
+    const void* x_lo;    // BF16 form: low parts (x - hi, rounded)
+    int64_t ldx;         // elements between consecutive right-hand sides
+    int64_t r_pad;       // multiple of the column tile
+    int32_t splits;
+    int64_t kchunk;      // multiple of the k step
+    float* part;
+    int64_t ld_part;     // = rows_pad
+};
+
+// After a GEMM: S[r][i] = sum_s part[s][r][i] (FP64, fixed order), then
+//   mode 0 (update):   y = (T / (k_scale S))^fi, written to y_out (FP64,
+//                      R x ld_y) and as the next GEMM's right-hand sides
+//                      (BF16 hi/lo or FP32, R_pad x ld_next, zero padding);
+//                      optionally marg = y * k_scale S;
+//   mode 1 (marginal): marg = y_in * k_scale S.
+struct MEpi {
+    const float* part;
+    int64_t ld_part;
+    int32_t splits;
+    int64_t rows;        // valid rows (n or m)
+    int64_t R;
+    int64_t r_pad;
+    const double* target;   // R x rows (histograms as rows)
+    double* y;              // R x rows (scalings out, or in for mode 1)
+    double* marg;           // R x rows, optional
+    void* next_hi;          // R_pad x ld_next (mode 0)
+    void* next_lo;
+    int64_t ld_next;        // >= rows, multiple of 64
+    int32_t bf16;           // next right-hand sides as BF16 hi/lo (1) or FP32 (0)
+    double fi;
+    int32_t fi_is_one;
+    double k_scale;
+    int32_t mode;
+    uint32_t* flags;
+};
+
+hipError_t launch_mgemm(int bf16, const MGemm& G, hipStream_t stream);
+hipError_t launch_mepi(const MEpi& E, hipStream_t stream);
+// KT (m x ldkt) = K^T for a stored K (n x ldk), padding columns of KT zero.
+hipError_t launch_transpose(int k_dtype, const void* K, int64_t ldk, int64_t n, int64_t m, void* KT, int64_t ldkt,
+                            hipStream_t stream);
+// Right-hand sides of the first iteration: v = 1 for r < R, j < m, else 0.
+hipError_t launch_ones_rhs(int bf16, void* hi, void* lo, int64_t R, int64_t r_pad, int64_t m, int64_t ld,
+                           hipStream_t stream);
+// Per right-hand side objective (one workgroup per r) from u, v, r, c, a, b.
+hipError_t launch_multi_loss(const double* U, const double* V, const double* Rm, const double* Cm, const double* A,
+                             const double* B, int64_t n, int64_t m, int64_t R, double eps, double tau, int fi_is_one,
+                             double* losses, uint32_t* flags, hipStream_t stream);
+
+// reset != 0: clear *flags; else write info (iters, flags).
+hipError_t launch_multi_info(uot_info* info, int64_t iters, uint32_t* flags, int reset, hipStream_t stream);
+
+constexpr int kMTileRows = 128;   // rows of A per workgroup
+constexpr int kMTileCols = 128;   // right-hand sides per workgroup
+constexpr int kMStep = 16;        // k per step (BF16); the FP32 form steps by 8
+
+}  // namespace uot

@@ -1,0 +1,343 @@
+// Many right-hand sides sharing one kernel K: the two half-steps of an
+// iteration (Section 2.1's row and column rescaling, for R histogram pairs
+// at once) become two matrix products,
+//     S = K V,    U = (A / S)^fi          (n x R)
+//     W = K^T U,  V = (B / W)^fi          (m x R)
+// on the matrix cores.  K^T is stored once (a transposed copy in the
+// workspace), so both products read their big operand with the reduction
+// index contiguous.  Right-hand sides are held k-contiguous (one row per
+// histogram).
+//
+// Two forms:
+//   BF16: K stored in bfloat16; each right-hand side is split into a
+//         bfloat16 high part and the bfloat16 rounding of the remainder, and
+//         both go through v_mfma_f32_32x32x16_bf16 (products exact, FP32
+//         accumulation), so the right-hand sides keep ~16 significant bits;
+//   FP32: K and right-hand sides in FP32 through v_mfma_f32_32x32x2_f32.
+// The reduction is split over k into chunks whose FP32 sums are added in
+// FP64, in a fixed order, by the epilogue that also applies the power.
+#include <math.h>
+
+#include "multi.h"
+#include "strip.h"
+
+namespace uot {
+
+namespace {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// Workgroup: 4 waves in a 2 x 2 arrangement; each wave owns 64 rows x 64
+// right-hand sides = 2 x 2 tiles of 32 x 32.
+template <bool BF>
+__global__ __launch_bounds__(256) void mgemm_kernel(MGemm G) {
+    constexpr int EA = BF ? 2 : 4;          // bytes per element
+    constexpr int STEP = BF ? 16 : 8;       // k per step
+    constexpr int KL = BF ? 8 : 4;          // k values a lane loads per operand per step
+    const int l = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int lr = l & 31;
+    const int lh = l >> 5;
+    const int64_t row0 = (int64_t)blockIdx.y * kMTileRows + (w & 1) * 64;
+    const int64_t col0 = (int64_t)blockIdx.x * kMTileCols + (w >> 1) * 64;
+    const int64_t k_begin = (int64_t)blockIdx.z * G.kchunk;
+    int64_t k_end = k_begin + G.kchunk;
+    if (k_end > G.kdim_pad) k_end = G.kdim_pad;
+
+    const uint32_t a_bytes = (uint32_t)(G.rows * G.lda * EA);
+    const uint32_t x_bytes = (uint32_t)(G.r_pad * G.ldx * EA);
+    const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc((void*)G.A, (short)0, (int)a_bytes, kBufferWord3);
+    const __amdgpu_buffer_rsrc_t rh = __builtin_amdgcn_make_buffer_rsrc((void*)G.x_hi, (short)0, (int)x_bytes, kBufferWord3);
+    const __amdgpu_buffer_rsrc_t rl =
+        __builtin_amdgcn_make_buffer_rsrc((void*)(BF ? G.x_lo : G.x_hi), (short)0, (int)x_bytes, kBufferWord3);
+    uint32_t va[2], vx[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int64_t row = row0 + t * 32 + lr;
+        va[t] = row < G.rows ? (uint32_t)(row * G.lda * EA) : a_bytes;      // rows beyond: 0
+        vx[t] = (uint32_t)((col0 + t * 32 + lr) * G.ldx * EA);
+    }
+
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc[t][u][q] = 0.0f;
+
+    u32x4 a_cur[2], h_cur[2], lo_cur[2], a_nxt[2], h_nxt[2], lo_nxt[2];
+    auto load = [&](int64_t k, u32x4* a, u32x4* h, u32x4* lo) {
+        const uint32_t ko = (uint32_t)((k + KL * lh) * EA);
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            a[t] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(ra, (int)(va[t] + ko), 0, 0));
+            h[t] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rh, (int)(vx[t] + ko), 0, 0));
+            if constexpr (BF)
+                lo[t] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rl, (int)(vx[t] + ko), 0, 0));
+        }
+    };
+    auto compute = [&](const u32x4* a, const u32x4* h, const u32x4* lo) {
+        if constexpr (BF) {
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const bf16x8_t av = __builtin_bit_cast(bf16x8_t, a[t]);
+                    acc[t][u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, __builtin_bit_cast(bf16x8_t, h[u]),
+                                                                        acc[t][u], 0, 0, 0);
+                    acc[t][u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, __builtin_bit_cast(bf16x8_t, lo[u]),
+                                                                        acc[t][u], 0, 0, 0);
+                }
+        } else {
+            // lane half lh holds k + 4 lh + q: the q-th product pairs k + q
+            // (lanes 0-31) with k + 4 + q (lanes 32-63), the same in both operands
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+#pragma unroll
+                    for (int u = 0; u < 2; ++u)
+                        acc[t][u] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a[t][q]),
+                                                                         __uint_as_float(h[u][q]), acc[t][u], 0, 0, 0);
+        }
+    };
+
+    if (k_begin < k_end) {
+        load(k_begin, a_cur, h_cur, lo_cur);
+        for (int64_t k = k_begin; k < k_end; k += STEP) {
+            const bool more = k + STEP < k_end;
+            if (more) load(k + STEP, a_nxt, h_nxt, lo_nxt);
+            compute(a_cur, h_cur, lo_cur);
+            if (more) {
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    a_cur[t] = a_nxt[t];
+                    h_cur[t] = h_nxt[t];
+                    lo_cur[t] = lo_nxt[t];
+                }
+            }
+        }
+    }
+
+    // acc[t][u][q]: row 8 (q/4) + 4 lh + q%4 of tile t, right-hand side lr of tile u.
+    float* P = G.part + (int64_t)blockIdx.z * G.r_pad * G.ld_part;
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int64_t i0 = row0 + t * 32 + 8 * g + 4 * lh;
+                const int64_t r = col0 + u * 32 + lr;
+                f32x4 v = {acc[t][u][4 * g], acc[t][u][4 * g + 1], acc[t][u][4 * g + 2], acc[t][u][4 * g + 3]};
+                __builtin_nontemporal_store(v, (f32x4*)(P + r * G.ld_part + i0));
+            }
+}
+
+__global__ __launch_bounds__(256) void mepi_kernel(MEpi E) {
+    const int64_t q4 = E.ld_next / 4;
+    const int64_t total = E.r_pad * q4;
+    uint32_t fl = 0;
+    for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * 256) {
+        const int64_t r = idx / q4;
+        const int64_t i0 = (idx % q4) * 4;
+        double S[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int s = 0; s < E.splits; ++s) {
+            const f32x4 p = *(const f32x4*)(E.part + ((int64_t)s * E.r_pad + r) * E.ld_part + i0);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) S[e] += (double)p[e];
+        }
+        double y[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t i = i0 + e;
+            const bool valid = r < E.R && i < E.rows;
+            const double s = S[e] * E.k_scale;
+            y[e] = 0.0;
+            if (valid) {
+                const int64_t o = r * E.rows + i;
+                if (E.mode == 0) {
+                    const double tgt = E.target[o];
+                    y[e] = scale_factor(tgt, s, E.fi, E.fi_is_one, 0.0);
+                    if (tgt > 0.0 && !(s > 0.0)) fl |= UOT_FLAG_ZERO_SUM;
+                    if (!isfinite(y[e])) fl |= UOT_FLAG_NONFINITE;
+                    E.y[o] = y[e];
+                    if (E.marg) E.marg[o] = y[e] * s;
+                } else {
+                    E.marg[o] = E.y[o] * s;
+                }
+            }
+        }
+        if (E.mode == 0) {
+            const int64_t o = r * E.ld_next + i0;
+            if (E.bf16) {
+                uint16_t hi[4], lo[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    hi[e] = f64_to_bf16(y[e]);
+                    const double h = (double)__uint_as_float((uint32_t)hi[e] << 16);
+                    lo[e] = f64_to_bf16(y[e] - h);
+                }
+                uint2 hv = {(uint32_t)hi[0] | ((uint32_t)hi[1] << 16), (uint32_t)hi[2] | ((uint32_t)hi[3] << 16)};
+                uint2 lv = {(uint32_t)lo[0] | ((uint32_t)lo[1] << 16), (uint32_t)lo[2] | ((uint32_t)lo[3] << 16)};
+                *(uint2*)((uint16_t*)E.next_hi + o) = hv;
+                *(uint2*)((uint16_t*)E.next_lo + o) = lv;
+            } else {
+                f32x4 v = {(float)y[0], (float)y[1], (float)y[2], (float)y[3]};
+                *(f32x4*)((float*)E.next_hi + o) = v;
+            }
+        }
+    }
+    if (fl) atomicOr(E.flags, fl);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void transpose_kernel(const T* __restrict__ K, int64_t ldk, int64_t n, int64_t m,
+                                                        T* __restrict__ KT, int64_t ldkt) {
+    __shared__ T tile[32][33];
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;     // 32 x 8
+    for (int64_t bj = blockIdx.x; bj * 32 < m; bj += gridDim.x)
+        for (int64_t bi = blockIdx.y; bi * 32 < ldkt; bi += gridDim.y) {
+            for (int k = ty; k < 32; k += 8) {
+                const int64_t i = bi * 32 + k, j = bj * 32 + tx;
+                tile[k][tx] = (i < n && j < m) ? K[i * ldk + j] : T(0);
+            }
+            __syncthreads();
+            for (int k = ty; k < 32; k += 8) {
+                const int64_t j = bj * 32 + k, i = bi * 32 + tx;
+                if (j < m && i < ldkt) KT[j * ldkt + i] = tile[tx][k];
+            }
+            __syncthreads();
+        }
+}
+
+__global__ void ones_rhs_kernel(int bf16, uint16_t* hi16, uint16_t* lo16, float* f, int64_t R, int64_t r_pad,
+                                int64_t m, int64_t ld) {
+    const int64_t total = r_pad * ld;
+    for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * 256) {
+        const int64_t r = idx / ld, j = idx % ld;
+        const bool one = r < R && j < m;
+        if (bf16) {
+            hi16[idx] = one ? (uint16_t)0x3f80u : (uint16_t)0;
+            lo16[idx] = 0;
+        } else {
+            f[idx] = one ? 1.0f : 0.0f;
+        }
+    }
+}
+
+__device__ __forceinline__ double kl_term_m(double x, double y) {
+    if (x > 0.0) return x * log(x / y) - x + y;
+    return y;
+}
+
+__device__ double block_sum_256(double x, double* sh) {
+    x = wave_sum_f64(x);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = x;
+    __syncthreads();
+    return sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+__global__ __launch_bounds__(256) void multi_loss_kernel(const double* U, const double* V, const double* Rm,
+                                                         const double* Cm, const double* A, const double* B, int64_t n,
+                                                         int64_t m, double eps, double tau, int fi_is_one,
+                                                         double* losses, uint32_t* flags) {
+    __shared__ double sh[4];
+    const int64_t r = blockIdx.x;
+    double rlu = 0.0, rs = 0.0, klr = 0.0, clv = 0.0, klc = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+        const double ri = Rm[r * n + i];
+        if (ri > 0.0) rlu += ri * log(U[r * n + i]);
+        rs += ri;
+        klr += kl_term_m(ri, A[r * n + i]);
+    }
+    for (int64_t j = threadIdx.x; j < m; j += 256) {
+        const double cj = Cm[r * m + j];
+        if (cj > 0.0) clv += cj * log(V[r * m + j]);
+        klc += kl_term_m(cj, B[r * m + j]);
+    }
+    rlu = block_sum_256(rlu, sh);
+    rs = block_sum_256(rs, sh);
+    clv = block_sum_256(clv, sh);
+    double L = eps * (rlu + clv - rs);
+    if (!fi_is_one) {
+        klr = block_sum_256(klr, sh);
+        klc = block_sum_256(klc, sh);
+        L += tau * (klr + klc);
+    }
+    if (threadIdx.x == 0) {
+        losses[r] = L;
+        if (!isfinite(L)) atomicOr(flags, UOT_FLAG_NONFINITE);
+    }
+}
+
+__global__ void multi_info_kernel(uot_info* info, int64_t iters, uint32_t* flags, int reset) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (reset) {
+        *flags = 0u;
+        return;
+    }
+    info->iters = iters;
+    info->err = 0.0;
+    info->absorptions = 0;
+    info->flags = *flags;
+}
+
+}  // namespace
+
+hipError_t launch_multi_info(uot_info* info, int64_t iters, uint32_t* flags, int reset, hipStream_t stream) {
+    hipLaunchKernelGGL(multi_info_kernel, dim3(1), dim3(64), 0, stream, info, iters, flags, reset);
+    return hipGetLastError();
+}
+
+hipError_t launch_mgemm(int bf16, const MGemm& G, hipStream_t stream) {
+    dim3 grid((unsigned)(G.r_pad / kMTileCols), (unsigned)(G.rows_pad / kMTileRows), (unsigned)G.splits);
+    if (bf16)
+        hipLaunchKernelGGL(mgemm_kernel<true>, grid, dim3(256), 0, stream, G);
+    else
+        hipLaunchKernelGGL(mgemm_kernel<false>, grid, dim3(256), 0, stream, G);
+    return hipGetLastError();
+}
+
+hipError_t launch_mepi(const MEpi& E, hipStream_t stream) {
+    const int64_t total = E.r_pad * (E.ld_next / 4);
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(mepi_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, E);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose(int k_dtype, const void* K, int64_t ldk, int64_t n, int64_t m, void* KT, int64_t ldkt,
+                            hipStream_t stream) {
+    dim3 grid((unsigned)std::min<int64_t>((m + 31) / 32, 1024), (unsigned)std::min<int64_t>((ldkt + 31) / 32, 1024));
+    switch (k_dtype) {
+        case UOT_F64: hipLaunchKernelGGL(transpose_kernel<uint64_t>, grid, dim3(256), 0, stream, (const uint64_t*)K, ldk, n, m, (uint64_t*)KT, ldkt); break;
+        case UOT_F32: hipLaunchKernelGGL(transpose_kernel<uint32_t>, grid, dim3(256), 0, stream, (const uint32_t*)K, ldk, n, m, (uint32_t*)KT, ldkt); break;
+        case UOT_BF16: hipLaunchKernelGGL(transpose_kernel<uint16_t>, grid, dim3(256), 0, stream, (const uint16_t*)K, ldk, n, m, (uint16_t*)KT, ldkt); break;
+        case UOT_FP8_E4M3: hipLaunchKernelGGL(transpose_kernel<uint8_t>, grid, dim3(256), 0, stream, (const uint8_t*)K, ldk, n, m, (uint8_t*)KT, ldkt); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_ones_rhs(int bf16, void* hi, void* lo, int64_t R, int64_t r_pad, int64_t m, int64_t ld,
+                           hipStream_t stream) {
+    int64_t blocks = (r_pad * ld + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(ones_rhs_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, bf16, (uint16_t*)hi,
+                       (uint16_t*)lo, (float*)hi, R, r_pad, m, ld);
+    return hipGetLastError();
+}
+
+hipError_t launch_multi_loss(const double* U, const double* V, const double* Rm, const double* Cm, const double* A,
+                             const double* B, int64_t n, int64_t m, int64_t R, double eps, double tau, int fi_is_one,
+                             double* losses, uint32_t* flags, hipStream_t stream) {
+    hipLaunchKernelGGL(multi_loss_kernel, dim3((unsigned)R), dim3(256), 0, stream, U, V, Rm, Cm, A, B, n, m, eps, tau,
+                       fi_is_one, losses, flags);
+    return hipGetLastError();
+}
+
+}  // namespace uot

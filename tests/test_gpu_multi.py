@@ -1,0 +1,125 @@
+"""R histogram pairs sharing one kernel, on the matrix cores, against the
+oracle run on each pair alone (independent instances of the loop) and
+against the single-pair GPU path on the same kernel.
+
+Bars (relative, entrywise on u, v and the loss):
+  same stored K, FP32 form: the matrix cores sum FP32 products in FP32
+  over k-chunks (FP64 across chunks), the right-hand side is rounded to
+  FP32 (2^-24); with the fixed point's amplification 1/(1 - fi^2) ~ 11 at
+  eps 0.05, tau 1 this is held to 2e-6;
+  same stored K, BF16 form: the right-hand side keeps ~16 bits (high part
+  plus rounded remainder, error <= 2^-17 relative), amplified: 2e-4;
+  BF16 K against the exact FP64 kernel: the BF16 storage bar 2e-3
+  (normwise), entrywise reported."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from gpu_helpers import rel_err, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+import paper_2412_11079_amd as uot  # noqa: E402
+
+
+def _stored(C, eps, storage, dtype):
+    K = oracle.kernel(C, eps)
+    Kr = K if storage is None else oracle.round_storage(K, storage)
+    n, m = K.shape
+    ldk = (m + 63) // 64 * 64
+    Kp = np.zeros((n, ldk))
+    Kp[:, :m] = Kr
+    return Kr, torch.from_numpy(Kp).to("cuda").to(dtype)
+
+
+def _compare(res, Kr, A, B, eps, tau, T, idx, bar, label):
+    U, V, L = res.U.cpu().numpy(), res.V.cpu().numpy(), res.loss.cpu().numpy()
+    worst = 0.0
+    for r in idx:
+        ref = oracle.sinkhorn(Kr, A[r], B[r], eps, tau, T)
+        e = max(rel_err(U[r], ref.u), rel_err(V[r], ref.v), abs(L[r] - ref.loss) / abs(ref.loss))
+        worst = max(worst, e)
+        assert e <= bar, (label, r, e)
+    say(f"  {label}: {len(idx)} right-hand sides, worst {worst:.3e}")
+    return worst
+
+
+@pytest.mark.parametrize("dtype,storage,bar", [(torch.float32, "f32", 2e-6), (torch.bfloat16, "bf16", 2e-4)])
+def test_multi_matches_oracle_on_same_kernel(dtype, storage, bar):
+    base, A, B = workloads.multi_rhs(n=300, m=257, R=40, max_iter=50)
+    A, B = A.T.copy(), B.T.copy()
+    C = oracle.cost_points(base.x, base.y, base.cost_kind)
+    Kr, Kd = _stored(C, base.eps, storage, dtype)
+    res = uot.sinkhorn_multi(Kd, to_dev(A), to_dev(B), m=base.m, eps=base.eps, tau=base.tau, max_iter=50)
+    torch.cuda.synchronize()
+    assert res.info()["flags"] == 0 and res.info()["iters"] == 50
+    _compare(res, Kr, A, B, base.eps, base.tau, 50, range(40), bar, str(dtype))
+
+
+def test_multi_bf16_storage_error_against_exact_kernel():
+    base, A, B = workloads.multi_rhs(n=513, m=1000, R=16, max_iter=80)
+    A, B = A.T.copy(), B.T.copy()
+    C = oracle.cost_points(base.x, base.y, base.cost_kind)
+    K = oracle.kernel(C, base.eps)
+    _, Kd = _stored(C, base.eps, "bf16", torch.bfloat16)
+    res = uot.sinkhorn_multi(Kd, to_dev(A), to_dev(B), m=base.m, eps=base.eps, tau=base.tau, max_iter=80)
+    U, V, L = res.U.cpu().numpy(), res.V.cpu().numpy(), res.loss.cpu().numpy()
+    worst_n = worst_e = 0.0
+    for r in range(16):
+        ref = oracle.sinkhorn(K, A[r], B[r], base.eps, base.tau, 80)
+        nu = np.linalg.norm(U[r] - ref.u) / np.linalg.norm(ref.u)
+        nv = np.linalg.norm(V[r] - ref.v) / np.linalg.norm(ref.v)
+        el = abs(L[r] - ref.loss) / abs(ref.loss)
+        worst_n = max(worst_n, nu, nv, el)
+        worst_e = max(worst_e, rel_err(U[r], ref.u), rel_err(V[r], ref.v))
+    say(f"  BF16 K vs exact kernel: normwise {worst_n:.3e}, entrywise {worst_e:.3e}")
+    assert worst_n <= 2e-3
+
+
+def test_multi_matches_single_pair_gpu_path():
+    """Each right-hand side against uot_sinkhorn on the same FP32 K (both
+    FP32 arithmetic on the GPU)."""
+    base, A, B = workloads.multi_rhs(n=700, m=640, R=8, max_iter=40)
+    A, B = A.T.copy(), B.T.copy()
+    Cd = uot.cost_from_points(to_dev(base.x), to_dev(base.y), base.cost_kind)
+    Kd = uot.kernel_from_cost(Cd, base.eps, torch.float32)
+    res = uot.sinkhorn_multi(Kd, to_dev(A), to_dev(B), m=base.m, eps=base.eps, tau=base.tau, max_iter=40)
+    U, V = res.U.cpu().numpy(), res.V.cpu().numpy()
+    for r in range(8):
+        single = uot.sinkhorn(to_dev(A[r]), to_dev(B[r]), Kd, m=base.m, eps=base.eps, tau=base.tau, max_iter=40)
+        e = max(rel_err(U[r], single.u.cpu().numpy()), rel_err(V[r], single.v.cpu().numpy()),
+                abs(float(res.loss[r].cpu()) - float(single.loss.cpu())) / abs(float(single.loss.cpu())))
+        assert e <= 4e-6, (r, e)
+
+
+def test_multi_argument_errors():
+    base, A, B = workloads.multi_rhs(n=64, m=64, R=4, max_iter=5)
+    A, B = A.T.copy(), B.T.copy()
+    C = oracle.cost_points(base.x, base.y, base.cost_kind)
+    _, K64 = _stored(C, base.eps, None, torch.float64)
+    with pytest.raises(ValueError):
+        uot.sinkhorn_multi(K64, to_dev(A), to_dev(B), eps=base.eps, tau=base.tau, max_iter=5)
+    _, K32 = _stored(C, base.eps, "f32", torch.float32)
+    with pytest.raises(uot.UOTError) as e:
+        uot.sinkhorn_multi(K32, to_dev(A), to_dev(B), eps=base.eps, tau=base.tau, max_iter=0)
+    assert e.value.status == 1
+
+
+def test_multi_full_size_sampled():
+    """8192 x 8192 cosine kernel, 256 pairs, 200 iterations, BF16 K: every
+    pair finite with flags 0; 4 sampled pairs against the oracle on the same
+    stored kernel (BF16 form bar)."""
+    base, A, B = workloads.multi_rhs()
+    A, B = A.T.copy(), B.T.copy()
+    say("  kernel on the host ...")
+    C = oracle.cost_points(base.x, base.y, base.cost_kind)
+    Kr, Kd = _stored(C, base.eps, "bf16", torch.bfloat16)
+    del C
+    say("  solving 256 pairs ...")
+    res = uot.sinkhorn_multi(Kd, to_dev(A), to_dev(B), m=base.m, eps=base.eps, tau=base.tau, max_iter=200)
+    torch.cuda.synchronize()
+    assert res.info()["flags"] == 0
+    assert torch.isfinite(res.U).all() and torch.isfinite(res.V).all() and torch.isfinite(res.loss).all()
+    _compare(res, Kr, A, B, base.eps, base.tau, 200, [0, 77, 128, 255], 2e-4, "full size")
