@@ -10,7 +10,11 @@ Prints ONE JSON line (rank 0).  Besides the contract fields it carries:
                 over its average launch duration (HIP events recorded by
                 the library on the launch stream during the timed steps);
   cpu_baseline  the FP64 oracle on the host cores, bounded sample;
-  plain         the plain two-pass form on the same GPU (same steps).
+  plain         the plain two-pass form on the same GPU (same steps);
+  fwd_bwd       forward + reverse pass of the differentiation workload;
+  batched       1024 uneven problems in one persistent launch;
+  multi         256 histogram pairs sharing one 8192^2 kernel (matrix cores);
+  precision     65536 x 8192 with BF16 / FP8 / FP32 K and absorption.
 """
 from __future__ import annotations
 
@@ -44,6 +48,10 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     p.add_argument("--no-plain", action="store_true", help="skip the plain two-pass comparison")
     p.add_argument("--no-grad", action="store_true", help="skip the forward+backward timing")
+    p.add_argument("--no-batched", action="store_true", help="skip the batched-problems timing")
+    p.add_argument("--no-multi", action="store_true", help="skip the multi-right-hand-side timing")
+    p.add_argument("--no-precision", action="store_true", help="skip the low-precision timing")
+    p.add_argument("--only", default="", help="comma list of sections to run alone (profiling)")
     p.add_argument("--calib-copy", action="store_true",
                    help="only run a plain device copy of known size (counter calibration)")
     return p.parse_args()
@@ -77,8 +85,8 @@ def traffic_from_counters():
 def main():
     args = parse()
     if args.gpus != 1:
-        sys.exit("bench.py measures one GPU: every box here has a single MI355X "
-                 "(--gpus must be 1; the multi-GPU sharding is described in DESIGN.md)")
+        sys.exit("bench.py measures one GPU (--gpus 1): this path runs on a single MI355X; "
+                 "a run over several GPUs is not built")
     import numpy as np
     import torch
 
@@ -87,6 +95,12 @@ def main():
 
     dev = "cuda:0"
     torch.cuda.set_device(0)
+
+    if args.only:
+        sections = {"grad": fwd_bwd, "batched": batched, "multi": multi, "precision": precision}
+        res = {k: sections[k](uot, workloads, torch, dev, args) for k in args.only.split(",")}
+        print(json.dumps(res), flush=True)
+        return
 
     if args.calib_copy:
         nbytes = 1 << 30
@@ -176,6 +190,12 @@ def main():
                         "speedup_fused_over_plain": round(fused["iters_per_s"] / plain["iters_per_s"], 3)}
     if not args.no_grad:
         out["fwd_bwd"] = fwd_bwd(uot, workloads, torch, dev, args)
+    if not args.no_batched:
+        out["batched"] = batched(uot, workloads, torch, dev, args)
+    if not args.no_multi:
+        out["multi"] = multi(uot, workloads, torch, dev, args)
+    if not args.no_precision:
+        out["precision"] = precision(uot, workloads, torch, dev, args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)
@@ -226,26 +246,168 @@ def fwd_bwd(uot, workloads, torch, dev, args):
             "k_passes": passes, "k_bytes_tb_s": round(passes * kb / ((f_ms + b_ms) * 1e-3) / 1e12, 3)}
 
 
-def cpu_baseline(prob):
-    """FP64 oracle on the host cores: kernel built once (untimed), then two
-    runs of T1 and T2 iterations; the rate is (T2 - T1) / (t2 - t1)."""
-    import numpy as np
+def _events(torch, n=2):
+    return [torch.cuda.Event(enable_timing=True) for _ in range(n)]
 
+
+def batched(uot, workloads, torch, dev, args):
+    """Batching workload: 1024 problems, n, m ~ U[16, 2048], 300-D cosine,
+    FP32 K (built before the timed region), 200 iterations, one persistent
+    launch per solve (replayed from a HIP graph).  Compared with the plain
+    FP32 form on the same GPU: the same problems solved one by one with the
+    single-problem fused path (a sample, scaled by work)."""
+    import numpy as np
+    probs = workloads.batched()
+    Ks, As, Bs = [], [], []
+    for p in probs:
+        C = uot.cost_from_points(torch.from_numpy(p.x).to(dev), torch.from_numpy(p.y).to(dev), p.cost_kind)
+        Ks.append(uot.kernel_from_cost(C, p.eps, torch.float32))
+        del C
+        As.append(torch.from_numpy(p.a).to(dev))
+        Bs.append(torch.from_numpy(p.b).to(dev))
+    T = probs[0].max_iter
+    solver = uot.BatchedSolver(Ks, As, Bs, eps=probs[0].eps, tau=probs[0].tau, max_iter=T, tune=1, trace=True)
+    solver.run()
+    torch.cuda.synchronize()
+    tail = solver.tail_idle_fraction()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        solver.run()
+    torch.cuda.current_stream().wait_stream(s)
+    with torch.cuda.graph(g):
+        solver.run()
+    reps = max(min(args.steps, 5), 1)
+    e0, e1 = _events(torch)
+    g.replay()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    flags = [solver.result().info(i)["flags"] for i in (0, len(probs) - 1)]
+    assert flags == [0, 0], flags
+    elems = sum(p.n * p.m for p in probs)
+    kbytes = elems * 4 * (T + 1)        # T iterations + the marginal sweep, K read once each
+    # plain FP32 form: single-problem fused solves of a sample, scaled by work
+    rng = np.random.default_rng(0)
+    sample = rng.choice(len(probs), 32, replace=False)
+    for i in sample[:2]:
+        uot.sinkhorn(As[i], Bs[i], Ks[i], m=probs[i].m, eps=probs[i].eps, tau=probs[i].tau, max_iter=T)
+    torch.cuda.synchronize()
+    e0.record()
+    for i in sample:
+        uot.sinkhorn(As[i], Bs[i], Ks[i], m=probs[i].m, eps=probs[i].eps, tau=probs[i].tau, max_iter=T)
+    e1.record()
+    torch.cuda.synchronize()
+    single_ms = e0.elapsed_time(e1) * elems / sum(probs[i].n * probs[i].m for i in sample)
+    return {"workload": f"batching: {len(probs)} problems, n,m ~ U[16,2048], 300-D cosine, FP32 K, eps=0.05, "
+                        f"tau=1, {T} iterations, one persistent launch (HIP graph replay)",
+            "ms_per_solve": round(ms, 3), "problem_iters_per_s": round(len(probs) * T / (ms * 1e-3), 1),
+            "k_bytes_tb_s": round(kbytes / (ms * 1e-3) / 1e12, 3), "tail_idle_fraction": round(tail, 4),
+            "plain_one_by_one_ms_est": round(single_ms, 1),
+            "speedup_over_one_by_one": round(single_ms / ms, 2)}
+
+
+def multi(uot, workloads, torch, dev, args):
+    """Shared 8192^2 cosine kernel, 256 histogram pairs, 200 iterations on
+    the matrix cores (BF16 K with hi/lo right-hand sides, and FP32 K).
+    Algorithmic work 2 products x 2 n m R flops per iteration.  Compared
+    with the plain FP32 form: single-pair fused solves on the same GPU."""
+    base, A, B = workloads.multi_rhs()
+    C = uot.cost_from_points(torch.from_numpy(base.x).to(dev), torch.from_numpy(base.y).to(dev), base.cost_kind)
+    At = torch.from_numpy(A.T.copy()).to(dev)
+    Bt = torch.from_numpy(B.T.copy()).to(dev)
+    T = base.max_iter
+    R = A.shape[1]
+    flops = 2 * 2.0 * base.n * base.m * R
+    out = {"workload": f"multi-RHS: shared {base.n}x{base.m} cosine kernel, R={R} pairs Dirichlet(0.5), "
+                       f"eps=0.05, tau=1, {T} iterations", "flops_per_iter": flops}
+    for name, dt in (("bf16", torch.bfloat16), ("f32", torch.float32)):
+        K = uot.kernel_from_cost(C, base.eps, dt)
+        for variant, tune in (("", 0), ("_lds", 2)):
+            uot.sinkhorn_multi(K, At, Bt, m=base.m, eps=base.eps, tau=base.tau, max_iter=2, tune=tune)
+            torch.cuda.synchronize()
+            e0, e1 = _events(torch)
+            e0.record()
+            r = uot.sinkhorn_multi(K, At, Bt, m=base.m, eps=base.eps, tau=base.tau, max_iter=T, tune=tune)
+            e1.record()
+            torch.cuda.synchronize()
+            assert r.info()["flags"] == 0
+            ms = e0.elapsed_time(e1)
+            out[name + variant] = {"ms_per_solve": round(ms, 3), "ms_per_iter": round(ms / T, 4),
+                                   "tflop_s": round(flops * T / (ms * 1e-3) / 1e12, 2),
+                                   "pair_iters_per_s": round(R * T / (ms * 1e-3), 1)}
+        del K
+    K = uot.kernel_from_cost(C, base.eps, torch.float32)
+    a0, b0 = At[0].contiguous(), Bt[0].contiguous()
+    uot.sinkhorn(a0, b0, K, m=base.m, eps=base.eps, tau=base.tau, max_iter=10)
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch)
+    e0.record()
+    for r in range(4):
+        uot.sinkhorn(At[r].contiguous(), Bt[r].contiguous(), K, m=base.m, eps=base.eps, tau=base.tau, max_iter=T)
+    e1.record()
+    torch.cuda.synchronize()
+    single = e0.elapsed_time(e1) / 4 * R
+    out["plain_fp32_one_pair_at_a_time_ms_est"] = round(single, 1)
+    out["speedup_bf16_over_plain"] = round(single / out["bf16"]["ms_per_solve"], 2)
+    out["speedup_f32_over_plain"] = round(single / out["f32"]["ms_per_solve"], 2)
+    return out
+
+
+def precision(uot, workloads, torch, dev, args):
+    """Precision workload at full size (65536 x 8192, eps 1e-3, absorption
+    above 30 checked every 10 iterations, 2000 iterations) with the kernel
+    stored in FP32, BF16 and FP8; iterations/s and K stream rate of each."""
+    prob = workloads.precision()
+    C = uot.cost_from_points(torch.from_numpy(prob.x).to(dev), torch.from_numpy(prob.y).to(dev),
+                             prob.cost_kind, prob.normalize_max)
+    a = torch.from_numpy(prob.a).to(dev)
+    b = torch.from_numpy(prob.b).to(dev)
+    out = {"workload": f"precision: {prob.n}x{prob.m}, 16-D normal points, eps={prob.eps}, tau={prob.tau}, "
+                       f"{prob.max_iter} iterations, absorption at |log| > 30 checked every 10"}
+    for name, dt, eb in (("f32", torch.float32, 4), ("bf16", torch.bfloat16, 2), ("fp8", torch.float8_e4m3fn, 1)):
+        e0, e1 = _events(torch)
+        e0.record()
+        r = uot.sinkhorn(a, b, None, C=C, k_dtype=dt, eps=prob.eps, tau=prob.tau, max_iter=prob.max_iter,
+                         absorb_log_threshold=30.0, check_every=10, profile=True)
+        e1.record()
+        torch.cuda.synchronize()
+        info = r.info()
+        ms = e0.elapsed_time(e1)
+        p = r.profile
+        pass_us = p["fused_ms"] * 1e3 / max(p["fused_launches"], 1)
+        out[name] = {"ms_per_solve": round(ms, 2), "iters_per_s": round(prob.max_iter / (ms * 1e-3), 1),
+                     "pass_us": round(pass_us, 2), "pass_tb_s": round(prob.n * prob.m * eb / (pass_us * 1e-6) / 1e12, 3),
+                     "absorptions": info["absorptions"], "flags": info["flags"]}
+    return out
+
+
+def cpu_baseline(prob):
+    """FP64 oracle on the host cores: kernel built once (untimed), then a
+    short run of T1 iterations and a run of T2 iterations sized to about
+    10 s; the rate is (T2 - T1) / (d2 - d1), which cancels per-call setup."""
     import oracle
     C = oracle.cost_points(prob.x, prob.y, prob.cost_kind, prob.normalize_max)
     K = oracle.kernel(C, prob.eps)
     del C
-    T1, T2 = 2, 12
-    t0 = time.perf_counter()
+    T1 = 2
+    a0 = time.perf_counter()
     oracle.sinkhorn(K, prob.a, prob.b, prob.eps, prob.tau, T1)
-    t1 = time.perf_counter()
+    d1 = time.perf_counter() - a0
+    T2 = T1 + max(10, int(10.0 / max(d1 / T1, 1e-3)))
+    b0 = time.perf_counter()
     oracle.sinkhorn(K, prob.a, prob.b, prob.eps, prob.tau, T2)
-    t2 = time.perf_counter()
-    rate = (T2 - T1) / ((t2 - t1) - (t1 - t0))
+    d2 = time.perf_counter() - b0
+    rate = (T2 - T1) / (d2 - d1)
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": round(rate, 3), "unit": "iters/s", "cores": cores, "kind": "oracle",
             "sample": f"headline workload at full size ({prob.n}x{prob.m}, FP64 K), {T2}-iteration run minus "
-                      f"{T1}-iteration run (kernel build excluded); wall {t2 - t0:.1f} s"}
+                      f"{T1}-iteration run (kernel build excluded); wall {d1 + d2:.1f} s"}
 
 
 if __name__ == "__main__":

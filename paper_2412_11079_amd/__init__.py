@@ -265,7 +265,7 @@ class MultiResult:
 
 
 def sinkhorn_multi(K: torch.Tensor, A: torch.Tensor, B: torch.Tensor, *, m: Optional[int] = None, eps: float,
-                   tau: float, max_iter: int) -> MultiResult:
+                   tau: float, max_iter: int, tune: int = 0) -> MultiResult:
     """R histogram pairs sharing K (include/uot.h, uot_sinkhorn_multi).
     K: (n, ldk) FP32 or BF16; A: (R, n), B: (R, m) FP64, one histogram per row."""
     if K.dtype not in (torch.float32, torch.bfloat16):
@@ -289,6 +289,7 @@ def sinkhorn_multi(K: torch.Tensor, A: torch.Tensor, B: torch.Tensor, *, m: Opti
     opt.max_iter = int(max_iter)
     opt.check_every = 1
     opt.fused = 1
+    opt.tune = int(tune)
     L = _lib.lib()
     need = L.uot_sinkhorn_multi_workspace_size(ctypes.byref(prob), R, ctypes.byref(opt))
     if need == 0:

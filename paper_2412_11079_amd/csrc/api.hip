@@ -1034,7 +1034,7 @@ MultiGemmShape multi_gemm_shape(int64_t rows, int64_t kdim_pad, int64_t r_pad) {
     g.kdim_pad = kdim_pad;
     const int64_t tiles = (r_pad / kMTileCols) * (g.rows_pad / kMTileRows);
     int64_t splits = std::max<int64_t>(1, std::min<int64_t>(kdim_pad / 256, (1024 + tiles - 1) / tiles));
-    g.kchunk = round_up((kdim_pad + splits - 1) / splits, kMStep);
+    g.kchunk = round_up((kdim_pad + splits - 1) / splits, 64);     // whole stages of every product variant
     g.splits = (int32_t)((kdim_pad + g.kchunk - 1) / g.kchunk);
     return g;
 }
@@ -1146,6 +1146,7 @@ uot_status run_multi(const uot_problem* p, int32_t R, const double* A, const dou
     rowg.kchunk = M.row.kchunk;
     rowg.part = part;
     rowg.ld_part = M.row.rows_pad;
+    rowg.variant = o->tune == 2 ? 1 : 0;      // 0: per-wave fragment loads (default); 1: LDS-staged tiles
     MGemm colg = rowg;
     colg.A = KT;
     colg.lda = M.ldn;

@@ -47,29 +47,44 @@ hipError_t launch_init(double* u, int64_t n, const double* u0, double* v, int64_
 // Column finalize: w = sum over strips of the partials (fixed order, FP64),
 // v = (b / w)^fi, c = v * w, and per-block sums of |c - c_prev| and |c| for
 // the stopping test (evaluated by the next iteration's first pass).
-// Block: 256 threads over 16 columns.  Thread t reads 4 adjacent columns
-// (one 16-byte chunk) of strips t/4, t/4 + 64, ... with all loads of a
-// group of 8 strips issued before any add; the 64 strip phases are then
+// Block: 256 threads over 64 columns.  Thread t reads 4 adjacent columns
+// (one 16-byte chunk) of strips t/16, t/16 + 16, ... with all loads of a
+// group of 8 strips issued before any add; the 16 strip phases are then
 // combined in LDS in a fixed order (one lane per column).
 // ---------------------------------------------------------------------------
-constexpr int FIN_COLS = 16;
+constexpr int FIN_COLS = 64;
 constexpr int FIN_THREADS = 256;
-constexpr int FIN_PHASES = FIN_THREADS / (FIN_COLS / 4);   // 64
+constexpr int FIN_PHASES = FIN_THREADS / (FIN_COLS / 4);   // 16
 
 int finalize_blocks(int64_t m) { return (int)((m + FIN_COLS - 1) / FIN_COLS); }
 
+// Each wave reads 4 strips x 256 contiguous bytes per load; the per-column
+// inputs and the stop flag are requested before the partials are summed so
+// that their latency overlaps.
 template <typename AT>
 __global__ __launch_bounds__(FIN_THREADS) void finalize_kernel(FinLaunch F) {
     __shared__ double part[FIN_PHASES][FIN_COLS + 1];
     Ctrl* ctrl = F.ctrl;
-    if (!F.marginal_only && ld_volatile_u32(&ctrl->done)) return;
-
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int cg = tid & (FIN_COLS / 4 - 1);   // 4-column group within the block
     const int ph = tid / (FIN_COLS / 4);       // strip phase
     const int64_t c0 = (int64_t)blockIdx.x * FIN_COLS + 4 * cg;
+    const int64_t j = (int64_t)blockIdx.x * FIN_COLS + lane;     // wave 0's column
+    const bool own = wave == 0 && j < F.m;
+    uint32_t done = 0;
+    double bj = 0.0, cp = 0.0, gp = 0.0, vin = 0.0;
+    if (own) {
+        if (!F.marginal_only) {
+            done = ld_volatile_u32(&ctrl->done);
+            bj = F.b[j];
+            cp = F.cprev[j];
+            if (F.gpot) gp = F.gpot[j];
+        } else if (F.c_out) {
+            vin = F.v[j];
+        }
+    }
     const AT* P = (const AT*)F.partials + c0;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     if (c0 < F.m) {
@@ -96,29 +111,24 @@ __global__ __launch_bounds__(FIN_THREADS) void finalize_kernel(FinLaunch F) {
     for (int e = 0; e < 4; ++e) part[ph][4 * cg + e] = acc[e];
     __syncthreads();
     if (wave != 0) return;
+    if (!F.marginal_only && __builtin_amdgcn_readfirstlane(done)) return;
 
-    // lanes >= FIN_COLS carry no column; they take part in the wave sums with zeros
-    const int64_t j = (lane < FIN_COLS) ? (int64_t)blockIdx.x * FIN_COLS + lane : F.m;
     double w = 0.0;
-    if (lane < FIN_COLS) {
-#pragma unroll 16
-        for (int k = 0; k < FIN_PHASES; ++k) w += part[k][lane];
-        w *= F.k_scale;
-    }
+#pragma unroll
+    for (int k = 0; k < FIN_PHASES; ++k) w += part[k][lane];
+    w *= F.k_scale;
 
     double dsum = 0.0, csum = 0.0;
-    if (j < F.m) {
+    if (own) {
         if (F.w_out) F.w_out[j] = w;
         if (F.marginal_only) {
-            if (F.c_out) F.c_out[j] = F.v[j] * w;
+            if (F.c_out) F.c_out[j] = vin * w;
             return;
         }
-        const double bj = F.b[j];
-        double shift = F.gpot ? -(1.0 - F.fi) * F.gpot[j] * F.inv_eps : 0.0;
+        double shift = F.gpot ? -(1.0 - F.fi) * gp * F.inv_eps : 0.0;
         double vj = scale_factor(bj, w, F.fi, F.fi_is_one, shift);
         F.v[j] = vj;
         double cj = vj * w;
-        double cp = F.cprev[j];
         F.cprev[j] = cj;
         dsum = fabs(cj - cp);
         csum = fabs(cj);

@@ -136,6 +136,150 @@ __global__ __launch_bounds__(256) void mgemm_kernel(MGemm G) {
             }
 }
 
+// Same product with the workgroup's operand tiles staged through LDS
+// (double-buffered, one barrier per stage): each A row and each
+// right-hand side is fetched from memory once per workgroup and read by
+// the two waves that need it from LDS.  Stage: BK = 32 (BF16) or 16 (FP32)
+// values of k, i.e. 64 bytes per row; LDS rows are padded to 80 bytes so
+// the 16-byte fragment reads of 32 consecutive rows hit distinct banks.
+template <bool BF>
+__global__ __launch_bounds__(256) void mgemm_lds_kernel(MGemm G) {
+    constexpr int EA = BF ? 2 : 4;
+    constexpr int BK = 64 / EA;                 // k per stage
+    constexpr int ROWB = 80;                    // LDS bytes per staged row
+    constexpr int NPL = BF ? 2 : 1;             // right-hand-side planes
+    constexpr int A_BYTES = kMTileRows * ROWB;
+    constexpr int X_BYTES = kMTileCols * ROWB;
+    constexpr int STAGE = A_BYTES + NPL * X_BYTES;
+    __shared__ __align__(16) unsigned char lds[2 * STAGE];
+
+    const int tid = threadIdx.x;
+    const int l = tid & 63;
+    const int w = tid >> 6;
+    const int lr = l & 31;
+    const int lh = l >> 5;
+    const int wm = w & 1, wn = w >> 1;
+    const int64_t tile_r = (int64_t)blockIdx.y * kMTileRows;
+    const int64_t tile_c = (int64_t)blockIdx.x * kMTileCols;
+    const int64_t k_begin = (int64_t)blockIdx.z * G.kchunk;
+    int64_t k_end = k_begin + G.kchunk;
+    if (k_end > G.kdim_pad) k_end = G.kdim_pad;
+
+    const uint32_t a_bytes = (uint32_t)(G.rows * G.lda * EA);
+    const uint32_t x_bytes = (uint32_t)(G.r_pad * G.ldx * EA);
+    const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc((void*)G.A, (short)0, (int)a_bytes, kBufferWord3);
+    const __amdgpu_buffer_rsrc_t rx0 = __builtin_amdgcn_make_buffer_rsrc((void*)G.x_hi, (short)0, (int)x_bytes, kBufferWord3);
+    const __amdgpu_buffer_rsrc_t rx1 =
+        __builtin_amdgcn_make_buffer_rsrc((void*)(BF ? G.x_lo : G.x_hi), (short)0, (int)x_bytes, kBufferWord3);
+
+    // Staging map: 16-byte chunk c of a stage = row c/4, bytes 16 (c%4).
+    // A: 512 chunks (2 per thread); X: 512 per plane (2 per thread per plane).
+    uint32_t ga[2], gx[2];
+    int la[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int c = tid + 256 * q;
+        const int row = c >> 2, kc = c & 3;
+        const int64_t grow = tile_r + row;
+        ga[q] = grow < G.rows ? (uint32_t)(grow * G.lda * EA + kc * 16) : a_bytes;
+        gx[q] = (uint32_t)((tile_c + row) * G.ldx * EA + kc * 16);
+        la[q] = row * ROWB + kc * 16;
+    }
+    u32x4 pa[2], px[NPL][2];
+    auto fetch = [&](int64_t k) {
+        const uint32_t ko = (uint32_t)(k * EA);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            pa[q] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(ra, (int)(ga[q] + ko), 0, 0));
+            px[0][q] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rx0, (int)(gx[q] + ko), 0, 0));
+            if constexpr (BF)
+                px[NPL - 1][q] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rx1, (int)(gx[q] + ko), 0, 0));
+        }
+    };
+    auto stash = [&](int buf) {
+        unsigned char* base = lds + buf * STAGE;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            *(u32x4*)(base + la[q]) = pa[q];
+#pragma unroll
+            for (int p = 0; p < NPL; ++p) *(u32x4*)(base + A_BYTES + p * X_BYTES + la[q]) = px[p][q];
+        }
+    };
+
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc[t][u][q] = 0.0f;
+
+    const int nst = (int)((k_end - k_begin + BK - 1) / BK);
+    if (nst > 0) {
+        fetch(k_begin);
+        stash(0);
+        __syncthreads();
+    }
+    for (int st = 0; st < nst; ++st) {
+        const int buf = st & 1;
+        const bool more = st + 1 < nst;
+        if (more) fetch(k_begin + (int64_t)(st + 1) * BK);
+        const unsigned char* base = lds + buf * STAGE;
+        // two MFMA k-steps per stage: 16 values (BF16) or 8 (FP32, 4 per lane half)
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            const int kb = ks * 32 + lh * 16;          // byte offset of the lane's k values in the row
+            u32x4 af[2], xf[NPL][2];
+#pragma unroll
+            for (int t = 0; t < 2; ++t) af[t] = *(const u32x4*)(base + (wm * 64 + t * 32 + lr) * ROWB + kb);
+#pragma unroll
+            for (int p = 0; p < NPL; ++p)
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+                    xf[p][u] = *(const u32x4*)(base + A_BYTES + p * X_BYTES + (wn * 64 + u * 32 + lr) * ROWB + kb);
+            if constexpr (BF) {
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        const bf16x8_t av = __builtin_bit_cast(bf16x8_t, af[t]);
+                        acc[t][u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, __builtin_bit_cast(bf16x8_t, xf[0][u]),
+                                                                            acc[t][u], 0, 0, 0);
+                        acc[t][u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            av, __builtin_bit_cast(bf16x8_t, xf[NPL - 1][u]), acc[t][u], 0, 0, 0);
+                    }
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int t = 0; t < 2; ++t)
+#pragma unroll
+                        for (int u = 0; u < 2; ++u)
+                            acc[t][u] = __builtin_amdgcn_mfma_f32_32x32x2f32(
+                                __uint_as_float(af[t][q]), __uint_as_float(xf[0][u][q]), acc[t][u], 0, 0, 0);
+            }
+        }
+        if (more) {
+            stash(buf ^ 1);
+        }
+        __syncthreads();
+    }
+
+    float* P = G.part + (int64_t)blockIdx.z * G.r_pad * G.ld_part;
+    const int64_t row0 = tile_r + wm * 64, col0 = tile_c + wn * 64;
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int64_t i0 = row0 + t * 32 + 8 * g + 4 * lh;
+                const int64_t r = col0 + u * 32 + lr;
+                f32x4 v = {acc[t][u][4 * g], acc[t][u][4 * g + 1], acc[t][u][4 * g + 2], acc[t][u][4 * g + 3]};
+                __builtin_nontemporal_store(v, (f32x4*)(P + r * G.ld_part + i0));
+            }
+}
+
 __global__ __launch_bounds__(256) void mepi_kernel(MEpi E) {
     const int64_t q4 = E.ld_next / 4;
     const int64_t total = E.r_pad * q4;
@@ -295,10 +439,17 @@ hipError_t launch_multi_info(uot_info* info, int64_t iters, uint32_t* flags, int
 
 hipError_t launch_mgemm(int bf16, const MGemm& G, hipStream_t stream) {
     dim3 grid((unsigned)(G.r_pad / kMTileCols), (unsigned)(G.rows_pad / kMTileRows), (unsigned)G.splits);
-    if (bf16)
-        hipLaunchKernelGGL(mgemm_kernel<true>, grid, dim3(256), 0, stream, G);
-    else
-        hipLaunchKernelGGL(mgemm_kernel<false>, grid, dim3(256), 0, stream, G);
+    if (G.variant == 1) {
+        if (bf16)
+            hipLaunchKernelGGL(mgemm_lds_kernel<true>, grid, dim3(256), 0, stream, G);
+        else
+            hipLaunchKernelGGL(mgemm_lds_kernel<false>, grid, dim3(256), 0, stream, G);
+    } else {
+        if (bf16)
+            hipLaunchKernelGGL(mgemm_kernel<true>, grid, dim3(256), 0, stream, G);
+        else
+            hipLaunchKernelGGL(mgemm_kernel<false>, grid, dim3(256), 0, stream, G);
+    }
     return hipGetLastError();
 }
 

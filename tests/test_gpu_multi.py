@@ -46,16 +46,18 @@ def _compare(res, Kr, A, B, eps, tau, T, idx, bar, label):
     return worst
 
 
+@pytest.mark.parametrize("tune", [0, 2], ids=["direct", "lds"])
 @pytest.mark.parametrize("dtype,storage,bar", [(torch.float32, "f32", 2e-6), (torch.bfloat16, "bf16", 2e-4)])
-def test_multi_matches_oracle_on_same_kernel(dtype, storage, bar):
+def test_multi_matches_oracle_on_same_kernel(dtype, storage, bar, tune):
     base, A, B = workloads.multi_rhs(n=300, m=257, R=40, max_iter=50)
     A, B = A.T.copy(), B.T.copy()
     C = oracle.cost_points(base.x, base.y, base.cost_kind)
     Kr, Kd = _stored(C, base.eps, storage, dtype)
-    res = uot.sinkhorn_multi(Kd, to_dev(A), to_dev(B), m=base.m, eps=base.eps, tau=base.tau, max_iter=50)
+    res = uot.sinkhorn_multi(Kd, to_dev(A), to_dev(B), m=base.m, eps=base.eps, tau=base.tau, max_iter=50,
+                             tune=tune)
     torch.cuda.synchronize()
     assert res.info()["flags"] == 0 and res.info()["iters"] == 50
-    _compare(res, Kr, A, B, base.eps, base.tau, 50, range(40), bar, str(dtype))
+    _compare(res, Kr, A, B, base.eps, base.tau, 50, range(40), bar, f"{dtype} tune={tune}")
 
 
 def test_multi_bf16_storage_error_against_exact_kernel():
