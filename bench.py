@@ -328,7 +328,7 @@ def multi(uot, workloads, torch, dev, args):
                        f"eps=0.05, tau=1, {T} iterations", "flops_per_iter": flops}
     for name, dt in (("bf16", torch.bfloat16), ("f32", torch.float32)):
         K = uot.kernel_from_cost(C, base.eps, dt)
-        for variant, tune in (("", 0), ("_lds", 2)):
+        for variant, tune in (("", 0), ("_direct", 2)):
             uot.sinkhorn_multi(K, At, Bt, m=base.m, eps=base.eps, tau=base.tau, max_iter=2, tune=tune)
             torch.cuda.synchronize()
             e0, e1 = _events(torch)

@@ -311,8 +311,8 @@ uot_status uot_plan(const uot_problem* prob, const double* u, const double* v, c
  * the matrix cores and added in FP64 in a fixed order.
  * opt: max_iter >= 1 iterations exactly; tol, absorption, checkpoints, warm
  * start and the cooperative loop must be off (else UOT_ERR_UNSUPPORTED);
- * tune = 2 selects the product variant that stages operand tiles through
- * LDS (the default loads each wave's fragments directly).
+ * tune = 2 selects the product variant in which each wave loads its own
+ * operand fragments (the default stages the workgroup's tiles through LDS).
  * Workspace (uot_sinkhorn_multi_workspace_size): a transposed copy of K,
  * the split partial sums and the right-hand-side planes.
  * Errors: UOT_ERR_ARG, UOT_ERR_DTYPE, UOT_ERR_ALIGN, UOT_ERR_WORKSPACE,

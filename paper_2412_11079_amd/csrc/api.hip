@@ -1146,7 +1146,7 @@ uot_status run_multi(const uot_problem* p, int32_t R, const double* A, const dou
     rowg.kchunk = M.row.kchunk;
     rowg.part = part;
     rowg.ld_part = M.row.rows_pad;
-    rowg.variant = o->tune == 2 ? 1 : 0;      // 0: per-wave fragment loads (default); 1: LDS-staged tiles
+    rowg.variant = o->tune == 2 ? 0 : 1;      // 1: LDS-staged tiles (default); 0: per-wave fragment loads
     MGemm colg = rowg;
     colg.A = KT;
     colg.lda = M.ldn;

@@ -23,7 +23,7 @@ struct MGemm {
     int64_t kchunk;      // multiple of the k step
     float* part;
     int64_t ld_part;     // = rows_pad
-    int32_t variant;     // 0: fragments loaded by each wave; 1: tiles staged through LDS
+    int32_t variant;     // 1: tiles staged through LDS; 0: fragments loaded by each wave
 };
 
 // After a GEMM: S[r][i] = sum_s part[s][r][i] (FP64, fixed order), then

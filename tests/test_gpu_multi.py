@@ -46,7 +46,7 @@ def _compare(res, Kr, A, B, eps, tau, T, idx, bar, label):
     return worst
 
 
-@pytest.mark.parametrize("tune", [0, 2], ids=["direct", "lds"])
+@pytest.mark.parametrize("tune", [0, 2], ids=["lds", "direct"])
 @pytest.mark.parametrize("dtype,storage,bar", [(torch.float32, "f32", 2e-6), (torch.bfloat16, "bf16", 2e-4)])
 def test_multi_matches_oracle_on_same_kernel(dtype, storage, bar, tune):
     base, A, B = workloads.multi_rhs(n=300, m=257, R=40, max_iter=50)
