@@ -152,13 +152,19 @@ uot_status check_problem(const uot_problem* p, const uot_options* o) {
     return UOT_OK;
 }
 
-int default_shape(int64_t nv) {
-    // Smallest instantiated shape whose lanes cover a row (in 16-byte chunks).
-    static const int order[] = {0, 1, 2, 3, 4, 6};
-    for (int idx : order) {
-        PassShape s = pass_shape(idx);
-        if ((int64_t)s.wg * s.nc >= nv) return idx;
+int default_shape(int64_t nv, bool persistent) {
+    // Smallest instantiated shape whose lanes cover a row (in 16-byte
+    // chunks); rows of up to 2048 chunks go in batches of rows per barrier
+    // (the persistent loop instantiates the one-row shapes only).
+    static const int order[] = {11, 10, 9, 8, 6};
+    static const int order_one_row[] = {0, 1, 2, 3, 4, 6};
+    if (persistent) {
+        for (int idx : order_one_row)
+            if ((int64_t)pass_shape(idx).wg * pass_shape(idx).nc >= nv) return idx;
+        return -1;
     }
+    for (int idx : order)
+        if ((int64_t)pass_shape(idx).wg * pass_shape(idx).nc >= nv) return idx;
     return -1;
 }
 
@@ -185,7 +191,7 @@ uot_status make_plan(const uot_problem* p, const uot_options* o, Plan& P) {
             return fail(UOT_ERR_UNSUPPORTED, "shape %d covers %lld columns, m=%lld", P.shape,
                         (long long)s.wg * s.nc * P.vec, (long long)p->m);
     } else {
-        P.shape = default_shape(nv);
+        P.shape = default_shape(nv, o->persistent != 0);
         if (P.shape < 0)
             return fail(UOT_ERR_UNSUPPORTED, "m=%lld exceeds the row length one workgroup holds (%d columns)",
                         (long long)p->m, 4096 * P.vec);
@@ -196,6 +202,8 @@ uot_status make_plan(const uot_problem* p, const uot_options* o, Plan& P) {
     P.persistent = o->persistent != 0;
     if (P.persistent && !o->fused)
         return fail(UOT_ERR_ARG, "the persistent loop runs the fused pass only");
+    if (P.persistent && s.rb != 1)
+        return fail(UOT_ERR_UNSUPPORTED, "the persistent loop runs the one-row shapes (0-7) only");
     int64_t target = 256LL * (1024 / s.wg);     // about one wave of workgroups on 256 CUs
     if (P.persistent) {
         // LDS: max(v, finalize scratch of 4 doubles per thread), then the row strips

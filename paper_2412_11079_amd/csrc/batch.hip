@@ -42,6 +42,16 @@ constexpr int nc_max() {
     return KVec<KT>::N >= kLaneCols ? 1 : kLaneCols / KVec<KT>::N;
 }
 
+// Rows per batch of a row group: the batch's dots are reduced together,
+// with one LDS exchange, and its R scaling factors are computed side by
+// side (lane r of each wave evaluates row r), so the long FP64 chain of the
+// power is paid once per batch, not once per row.  Two batches are in
+// registers (one being processed, the next one loading).
+template <typename KT>
+constexpr int rows_per_batch() {
+    return (nc_max<KT>() >= 4 || KVec<KT>::N >= 16) ? 2 : 3;     // within 256 VGPRs
+}
+
 // Block-wide FP64 sum in a fixed order; every thread receives the result.
 __device__ __forceinline__ double block_sum(double x, double* scratch) {
     x = wave_sum_f64(x);
@@ -62,7 +72,7 @@ __device__ __forceinline__ double kl_term(double x, double y) {
 }
 
 struct BatchShared {
-    double red[2][kBatchNW];
+    double red[2][4][kBatchNW];
     double scratch[kBatchNW];
     int32_t idx;
     uint32_t flags;
@@ -75,29 +85,35 @@ struct BatchSolve {
     static constexpr int V = KV::N;
     static constexpr int NCM = nc_max<KT>();
     static constexpr int E = NCM * V;
+    static constexpr int R = rows_per_batch<KT>();
 
     __amdgpu_buffer_rsrc_t rsrc;
     uint32_t row_bytes;
     int rg, nc, lr, wpr, grp, gl;
     int col[NCM];                       // first column of each chunk (m < 2^31)
     uint32_t voff[NCM];
-    Raw buf[2][NCM];
+    Raw buf[2][R][NCM];
     double acc[E];
 
+    // Rows k = b R + r (r < R) of the group, i = grp + rg k, into buffer Q;
+    // rows beyond the matrix read 0.
     template <int Q>
-    __device__ __forceinline__ void load_row(int64_t i) {
-        const uint32_t soff = (uint32_t)i * row_bytes;
+    __device__ __forceinline__ void load_batch(int64_t b) {
 #pragma unroll
-        for (int c = 0; c < NCM; ++c)
-            buf[Q][c] = __builtin_bit_cast(
-                Raw, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)voff[c], (int)soff, 2));
+        for (int r = 0; r < R; ++r) {
+            const uint32_t soff = (uint32_t)(grp + (int64_t)rg * (b * R + r)) * row_bytes;
+#pragma unroll
+            for (int c = 0; c < NCM; ++c)
+                buf[Q][r][c] = __builtin_bit_cast(
+                    Raw, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)voff[c], (int)soff, 2));
+        }
     }
 
-    // The lane's chunk c of the row in buffer Q, widened; columns >= m read
+    // The lane's chunk c of row r in buffer Q, widened; columns >= m read
     // as 0 (chunks beyond the shape's nc point past the buffer and read 0).
     template <int Q>
-    __device__ __forceinline__ void unpack(int c, int m, bool ragged, double* x) const {
-        Unpack<KT, double>::run(buf[Q][c], x);
+    __device__ __forceinline__ void unpack(int r, int c, int m, bool ragged, double* x) const {
+        Unpack<KT, double>::run(buf[Q][r][c], x);
         if (ragged) {
 #pragma unroll
             for (int e = 0; e < V; ++e)
@@ -105,76 +121,103 @@ struct BatchSolve {
         }
     }
 
+    // Row totals of the batch (every lane of the group gets all R).
     template <int Q>
-    __device__ __forceinline__ double lane_dot(const double* vl, int m, bool ragged) const {
-        double s = 0.0;
+    __device__ __forceinline__ void batch_totals(const double* vl, int m, bool ragged, BatchShared& sh, int& slot,
+                                                 double* t) const {
 #pragma unroll
-        for (int c = 0; c < NCM; ++c) {
-            if (c < nc) {
-                double x[V];
-                unpack<Q>(c, m, ragged, x);
+        for (int r = 0; r < R; ++r) {
+            double s = 0.0;
 #pragma unroll
-                for (int e = 0; e < V; ++e) s = fma(x[e], vl[col[c] + e], s);
+            for (int c = 0; c < NCM; ++c) {
+                if (c < nc) {
+                    double x[V];
+                    unpack<Q>(r, c, m, ragged, x);
+#pragma unroll
+                    for (int e = 0; e < V; ++e) s = fma(x[e], vl[col[c] + e], s);
+                }
             }
+            t[r] = wave_sum_f64(s);
         }
-        return s;
-    }
-
-    // Row total over the group's waves: wave sums, then (several waves per
-    // row) an LDS exchange among all waves.  Every lane of the group gets it.
-    __device__ __forceinline__ double row_total(double s, BatchShared& sh, int& slot) const {
-        const double d = wave_sum_f64(s);
-        if (wpr == 1) return d;
-        const int wave = threadIdx.x >> 6;
-        if ((threadIdx.x & 63) == 0) sh.red[slot][wave] = d;
-        __syncthreads();
-        double t = 0.0;
-        for (int w = 0; w < wpr; ++w) t += sh.red[slot][grp * wpr + w];
-        slot ^= 1;
-        return t;
-    }
-
-    // One row of an iteration: dot, u_i, column accumulation (the group's
-    // next row is requested into the other buffer first).
-    template <int Q>
-    __device__ __forceinline__ void sweep_row(const BatchDesc& P, int64_t i, const double* vl, int m, bool ragged,
-                                              BatchShared& sh, int& slot, uint32_t& fl) {
-        load_row<Q ^ 1>(i + rg);                     // beyond the last row: reads 0
-        const double tot = row_total(lane_dot<Q>(vl, m, ragged), sh, slot) * P.k_scale;
-        double ui = 0.0;
-        if (i < P.n) {
-            const double ai = P.a[i];
-            ui = scale_factor(ai, tot, P.fi, P.fi_is_one, 0.0);
-            if (gl == 0) {
-                P.u[i] = ui;
-                if (ai > 0.0 && !(tot > 0.0)) fl |= UOT_FLAG_ZERO_SUM;
-                if (!isfinite(ui)) fl |= UOT_FLAG_NONFINITE;
-            }
-        }
+        if (wpr > 1) {
+            const int wave = threadIdx.x >> 6;
+            if ((threadIdx.x & 63) == 0)
 #pragma unroll
-        for (int c = 0; c < NCM; ++c) {
-            if (c < nc) {
-                double x[V];
-                unpack<Q>(c, m, ragged, x);
+                for (int r = 0; r < R; ++r) sh.red[slot][r][wave] = t[r];
+            __syncthreads();
 #pragma unroll
-                for (int e = 0; e < V; ++e) acc[c * V + e] = fma(x[e], ui, acc[c * V + e]);
+            for (int r = 0; r < R; ++r) {
+                double a = 0.0;
+                for (int w = 0; w < wpr; ++w) a += sh.red[slot][r][grp * wpr + w];
+                t[r] = a;
             }
+            slot ^= 1;
         }
     }
 
-    // One row of the final sweep: r_i = u_i (K v)_i and the objective's row terms.
+    // The batch's total held by lane r (r < R) of each wave.
+    __device__ __forceinline__ double lane_total(const double* t) const {
+        const int lane = threadIdx.x & 63;
+        double tl = t[0];
+#pragma unroll
+        for (int r = 1; r < R; ++r)
+            if (lane == r) tl = t[r];
+        return tl;
+    }
+
+    // One batch of an iteration: row totals, the R factors side by side,
+    // column accumulation.  The next batch is requested first.
     template <int Q>
-    __device__ __forceinline__ void marg_row(const BatchDesc& P, int64_t i, const double* vl, int m, bool ragged,
-                                             BatchShared& sh, int& slot, double& rlu, double& rsum, double& klr) {
-        load_row<Q ^ 1>(i + rg);
-        const double tot = row_total(lane_dot<Q>(vl, m, ragged), sh, slot) * P.k_scale;
-        if (i < P.n && gl == 0) {
-            const double ui = P.u[i];
-            const double ri = ui * tot;
-            P.r[i] = ri;
+    __device__ __forceinline__ void sweep_batch(const BatchDesc& P, int64_t b, const double* vl, int m, bool ragged,
+                                                BatchShared& sh, int& slot, uint32_t& fl) {
+        load_batch<Q ^ 1>(b + 1);
+        double t[R];
+        batch_totals<Q>(vl, m, ragged, sh, slot, t);
+        const int lane = threadIdx.x & 63;
+        const double tl = lane_total(t) * P.k_scale;
+        const int64_t il = grp + (int64_t)rg * (b * R + (lane < R ? lane : 0));
+        double ul = 0.0;
+        if (lane < R && il < P.n) {
+            const double ai = P.a[il];
+            ul = scale_factor(ai, tl, P.fi, P.fi_is_one, 0.0);
+            if (gl < R) {              // the group's first wave writes
+                P.u[il] = ul;
+                if (ai > 0.0 && !(tl > 0.0)) fl |= UOT_FLAG_ZERO_SUM;
+                if (!isfinite(ul)) fl |= UOT_FLAG_NONFINITE;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double ur = readlane_f64(ul, r);
+#pragma unroll
+            for (int c = 0; c < NCM; ++c) {
+                if (c < nc) {
+                    double x[V];
+                    unpack<Q>(r, c, m, ragged, x);
+#pragma unroll
+                    for (int e = 0; e < V; ++e) acc[c * V + e] = fma(x[e], ur, acc[c * V + e]);
+                }
+            }
+        }
+    }
+
+    // One batch of the final sweep: r_i = u_i (K v)_i and the objective's row terms.
+    template <int Q>
+    __device__ __forceinline__ void marg_batch(const BatchDesc& P, int64_t b, const double* vl, int m, bool ragged,
+                                               BatchShared& sh, int& slot, double& rlu, double& rsum, double& klr) {
+        load_batch<Q ^ 1>(b + 1);
+        double t[R];
+        batch_totals<Q>(vl, m, ragged, sh, slot, t);
+        const int lane = threadIdx.x & 63;
+        const double tl = lane_total(t) * P.k_scale;
+        const int64_t il = grp + (int64_t)rg * (b * R + (lane < R ? lane : 0));
+        if (lane < R && gl < R && il < P.n) {
+            const double ui = P.u[il];
+            const double ri = ui * tl;
+            P.r[il] = ri;
             if (ri > 0.0) rlu += ri * log(ui);
             rsum += ri;
-            klr += kl_term(ri, P.a[i]);
+            klr += kl_term(ri, P.a[il]);
         }
     }
 
@@ -211,6 +254,7 @@ struct BatchSolve {
         // rows of a group: i = grp + rg k, k < kmax (the same count for every
         // group: groups that exchange row totals step together)
         const int64_t kmax = (n + rg - 1) / rg;
+        const int64_t nbatch = (kmax + R - 1) / R;
         int slot = 0;
         int64_t it = 0;
         double err = 0.0;
@@ -218,10 +262,10 @@ struct BatchSolve {
         for (int64_t t = 1; t <= B.max_iter; ++t) {
 #pragma unroll
             for (int e = 0; e < E; ++e) acc[e] = 0.0;
-            load_row<0>(grp);
-            for (int64_t k = 0; k < kmax; k += 2) {
-                sweep_row<0>(P, grp + rg * k, vl, m, ragged, sh, slot, fl);
-                if (k + 1 < kmax) sweep_row<1>(P, grp + rg * (k + 1), vl, m, ragged, sh, slot, fl);
+            load_batch<0>(0);
+            for (int64_t bb = 0; bb < nbatch; bb += 2) {
+                sweep_batch<0>(P, bb, vl, m, ragged, sh, slot, fl);
+                if (bb + 1 < nbatch) sweep_batch<1>(P, bb + 1, vl, m, ragged, sh, slot, fl);
             }
             // Column sums: the groups' partials added in group order.
             if (rg > 1) {
@@ -278,10 +322,10 @@ struct BatchSolve {
 
         // Row marginal r = u (K v) with the final v, and the objective's terms.
         double rlu = 0.0, rsum = 0.0, klr = 0.0;
-        load_row<0>(grp);
-        for (int64_t k = 0; k < kmax; k += 2) {
-            marg_row<0>(P, grp + rg * k, vl, m, ragged, sh, slot, rlu, rsum, klr);
-            if (k + 1 < kmax) marg_row<1>(P, grp + rg * (k + 1), vl, m, ragged, sh, slot, rlu, rsum, klr);
+        load_batch<0>(0);
+        for (int64_t bb = 0; bb < nbatch; bb += 2) {
+            marg_batch<0>(P, bb, vl, m, ragged, sh, slot, rlu, rsum, klr);
+            if (bb + 1 < nbatch) marg_batch<1>(P, bb + 1, vl, m, ragged, sh, slot, rlu, rsum, klr);
         }
         double clv = 0.0, klc = 0.0;
         if (grp == 0) {

@@ -29,10 +29,10 @@ namespace uot {
 // ---------------------------------------------------------------------------
 // Per-iteration pass kernel.
 // ---------------------------------------------------------------------------
-template <typename KT, typename AT, int WG, int NC, int D, bool VLDS, int MODE>
+template <typename KT, typename AT, int WG, int NC, int D, bool VLDS, int MODE, int RB>
 __global__ __launch_bounds__(WG) void pass_kernel(PassLaunch L) {
-    using S = Strip<KT, AT, WG, NC, D, VLDS, MODE>;
-    __shared__ double red[2][S::NW];
+    using S = Strip<KT, AT, WG, NC, D, VLDS, MODE, RB>;
+    __shared__ double red[2][S::NW * RB];
     __shared__ double err_sh;
     extern __shared__ __align__(16) unsigned char dyn_lds[];
 
@@ -199,16 +199,20 @@ __global__ __launch_bounds__(WG) void persist_kernel(PersistLaunch P) {
     }
 }
 
-// Instantiated launch shapes {WG, NC, D, v in LDS}.
+// Instantiated launch shapes {WG, NC, D, v in LDS, rows per barrier}.
 static const PassShape kShapes[] = {
-    {256, 1, 4, 0},    // 0: short rows
-    {512, 1, 4, 0},    // 1
-    {1024, 1, 4, 0},   // 2
-    {1024, 2, 3, 0},   // 3
-    {512, 4, 3, 0},    // 4
-    {512, 8, 2, 1},    // 5: 16384 FP32 columns, 8 waves, v in LDS
-    {1024, 4, 2, 1},   // 6: 16384 FP32 columns, 16 waves, v in LDS
-    {512, 8, 3, 1},    // 7: as 5, three rows in flight
+    {256, 1, 4, 0, 1},    // 0: short rows
+    {512, 1, 4, 0, 1},    // 1
+    {1024, 1, 4, 0, 1},   // 2
+    {1024, 2, 3, 0, 1},   // 3
+    {512, 4, 3, 0, 1},    // 4
+    {512, 8, 2, 1, 1},    // 5: 16384 FP32 columns, 8 waves, v in LDS
+    {1024, 4, 2, 1, 1},   // 6: 16384 FP32 columns, 16 waves, v in LDS
+    {512, 8, 3, 1, 1},    // 7: as 5, three rows in flight
+    {1024, 2, 2, 0, 2},   // 8: 8192 FP32 columns, batches of 2 rows
+    {1024, 1, 2, 0, 4},   // 9: 4096 FP32 / 8192 BF16 columns, batches of 4 rows
+    {512, 1, 2, 0, 4},    // 10: 2048 FP32 / 8192 FP8 columns, batches of 4 rows
+    {256, 1, 2, 0, 4},    // 11: 1024 FP32 columns, batches of 4 rows
 };
 static constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
@@ -217,10 +221,10 @@ PassShape pass_shape(int idx) { return kShapes[idx]; }
 
 // Launch one instantiation; raises its dynamic-LDS limit first when the
 // request exceeds the default 64 KiB (once per size increase).
-template <typename KT, typename AT, int WG, int NC, int D, bool VLDS, int MODE>
+template <typename KT, typename AT, int WG, int NC, int D, bool VLDS, int MODE, int RB>
 static hipError_t launch_one(const PassLaunch& L, size_t lds, hipStream_t stream) {
     static size_t raised = 65536;
-    auto fn = pass_kernel<KT, AT, WG, NC, D, VLDS, MODE>;
+    auto fn = pass_kernel<KT, AT, WG, NC, D, VLDS, MODE, RB>;
     if (lds > raised) {
         hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
@@ -230,13 +234,13 @@ static hipError_t launch_one(const PassLaunch& L, size_t lds, hipStream_t stream
     return hipGetLastError();
 }
 
-template <typename KT, typename AT, int WG, int NC, int D, bool VLDS>
+template <typename KT, typename AT, int WG, int NC, int D, bool VLDS, int RB = 1>
 static hipError_t launch_shape(int mode, const PassLaunch& L, size_t lds, hipStream_t stream) {
     switch (mode) {
-        case MODE_FUSED: return launch_one<KT, AT, WG, NC, D, VLDS, MODE_FUSED>(L, lds, stream);
-        case MODE_ROW: return launch_one<KT, AT, WG, NC, D, VLDS, MODE_ROW>(L, lds, stream);
-        case MODE_COL: return launch_one<KT, AT, WG, NC, D, VLDS, MODE_COL>(L, lds, stream);
-        case MODE_MARG: return launch_one<KT, AT, WG, NC, D, VLDS, MODE_MARG>(L, lds, stream);
+        case MODE_FUSED: return launch_one<KT, AT, WG, NC, D, VLDS, MODE_FUSED, RB>(L, lds, stream);
+        case MODE_ROW: return launch_one<KT, AT, WG, NC, D, VLDS, MODE_ROW, RB>(L, lds, stream);
+        case MODE_COL: return launch_one<KT, AT, WG, NC, D, VLDS, MODE_COL, RB>(L, lds, stream);
+        case MODE_MARG: return launch_one<KT, AT, WG, NC, D, VLDS, MODE_MARG, RB>(L, lds, stream);
         default: return hipErrorInvalidValue;
     }
 }
@@ -252,6 +256,10 @@ static hipError_t launch_typed(int mode, int shape_idx, const PassLaunch& L, siz
         case 5: return launch_shape<KT, AT, 512, 8, 2, true>(mode, L, lds, stream);
         case 6: return launch_shape<KT, AT, 1024, 4, 2, true>(mode, L, lds, stream);
         case 7: return launch_shape<KT, AT, 512, 8, 3, true>(mode, L, lds, stream);
+        case 8: return launch_shape<KT, AT, 1024, 2, 2, false, 2>(mode, L, lds, stream);
+        case 9: return launch_shape<KT, AT, 1024, 1, 2, false, 4>(mode, L, lds, stream);
+        case 10: return launch_shape<KT, AT, 512, 1, 2, false, 4>(mode, L, lds, stream);
+        case 11: return launch_shape<KT, AT, 256, 1, 2, false, 4>(mode, L, lds, stream);
         default: return hipErrorInvalidValue;
     }
 }

@@ -20,7 +20,12 @@ constexpr int kLoadAux = UOT_K_LOAD_AUX;
 // One workgroup's streaming pass over its strip of rows.  Shared by the
 // per-iteration pass kernel and the persistent kernel.
 // ---------------------------------------------------------------------------
-template <typename KT, typename AT, int WG, int NC, int D, bool VLDS, int MODE>
+// RB > 1: rows are taken in batches of RB.  The batch's dot products are
+// reduced together (one LDS exchange and one barrier per batch) and its RB
+// scaling factors are evaluated side by side, lane r of every wave taking
+// row r, then broadcast; for short rows this divides the per-row chain of
+// reduction, barrier and FP64 power by RB.  D then counts batches in flight.
+template <typename KT, typename AT, int WG, int NC, int D, bool VLDS, int MODE, int RB = 1>
 struct Strip {
     using KV = KVec<KT>;
     using Raw = typename KV::raw;
@@ -39,7 +44,7 @@ struct Strip {
     bool ragged;
     int64_t col[NC];
     uint32_t voff[NC];
-    Raw buf[D][NC];
+    Raw buf[D * RB][NC];
     AT vv[kVreg ? E : 1];
     AT acc[kAcc ? E : 1];
 
@@ -70,11 +75,30 @@ struct Strip {
                 Raw, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)voff[c], (int)soff, kLoadAux));
     }
 
-    // Rows 0 .. D-2 in flight (issued before anything the pass waits on).
+    // Rows kb RB + r of batch kb into buffers Q RB + r.
+    template <int Q>
+    __device__ __forceinline__ void load_batch(int kb) {
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const uint32_t soff = (uint32_t)(kb * RB + r) * row_bytes;
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                buf[Q * RB + r][c] = __builtin_bit_cast(
+                    Raw, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)voff[c], (int)soff, kLoadAux));
+        }
+    }
+
+    // Rows (batches) 0 .. D-2 in flight (issued before anything the pass waits on).
     __device__ __forceinline__ void prime() {
-        if constexpr (D >= 2) load_row<0>(0);
-        if constexpr (D >= 3) load_row<1>(1);
-        if constexpr (D >= 4) load_row<2>(2);
+        if constexpr (RB == 1) {
+            if constexpr (D >= 2) load_row<0>(0);
+            if constexpr (D >= 3) load_row<1>(1);
+            if constexpr (D >= 4) load_row<2>(2);
+        } else {
+            if constexpr (D >= 2) load_batch<0>(0);
+            if constexpr (D >= 3) load_batch<1>(1);
+            if constexpr (D >= 4) load_batch<2>(2);
+        }
     }
 
     __device__ __forceinline__ void load_v_regs(const double* v) {
@@ -98,7 +122,7 @@ struct Strip {
     // accumulation of the column partials (FUSED/COL/MARG).
     template <int Q>
     __device__ __forceinline__ void process(const PassLaunch& L, int k, const AT* vl, const double* row_in,
-                                            const double* row_sh, double (*red)[NW], int& slot) {
+                                            const double* row_sh, double (*red)[NW * RB], int& slot) {
         const int tid = threadIdx.x;
         const int lane = tid & 63;
         const int wave = tid >> 6;
@@ -162,21 +186,113 @@ struct Strip {
         }
     }
 
+    // One batch of RB rows (RB > 1): the rows' dots, one exchange, the
+    // factors side by side, the accumulation.  Rows past the strip (the last
+    // batch may be partial) read 0 and write nothing.
+    template <int Q>
+    __device__ __forceinline__ void process_batch(const PassLaunch& L, int kb, const AT* vl, const double* row_in,
+                                                  const double* row_sh, double (*red)[NW * RB], int& slot) {
+        const int tid = threadIdx.x;
+        const int lane = tid & 63;
+        const int wave = tid >> 6;
+        const int kl = kb * RB + (lane < RB ? lane : 0);      // lane r's row
+        double ul = 0.0;
+        if constexpr (kDot) {
+            double d[RB];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                AT s = (AT)0;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    AT x[V];
+                    Unpack<KT, AT>::run(buf[Q * RB + r][c], x);
+                    if (ragged) {
+#pragma unroll
+                        for (int e = 0; e < V; ++e)
+                            if (col[c] + e >= m) x[e] = (AT)0;
+                    }
+                    if constexpr (VLDS) {
+                        if (col[c] < m) {
+#pragma unroll
+                            for (int e = 0; e < V; ++e) s = fma(x[e], vl[col[c] + e], s);
+                        }
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < V; ++e) s = fma(x[e], vv[c * V + e], s);
+                    }
+                }
+                d[r] = wave_sum_f64((double)s);
+            }
+            if (lane == 0)
+#pragma unroll
+                for (int r = 0; r < RB; ++r) red[slot][r * NW + wave] = d[r];
+            __syncthreads();
+            // Every lane forms the row totals in the same fixed order; lane r keeps row r's.
+            double tl = 0.0;
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                double tot = 0.0;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) tot += red[slot][r * NW + w];
+                if (lane == r) tl = tot;
+            }
+            tl *= L.k_scale;
+            slot ^= 1;
+            if (lane < RB && kl < nrows) {
+                if constexpr (MODE == MODE_MARG) {
+                    ul = row_in[kl];
+                    if (wave == 0) L.s_out[r0 + kl] = tl;
+                } else {
+                    const double ai = row_in[kl];
+                    ul = scale_factor(ai, tl, L.fi, L.fi_is_one, row_sh[kl]);
+                    if (wave == 0) {
+                        L.u[r0 + kl] = ul;
+                        if (L.s_trace) L.s_trace[r0 + kl] = tl;
+                        if (ai > 0.0 && !(tl > 0.0)) atomicOr(&L.ctrl->flags, UOT_FLAG_ZERO_SUM);
+                        if (!isfinite(ul)) atomicOr(&L.ctrl->flags, UOT_FLAG_NONFINITE);
+                    }
+                }
+            }
+        } else {
+            if (lane < RB && kl < nrows) ul = row_in[kl];
+        }
+        if constexpr (kAcc) {
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const AT ur = (AT)readlane_f64(ul, r);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    AT x[V];
+                    Unpack<KT, AT>::run(buf[Q * RB + r][c], x);
+#pragma unroll
+                    for (int e = 0; e < V; ++e) acc[c * V + e] = fma(x[e], ur, acc[c * V + e]);
+                }
+            }
+        }
+    }
+
     template <int Q>
     __device__ __forceinline__ bool step(const PassLaunch& L, int k0, const AT* vl, const double* row_in,
-                                         const double* row_sh, double (*red)[NW], int& slot) {
+                                         const double* row_sh, double (*red)[NW * RB], int& slot) {
         const int k = k0 + Q;
-        if (k >= nrows) return false;
-        load_row<(Q + D - 1) % D>(k + D - 1);
-        process<Q>(L, k, vl, row_in, row_sh, red, slot);
+        if constexpr (RB == 1) {
+            if (k >= nrows) return false;
+            load_row<(Q + D - 1) % D>(k + D - 1);
+            process<Q>(L, k, vl, row_in, row_sh, red, slot);
+        } else {
+            if (k * RB >= nrows) return false;
+            load_batch<(Q + D - 1) % D>(k + D - 1);
+            process_batch<Q>(L, k, vl, row_in, row_sh, red, slot);
+        }
         return true;
     }
 
-    // All rows of the strip; expects prime() to have been called.
+    // All rows (batches) of the strip; expects prime() to have been called.
     __device__ __forceinline__ void stream(const PassLaunch& L, const AT* vl, const double* row_in,
-                                           const double* row_sh, double (*red)[NW]) {
+                                           const double* row_sh, double (*red)[NW * RB]) {
         int slot = 0;
-        for (int k0 = 0; k0 < nrows; k0 += D) {
+        const int steps = (nrows + RB - 1) / RB;
+        for (int k0 = 0; k0 < steps; k0 += D) {
             if (!step<0>(L, k0, vl, row_in, row_sh, red, slot)) break;
             if constexpr (D >= 2) if (!step<1 % D>(L, k0, vl, row_in, row_sh, red, slot)) break;
             if constexpr (D >= 3) if (!step<2 % D>(L, k0, vl, row_in, row_sh, red, slot)) break;

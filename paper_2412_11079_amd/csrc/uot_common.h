@@ -260,8 +260,9 @@ struct PassLaunch {
 struct PassShape {
     int wg;       // threads per workgroup
     int nc;       // 16-byte chunks per lane per row
-    int depth;    // rows in flight (software pipeline depth)
+    int depth;    // rows (or row batches) in flight (software pipeline depth)
     int vlds;     // 1: v read from LDS, 0: v held in registers
+    int rb;       // rows per barrier (batch size)
 };
 
 // Number of instantiated shapes and their table.
