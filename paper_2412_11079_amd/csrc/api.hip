@@ -1036,12 +1036,16 @@ struct MultiGemmShape {
     int32_t splits;
 };
 
-MultiGemmShape multi_gemm_shape(int64_t rows, int64_t kdim_pad, int64_t r_pad) {
+// Split of the reduction: enough workgroups to fill the device (about 512
+// for the BF16 form, whose partial sums cost relatively more, 1024 for FP32;
+// measured at 8192^2 x 256) with chunks of at least 256.
+MultiGemmShape multi_gemm_shape(int64_t rows, int64_t kdim_pad, int64_t r_pad, bool bf16) {
     MultiGemmShape g;
     g.rows_pad = round_up(rows, kMTileRows);
     g.kdim_pad = kdim_pad;
     const int64_t tiles = (r_pad / kMTileCols) * (g.rows_pad / kMTileRows);
-    int64_t splits = std::max<int64_t>(1, std::min<int64_t>(kdim_pad / 256, (1024 + tiles - 1) / tiles));
+    const int64_t target = bf16 ? 512 : 1024;
+    int64_t splits = std::max<int64_t>(1, std::min<int64_t>(kdim_pad / 256, (target + tiles - 1) / tiles));
     g.kchunk = round_up((kdim_pad + splits - 1) / splits, 64);     // whole stages of every product variant
     g.splits = (int32_t)((kdim_pad + g.kchunk - 1) / g.kchunk);
     return g;
@@ -1083,8 +1087,8 @@ uot_status make_multi_plan(const uot_problem* p, int32_t R, const uot_options* o
     if ((int64_t)M.n * p->ldk * M.es >= ((int64_t)1 << 31) || M.m * M.ldn * M.es >= ((int64_t)1 << 31) ||
         M.r_pad * std::max(M.ldn, M.ldm) * M.es >= ((int64_t)1 << 31))
         return fail(UOT_ERR_UNSUPPORTED, "K and the right-hand sides must each be below 2 GiB");
-    M.row = multi_gemm_shape(M.n, M.ldm, M.r_pad);      // S = K V: rows n, reduction over m
-    M.col = multi_gemm_shape(M.m, M.ldn, M.r_pad);      // W = K^T U: rows m, reduction over n
+    M.row = multi_gemm_shape(M.n, M.ldm, M.r_pad, M.bf16);      // S = K V: rows n, reduction over m
+    M.col = multi_gemm_shape(M.m, M.ldn, M.r_pad, M.bf16);      // W = K^T U: rows m, reduction over n
     size_t off = 0;
     M.off_kt = off;
     off = align_up(off + (size_t)M.m * M.ldn * M.es, kAlign);
