@@ -86,9 +86,25 @@ __global__ __launch_bounds__(WG) void adj_kernel(AdjLaunch L) {
     const int64_t mp = (m + V - 1) / V * V;
     AT* yl = (AT*)(lgy + (size_t)R * (DIM > 0 ? DIM : 1));
     if constexpr (DIM > 0) {
-        for (int64_t j = tid; j < mp; j += WG)
+        // Loads of U points issued before the first wait (indices clamped in bounds).
+        constexpr int U = 4;
+        for (int64_t j0 = tid; j0 < mp; j0 += (int64_t)WG * U) {
+            double x[U][DIM];
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) yl[d * mp + j] = (j < m) ? (AT)L.y[j * DIM + d] : (AT)0;
+            for (int q = 0; q < U; ++q) {
+                const int64_t j = j0 + (int64_t)q * WG;
+                const int64_t jc = j < m ? j : m - 1;
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) x[q][d] = L.y[jc * DIM + d];
+            }
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                const int64_t j = j0 + (int64_t)q * WG;
+                if (j < mp)
+#pragma unroll
+                    for (int d = 0; d < DIM; ++d) yl[d * mp + j] = (j < m) ? (AT)x[q][d] : (AT)0;
+            }
+        }
     }
     // Right-hand sides of this lane's columns.
     AT Av[E], Bv[kB ? E : 1];

@@ -89,7 +89,7 @@ __global__ __launch_bounds__(FIN_THREADS) void finalize_kernel(FinLaunch F) {
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     if (c0 < F.m) {
         // ldp is a multiple of 64, so the 4 columns never leave the partial row.
-        constexpr int U = 8;
+        constexpr int U = 16;
         int g = ph;
         for (; g + (U - 1) * FIN_PHASES < F.G; g += U * FIN_PHASES) {
             double x[U][4];

@@ -53,7 +53,7 @@ __global__ __launch_bounds__(WG) void pass_kernel(PassLaunch L) {
     double* row_in = (double*)(dyn_lds + (VLDS && S::kDot ? L.ldv_bytes : 0));
     double* row_sh = row_in + L.rows_per_wg;
     stage_rows<S, MODE, VLDS, AT>(L, r0, nrows, row_in, row_sh);
-    if constexpr (VLDS && S::kDot) stage_v<S::V, AT>(L.v, L.m, vl);
+    if constexpr (VLDS && S::kDot) stage_v<S::V, WG, AT>(L.v, L.m, vl);
     __syncthreads();
     st.load_v_regs(L.v);
     st.clear_acc();
@@ -126,7 +126,7 @@ __global__ __launch_bounds__(WG) void persist_kernel(PersistLaunch P) {
     for (; t <= P.max_iter; ++t) {
         if (stop_test(L, t, &err_sh)) break;
         st.prime();
-        if constexpr (VLDS) stage_v<S::V, AT>(L.v, L.m, vl);
+        if constexpr (VLDS) stage_v<S::V, WG, AT>(L.v, L.m, vl);
         __syncthreads();
         st.load_v_regs(L.v);
         st.clear_acc();

@@ -331,10 +331,29 @@ __device__ __forceinline__ void stage_rows(const PassLaunch& L, int64_t r0, int 
     }
 }
 
-template <int V, typename AT>
+// v (FP64) into LDS as AT.  Each lane issues its kStageV loads before the
+// first wait (a loop that waited on each load in turn would put that many L2
+// round trips in front of the workgroup's first row).  The loads go through a
+// buffer resource over v: one lane offset plus a per-load scalar offset, and
+// entries j >= m read as 0.  Requires 8 m < 2^31 (v fits in LDS here).
+constexpr int kStageV = 16;
+
+template <int V, int NT, typename AT>
 __device__ __forceinline__ void stage_v(const double* v, int64_t m, AT* vl) {
-    const int64_t mv = (m + V - 1) / V * V;
-    for (int64_t j = threadIdx.x; j < mv; j += blockDim.x) vl[j] = (j < m) ? (AT)v[j] : (AT)0;
+    const int mv = (int)((m + V - 1) / V * V);
+    constexpr int nt = NT;
+    const __amdgpu_buffer_rsrc_t vr = __builtin_amdgcn_make_buffer_rsrc((void*)v, (short)0, (int)(m * 8), kBufferWord3);
+    for (int j0 = threadIdx.x; j0 < mv; j0 += nt * kStageV) {
+        double x[kStageV];
+#pragma unroll
+        for (int q = 0; q < kStageV; ++q)
+            x[q] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(vr, j0 * 8, q * nt * 8, 0));
+#pragma unroll
+        for (int q = 0; q < kStageV; ++q) {
+            const int j = j0 + q * nt;
+            if (j < mv) vl[j] = (AT)x[q];
+        }
+    }
 }
 
 // Stopping test of the previous iteration (see PassLaunch): identical in
