@@ -27,6 +27,55 @@
 
 namespace uot {
 
+// Totals over a 512-lane workgroup of ND <= 8 per-lane values, FP64, in a
+// fixed order; every lane returns the same T.
+//  1. Within each 16-lane row, a transposing butterfly: at each level a lane
+//     keeps half of its values and sends the other half to its partner (row
+//     mirror, half-row mirror, lane ^ 2), so ND values cost 4 + 2 + 1 moves
+//     instead of 4 per value; after a last lane ^ 1 exchange, lanes 2p and
+//     2p + 1 of a row hold the row's sum of value p = (lane >> 1) & 7.
+//  2. Even lanes write their sum to red[p][4 wave + row]; one barrier.
+//  3. Lane l adds the 4 entries red[l >> 3][4 (l & 7) .. +3] in order, then
+//     the 8 lanes of each group finish with three exchanges (lane ^ 1,
+//     lane ^ 2, half-row mirror) and T[p] is read from lane 8 p.
+template <int ND>
+__device__ __forceinline__ void block_sums8(const double (&x)[ND], double (*red)[32], int lane, int wave,
+                                            double (&T)[ND]) {
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = q < ND ? x[q] : 0.0;
+    const bool b3 = (lane & 8) != 0, b2 = (lane & 4) != 0, b1 = (lane & 2) != 0;
+    double a[4], b[2];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const double keep = b3 ? v[j + 4] : v[j];
+        const double send = b3 ? v[j] : v[j + 4];
+        a[j] = keep + dpp_f64<0x140>(send);       // row_mirror: lane i <-> 15 - i
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const double keep = b2 ? a[j + 2] : a[j];
+        const double send = b2 ? a[j] : a[j + 2];
+        b[j] = keep + dpp_f64<0x141>(send);       // row_half_mirror: i <-> 7 - i in each half
+    }
+    double c;
+    {
+        const double keep = b1 ? b[1] : b[0];
+        const double send = b1 ? b[0] : b[1];
+        c = keep + dpp_f64<0x4E>(send);           // lane ^ 2
+    }
+    c += dpp_f64<0xB1>(c);                         // lane ^ 1
+    if (!(lane & 1)) red[(lane >> 1) & 7][4 * wave + (lane >> 4)] = c;
+    __syncthreads();
+    const double* p = &red[lane >> 3][4 * (lane & 7)];
+    double t = ((p[0] + p[1]) + p[2]) + p[3];
+    t += dpp_f64<0xB1>(t);
+    t += dpp_f64<0x4E>(t);
+    t += dpp_f64<0x141>(t);
+#pragma unroll
+    for (int q = 0; q < ND; ++q) T[q] = readlane_f64(t, 8 * q);
+}
+
 template <typename KT, typename AT, int WG, int NC, int D, int DIM, int PHASE>
 __global__ __launch_bounds__(WG) void adj_kernel(AdjLaunch L) {
     using S = Strip<KT, AT, WG, NC, D, false, MODE_COL>;
@@ -36,7 +85,8 @@ __global__ __launch_bounds__(WG) void adj_kernel(AdjLaunch L) {
     constexpr int NW = WG / 64;
     constexpr bool kB = (PHASE == ADJ_SEED) || (DIM > 0);   // dots with B needed
     constexpr int ND = 2 + 2 * DIM;                         // dA, dB, dAy[DIM], dBy[DIM]
-    __shared__ double red[2][ND][NW];
+    static_assert(NW == 8 && ND <= 8, "the row reduction maps 8 values x 8 waves onto 64 lanes");
+    __shared__ double red[2][8][32];
     extern __shared__ __align__(16) unsigned char dyn_lds[];
 
     const int tid = threadIdx.x;
@@ -83,8 +133,10 @@ __global__ __launch_bounds__(WG) void adj_kernel(AdjLaunch L) {
 
     // Coordinates of y in LDS, one contiguous row per coordinate (after the
     // per-row arrays): yl[d * mp + j].
+    // yl starts on a 16-byte boundary so that V consecutive entries load as one vector.
     const int64_t mp = (m + V - 1) / V * V;
-    AT* yl = (AT*)(lgy + (size_t)R * (DIM > 0 ? DIM : 1));
+    const size_t yl_off = (sizeof(double) * (size_t)R * (6 + (DIM > 0 ? DIM : 1)) + 15) & ~(size_t)15;
+    AT* yl = (AT*)(dyn_lds + yl_off);
     if constexpr (DIM > 0) {
         // Loads of U points issued before the first wait (indices clamped in bounds).
         constexpr int U = 4;
@@ -135,7 +187,16 @@ __global__ __launch_bounds__(WG) void adj_kernel(AdjLaunch L) {
                 for (int e = 0; e < V; ++e)
                     if (st.col[c] + e >= m) x[e] = (AT)0;
             }
-            const bool live = st.col[c] < m;
+            // The chunk's coordinates as one 16-byte LDS read per dimension.  A
+            // chunk past column m reads the last chunk instead (in bounds); its
+            // K entries and right-hand sides are 0, so it adds nothing.
+            AT yv[DIM > 0 ? DIM : 1][V];
+            if constexpr (DIM > 0) {
+                const int jc = (int)(st.col[c] < mp ? st.col[c] : mp - V);
+#pragma unroll
+                for (int d = 0; d < DIM; ++d)
+                    Unpack<AT, AT>::run(*(const Raw*)&yl[d * mp + jc], yv[d]);
+            }
 #pragma unroll
             for (int e = 0; e < V; ++e) {
                 const int q = c * V + e;
@@ -146,39 +207,23 @@ __global__ __launch_bounds__(WG) void adj_kernel(AdjLaunch L) {
                     tB = x[e] * Bv[q];
                     dB += tB;
                 }
-                if constexpr (DIM > 0) {
-                    if (live) {
 #pragma unroll
-                        for (int d = 0; d < DIM; ++d) {
-                            const AT yv = yl[d * mp + st.col[c] + e];
-                            dAy[d] = fma(tA, yv, dAy[d]);
-                            dBy[d] = fma(tB, yv, dBy[d]);
-                        }
-                    }
+                for (int d = 0; d < DIM; ++d) {
+                    dAy[d] = fma(tA, yv[d][e], dAy[d]);
+                    dBy[d] = fma(tB, yv[d][e], dBy[d]);
                 }
             }
         }
         double part[ND];
-        part[0] = wave_sum_f64((double)dA);
-        part[1] = kB ? wave_sum_f64((double)dB) : 0.0;
+        part[0] = (double)dA;
+        part[1] = (double)dB;
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
-            part[2 + d] = wave_sum_f64((double)dAy[d]);
-            part[2 + DIM + d] = wave_sum_f64((double)dBy[d]);
+            part[2 + d] = (double)dAy[d];
+            part[2 + DIM + d] = (double)dBy[d];
         }
-        if (lane == 0) {
-#pragma unroll
-            for (int q = 0; q < ND; ++q) red[slot][q][wave] = part[q];
-        }
-        __syncthreads();
         double T[ND];
-#pragma unroll
-        for (int q = 0; q < ND; ++q) {
-            double acc = 0.0;
-#pragma unroll
-            for (int w = 0; w < NW; ++w) acc += red[slot][q][w];
-            T[q] = acc;
-        }
+        block_sums8<ND>(part, red[slot], lane, wave, T);
         slot ^= 1;
         const double ui = lu[k], ai = la[k];
         double qrow;
