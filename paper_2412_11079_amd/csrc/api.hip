@@ -152,19 +152,29 @@ uot_status check_problem(const uot_problem* p, const uot_options* o) {
     return UOT_OK;
 }
 
-int default_shape(int64_t nv, bool persistent) {
-    // Smallest instantiated shape whose lanes cover a row (in 16-byte
-    // chunks); rows of up to 2048 chunks go in batches of rows per barrier
-    // (the persistent loop instantiates the one-row shapes only).
-    static const int order[] = {11, 10, 9, 8, 6};
+int default_shape(int64_t nv, bool persistent, int k_dtype, bool acc64) {
+    // Smallest shape in the storage type's list whose lanes cover a row (in
+    // 16-byte chunks); rows of up to 2048 chunks go in batches of rows per
+    // barrier (the persistent loop instantiates the one-row shapes only).
+    // The 512-lane batched shapes 12-14 were measured fastest for rows of
+    // 8192 FP32, BF16 and FP8 entries (eight waves per barrier instead of
+    // sixteen, twice the bytes per lane in flight).
+    static const int order_f32[] = {11, 10, 9, 12, 6};
+    static const int order_bf16[] = {11, 10, 13, 8, 6};
+    static const int order_fp8[] = {11, 14, 9, 8, 6};
+    static const int order_other[] = {11, 10, 9, 8, 6};
     static const int order_one_row[] = {0, 1, 2, 3, 4, 6};
+    const int* order = order_other;
     if (persistent) {
         for (int idx : order_one_row)
             if ((int64_t)pass_shape(idx).wg * pass_shape(idx).nc >= nv) return idx;
         return -1;
     }
-    for (int idx : order)
-        if ((int64_t)pass_shape(idx).wg * pass_shape(idx).nc >= nv) return idx;
+    if (k_dtype == UOT_F32 && !acc64) order = order_f32;
+    else if (k_dtype == UOT_BF16) order = order_bf16;
+    else if (k_dtype == UOT_FP8_E4M3) order = order_fp8;
+    for (int q = 0; q < 5; ++q)
+        if ((int64_t)pass_shape(order[q]).wg * pass_shape(order[q]).nc >= nv) return order[q];
     return -1;
 }
 
@@ -191,7 +201,7 @@ uot_status make_plan(const uot_problem* p, const uot_options* o, Plan& P) {
             return fail(UOT_ERR_UNSUPPORTED, "shape %d covers %lld columns, m=%lld", P.shape,
                         (long long)s.wg * s.nc * P.vec, (long long)p->m);
     } else {
-        P.shape = default_shape(nv, o->persistent != 0);
+        P.shape = default_shape(nv, o->persistent != 0, P.k_dtype, P.acc64);
         if (P.shape < 0)
             return fail(UOT_ERR_UNSUPPORTED, "m=%lld exceeds the row length one workgroup holds (%d columns)",
                         (long long)p->m, 4096 * P.vec);
@@ -205,6 +215,20 @@ uot_status make_plan(const uot_problem* p, const uot_options* o, Plan& P) {
     if (P.persistent && s.rb != 1)
         return fail(UOT_ERR_UNSUPPORTED, "the persistent loop runs the one-row shapes (0-7) only");
     int64_t target = 256LL * (1024 / s.wg);     // about one wave of workgroups on 256 CUs
+    if (!P.persistent) {
+        // Shapes whose registers allow fewer than 1024 lanes per CU: the
+        // grid above runs in several rounds of resident workgroups.  That
+        // pays only while each strip is long (measured: 2 MiB and 4 MiB
+        // strips gain from two rounds, 0.5 MiB and 1 MiB strips lose); with
+        // shorter strips the grid is cut to one round.
+        const size_t lds_est = (s.vlds ? (size_t)P.ldv_bytes : 0) + 2 * sizeof(double) * (size_t)((p->n + 255) / 256);
+        int dev = 0, cus = 0;
+        const int per_cu = pass_resident_per_cu(P.k_dtype, P.acc64, MODE_FUSED, P.shape, lds_est);
+        const int64_t strip_bytes = (p->n + target - 1) / target * p->m * elem_size(p->k_dtype);
+        if (per_cu > 0 && strip_bytes < (2LL << 20) && hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            target = std::min<int64_t>(target, (int64_t)per_cu * cus);
+    }
     if (P.persistent) {
         // LDS: max(v, finalize scratch of 4 doubles per thread), then the row strips
         P.scratch_bytes = round_up(std::max<int64_t>(s.vlds ? P.ldv_bytes : 0, (int64_t)s.wg * 32), 16);

@@ -213,6 +213,9 @@ static const PassShape kShapes[] = {
     {1024, 1, 2, 0, 4},   // 9: 4096 FP32 / 8192 BF16 columns, batches of 4 rows
     {512, 1, 2, 0, 4},    // 10: 2048 FP32 / 8192 FP8 columns, batches of 4 rows
     {256, 1, 2, 0, 4},    // 11: 1024 FP32 columns, batches of 4 rows
+    {512, 4, 2, 0, 2},    // 12: 8192 FP32 columns, 512 lanes, batches of 2 rows
+    {512, 2, 2, 0, 4},    // 13: 8192 BF16 columns, 512 lanes, batches of 4 rows
+    {512, 1, 2, 0, 8},    // 14: 8192 FP8 columns, 512 lanes, batches of 8 rows
 };
 static constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
@@ -221,8 +224,10 @@ PassShape pass_shape(int idx) { return kShapes[idx]; }
 
 // Launch one instantiation; raises its dynamic-LDS limit first when the
 // request exceeds the default 64 KiB (once per size increase).
+// With `resident` set, nothing is launched: *resident receives how many
+// workgroups of this instantiation fit on one CU with `lds` bytes of LDS.
 template <typename KT, typename AT, int WG, int NC, int D, bool VLDS, int MODE, int RB>
-static hipError_t launch_one(const PassLaunch& L, size_t lds, hipStream_t stream) {
+static hipError_t launch_one(const PassLaunch& L, size_t lds, hipStream_t stream, int* resident) {
     static size_t raised = 65536;
     auto fn = pass_kernel<KT, AT, WG, NC, D, VLDS, MODE, RB>;
     if (lds > raised) {
@@ -230,36 +235,41 @@ static hipError_t launch_one(const PassLaunch& L, size_t lds, hipStream_t stream
         if (e != hipSuccess) return e;
         raised = lds;
     }
+    if (resident) return hipOccupancyMaxActiveBlocksPerMultiprocessor(resident, (const void*)fn, WG, lds);
     hipLaunchKernelGGL(fn, dim3(L.grid), dim3(WG), lds, stream, L);
     return hipGetLastError();
 }
 
 template <typename KT, typename AT, int WG, int NC, int D, bool VLDS, int RB = 1>
-static hipError_t launch_shape(int mode, const PassLaunch& L, size_t lds, hipStream_t stream) {
+static hipError_t launch_shape(int mode, const PassLaunch& L, size_t lds, hipStream_t stream, int* resident) {
     switch (mode) {
-        case MODE_FUSED: return launch_one<KT, AT, WG, NC, D, VLDS, MODE_FUSED, RB>(L, lds, stream);
-        case MODE_ROW: return launch_one<KT, AT, WG, NC, D, VLDS, MODE_ROW, RB>(L, lds, stream);
-        case MODE_COL: return launch_one<KT, AT, WG, NC, D, VLDS, MODE_COL, RB>(L, lds, stream);
-        case MODE_MARG: return launch_one<KT, AT, WG, NC, D, VLDS, MODE_MARG, RB>(L, lds, stream);
+        case MODE_FUSED: return launch_one<KT, AT, WG, NC, D, VLDS, MODE_FUSED, RB>(L, lds, stream, resident);
+        case MODE_ROW: return launch_one<KT, AT, WG, NC, D, VLDS, MODE_ROW, RB>(L, lds, stream, resident);
+        case MODE_COL: return launch_one<KT, AT, WG, NC, D, VLDS, MODE_COL, RB>(L, lds, stream, resident);
+        case MODE_MARG: return launch_one<KT, AT, WG, NC, D, VLDS, MODE_MARG, RB>(L, lds, stream, resident);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <typename KT, typename AT>
-static hipError_t launch_typed(int mode, int shape_idx, const PassLaunch& L, size_t lds, hipStream_t stream) {
+static hipError_t launch_typed(int mode, int shape_idx, const PassLaunch& L, size_t lds, hipStream_t stream,
+                               int* resident) {
     switch (shape_idx) {
-        case 0: return launch_shape<KT, AT, 256, 1, 4, false>(mode, L, lds, stream);
-        case 1: return launch_shape<KT, AT, 512, 1, 4, false>(mode, L, lds, stream);
-        case 2: return launch_shape<KT, AT, 1024, 1, 4, false>(mode, L, lds, stream);
-        case 3: return launch_shape<KT, AT, 1024, 2, 3, false>(mode, L, lds, stream);
-        case 4: return launch_shape<KT, AT, 512, 4, 3, false>(mode, L, lds, stream);
-        case 5: return launch_shape<KT, AT, 512, 8, 2, true>(mode, L, lds, stream);
-        case 6: return launch_shape<KT, AT, 1024, 4, 2, true>(mode, L, lds, stream);
-        case 7: return launch_shape<KT, AT, 512, 8, 3, true>(mode, L, lds, stream);
-        case 8: return launch_shape<KT, AT, 1024, 2, 2, false, 2>(mode, L, lds, stream);
-        case 9: return launch_shape<KT, AT, 1024, 1, 2, false, 4>(mode, L, lds, stream);
-        case 10: return launch_shape<KT, AT, 512, 1, 2, false, 4>(mode, L, lds, stream);
-        case 11: return launch_shape<KT, AT, 256, 1, 2, false, 4>(mode, L, lds, stream);
+        case 0: return launch_shape<KT, AT, 256, 1, 4, false>(mode, L, lds, stream, resident);
+        case 1: return launch_shape<KT, AT, 512, 1, 4, false>(mode, L, lds, stream, resident);
+        case 2: return launch_shape<KT, AT, 1024, 1, 4, false>(mode, L, lds, stream, resident);
+        case 3: return launch_shape<KT, AT, 1024, 2, 3, false>(mode, L, lds, stream, resident);
+        case 4: return launch_shape<KT, AT, 512, 4, 3, false>(mode, L, lds, stream, resident);
+        case 5: return launch_shape<KT, AT, 512, 8, 2, true>(mode, L, lds, stream, resident);
+        case 6: return launch_shape<KT, AT, 1024, 4, 2, true>(mode, L, lds, stream, resident);
+        case 7: return launch_shape<KT, AT, 512, 8, 3, true>(mode, L, lds, stream, resident);
+        case 8: return launch_shape<KT, AT, 1024, 2, 2, false, 2>(mode, L, lds, stream, resident);
+        case 9: return launch_shape<KT, AT, 1024, 1, 2, false, 4>(mode, L, lds, stream, resident);
+        case 10: return launch_shape<KT, AT, 512, 1, 2, false, 4>(mode, L, lds, stream, resident);
+        case 11: return launch_shape<KT, AT, 256, 1, 2, false, 4>(mode, L, lds, stream, resident);
+        case 12: return launch_shape<KT, AT, 512, 4, 2, false, 2>(mode, L, lds, stream, resident);
+        case 13: return launch_shape<KT, AT, 512, 2, 2, false, 4>(mode, L, lds, stream, resident);
+        case 14: return launch_shape<KT, AT, 512, 1, 2, false, 8>(mode, L, lds, stream, resident);
         default: return hipErrorInvalidValue;
     }
 }
@@ -272,17 +282,29 @@ size_t pass_lds_bytes(int shape_idx, int mode, int acc64, const PassLaunch& L) {
     return b;
 }
 
+static hipError_t dispatch_pass(int k_dtype, int acc64, int mode, int shape_idx, const PassLaunch& L, size_t lds,
+                                hipStream_t stream, int* resident) {
+    if (k_dtype == UOT_F64) return launch_typed<double, double>(mode, shape_idx, L, lds, stream, resident);
+    if (k_dtype == UOT_F32) {
+        if (acc64) return launch_typed<float, double>(mode, shape_idx, L, lds, stream, resident);
+        return launch_typed<float, float>(mode, shape_idx, L, lds, stream, resident);
+    }
+    if (k_dtype == UOT_BF16) return launch_typed<bf16_t, float>(mode, shape_idx, L, lds, stream, resident);
+    if (k_dtype == UOT_FP8_E4M3) return launch_typed<fp8_t, float>(mode, shape_idx, L, lds, stream, resident);
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_pass(int k_dtype, int acc64, int mode, int shape_idx, const PassLaunch& L,
                        hipStream_t stream) {
-    size_t lds = pass_lds_bytes(shape_idx, mode, acc64, L);
-    if (k_dtype == UOT_F64) return launch_typed<double, double>(mode, shape_idx, L, lds, stream);
-    if (k_dtype == UOT_F32) {
-        if (acc64) return launch_typed<float, double>(mode, shape_idx, L, lds, stream);
-        return launch_typed<float, float>(mode, shape_idx, L, lds, stream);
-    }
-    if (k_dtype == UOT_BF16) return launch_typed<bf16_t, float>(mode, shape_idx, L, lds, stream);
-    if (k_dtype == UOT_FP8_E4M3) return launch_typed<fp8_t, float>(mode, shape_idx, L, lds, stream);
-    return hipErrorInvalidValue;
+    return dispatch_pass(k_dtype, acc64, mode, shape_idx, L, pass_lds_bytes(shape_idx, mode, acc64, L), stream,
+                         nullptr);
+}
+
+int pass_resident_per_cu(int k_dtype, int acc64, int mode, int shape_idx, size_t lds) {
+    int per_cu = 0;
+    PassLaunch L{};
+    if (dispatch_pass(k_dtype, acc64, mode, shape_idx, L, lds, nullptr, &per_cu) != hipSuccess) return 0;
+    return per_cu;
 }
 
 

@@ -227,14 +227,15 @@ struct Strip {
 #pragma unroll
                 for (int r = 0; r < RB; ++r) red[slot][r * NW + wave] = d[r];
             __syncthreads();
-            // Every lane forms the row totals in the same fixed order; lane r keeps row r's.
+            // Lane r NW + w takes wave w's sum of row r; each group of NW lanes
+            // adds its row's sums in a fixed tree, and lane r keeps row r's total.
+            static_assert(RB * NW <= 64, "one exchange entry per lane");
+            const double t = group_sum_f64<NW>(lane < RB * NW ? red[slot][lane] : 0.0);
             double tl = 0.0;
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
-                double tot = 0.0;
-#pragma unroll
-                for (int w = 0; w < NW; ++w) tot += red[slot][r * NW + w];
-                if (lane == r) tl = tot;
+                const double x = readlane_f64(t, r * NW);
+                if (lane == r) tl = x;
             }
             tl *= L.k_scale;
             slot ^= 1;

@@ -178,6 +178,18 @@ __device__ __forceinline__ double wave_sum_f64(double x) {
     return ((r0 + r1) + r2) + r3;
 }
 
+// Sum over aligned groups of G lanes (G = 1, 2, 4, 8 or 16), every lane of a
+// group returning the same bits: the first log2(G) exchanges of wave_sum_f64.
+template <int G>
+__device__ __forceinline__ double group_sum_f64(double x) {
+    static_assert(G == 1 || G == 2 || G == 4 || G == 8 || G == 16, "group of 1-16 lanes");
+    if constexpr (G >= 2) x += dpp_f64<0xB1>(x);
+    if constexpr (G >= 4) x += dpp_f64<0x4E>(x);
+    if constexpr (G >= 8) x += dpp_f64<0x141>(x);
+    if constexpr (G >= 16) x += dpp_f64<0x140>(x);
+    return x;
+}
+
 __device__ __forceinline__ double wave_max_f64(double x) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) x = fmax(x, __shfl_xor(x, off, 64));
@@ -269,6 +281,9 @@ struct PassShape {
 int pass_shape_count();
 PassShape pass_shape(int idx);
 size_t pass_lds_bytes(int shape_idx, int mode, int acc64, const PassLaunch& L);
+// Workgroups of a pass instantiation that fit on one CU with `lds` bytes of
+// dynamic LDS (0 on error).
+int pass_resident_per_cu(int k_dtype, int acc64, int mode, int shape_idx, size_t lds);
 
 // Launch one streaming pass; returns hipSuccess or an error.  k_dtype and
 // acc64 select the instantiation; shape_idx indexes pass_shape().

@@ -102,12 +102,12 @@ def test_ragged_sizes_fused_and_plain(n, m, dtype):
         compare(res, ref, tol, tol, f"n={n} m={m} fused={fused}")
 
 
-@pytest.mark.parametrize("shape", [1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12])
+@pytest.mark.parametrize("shape", [1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15])
 def test_every_launch_shape(shape):
     """Each instantiated launch shape (tune index) on a problem it covers;
     600 rows give workgroups a partial last batch in the row-batched shapes."""
     cover = {1: 1024, 2: 2048, 3: 4096, 4: 8192, 5: 8192, 6: 16384, 7: 16384, 8: 16384,
-             9: 8192, 10: 4096, 11: 2048, 12: 1024}[shape]
+             9: 8192, 10: 4096, 11: 2048, 12: 1024, 13: 8192, 14: 4096, 15: 2048}[shape]
     n = 600
     prob = workloads.headline(n=n, m=cover - 3, max_iter=12)
     ref = _oracle(prob)

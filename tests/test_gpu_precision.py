@@ -91,12 +91,14 @@ def _rel(a, b):
     return float(np.max(np.abs(a - b) / np.abs(b)))
 
 
+@pytest.mark.parametrize("m", [1111, 7999])
 @pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16, torch.float8_e4m3fn])
-def test_stored_kernel_iteration_matches_oracle_on_same_kernel(dtype):
+def test_stored_kernel_iteration_matches_oracle_on_same_kernel(dtype, m):
     """Without absorption (eps = 0.02, so the normalised kernel spans e^-50
     .. 1): a stored K given to uot_sinkhorn against the oracle's plain
-    iteration on the oracle's rounding of the same K.  Ragged n, m."""
-    prob = workloads.precision(n=3001, m=1111, max_iter=120)
+    iteration on the oracle's rounding of the same K.  Ragged n, m; m = 7999
+    takes the 512-lane row-batched launch shapes of each storage type."""
+    prob = workloads.precision(n=3001 if m < 4000 else 1001, m=m, max_iter=120)
     prob.eps = 0.02
     C = oracle.cost_points(prob.x, prob.y, 0, True)
     f, g = _normalised_potentials(C)
