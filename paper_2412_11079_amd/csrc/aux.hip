@@ -4,6 +4,7 @@
 //     after its thread join), with the stopping test of Section 2.1;
 //   - initialisation, objective, cost from points, Gibbs kernel build.
 #include <algorithm>
+#include <cmath>
 
 #include "plan.h"
 #include "uot_common.h"
@@ -356,23 +357,88 @@ template <> struct Store<fp8_t> {
     static __device__ __forceinline__ fp8_t cv(double x) { return fp8_t{f64_to_e4m3(x)}; }
 };
 
+// Four adjacent stored entries written with one store (4-entry chunks start
+// at a multiple of 4 entries and rows at a multiple of 16 bytes).
+template <typename KT> struct Pack4;
+template <> struct Pack4<double> {
+    static __device__ __forceinline__ void put(double* p, const double* x) {
+        *(f64x2*)p = f64x2{x[0], x[1]};
+        *(f64x2*)(p + 2) = f64x2{x[2], x[3]};
+    }
+};
+template <> struct Pack4<float> {
+    static __device__ __forceinline__ void put(float* p, const double* x) {
+        *(f32x4*)p = f32x4{(float)x[0], (float)x[1], (float)x[2], (float)x[3]};
+    }
+};
+template <> struct Pack4<bf16_t> {
+    static __device__ __forceinline__ void put(bf16_t* p, const double* x) {
+        uint64_t w = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) w |= (uint64_t)f64_to_bf16(x[e]) << (16 * e);
+        *(uint64_t*)p = w;
+    }
+};
+template <> struct Pack4<fp8_t> {
+    static __device__ __forceinline__ void put(fp8_t* p, const double* x) {
+        uint32_t w = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) w |= (uint32_t)f64_to_e4m3(x[e]) << (8 * e);
+        *(uint32_t*)p = w;
+    }
+};
+
+// Each lane builds 4 adjacent entries of a row.  Exponents e = f_i + g_j -
+// C_ij below `cut` are stored as 0 without evaluating exp: cut sits a factor
+// e below the largest value the storage type rounds to zero (see zero_cut),
+// so the stored bits are the same.
 template <typename KT>
 __global__ void kernel_build(const double* __restrict__ C, int64_t ldc, int64_t n, int64_t m, double eps,
                              const double* __restrict__ f, const double* __restrict__ g,
-                             KT* __restrict__ K, int64_t ldk, double store_scale) {
+                             KT* __restrict__ K, int64_t ldk, double store_scale, double cut) {
+    const int64_t chunks = (ldk + 3) / 4;
     for (int64_t i = blockIdx.y; i < n; i += gridDim.y) {
         const double fi_ = f ? f[i] : 0.0;
-        for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < ldk;
-             j += (int64_t)gridDim.x * blockDim.x) {
-            double val = 0.0;
-            if (j < m) {
-                double e = fi_ - C[i * ldc + j];
-                if (g) e += g[j];
-                val = store_scale * exp(e / eps);
+        for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < chunks;
+             q += (int64_t)gridDim.x * blockDim.x) {
+            const int64_t j0 = 4 * q;
+            double val[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t j = j0 + e;
+                val[e] = 0.0;
+                if (j < m) {
+                    double x = fi_ - C[i * ldc + j];
+                    if (g) x += g[j];
+                    if (!(x < cut)) val[e] = store_scale * exp(x / eps);
+                }
             }
-            K[i * ldk + j] = Store<KT>::cv(val);
+            KT* p = K + i * ldk + j0;
+            if (j0 + 4 <= ldk) {
+                Pack4<KT>::put(p, val);
+            } else {
+                for (int e = 0; j0 + e < ldk; ++e) p[e] = Store<KT>::cv(val[e]);
+            }
         }
     }
+}
+
+// Exponent below which store_scale * exp(e / eps) certainly stores as 0:
+// the type's zero bound (FP64: exp underflows below 2^-1075; FP32: values up
+// to 2^-150 round to 0; BF16 here: below 2^-126; E4M3: up to 2^-10), one
+// unit of e / eps further down so that rounding of exp and of this bound
+// cannot matter.
+static double zero_cut(int k_dtype, double eps, double store_scale) {
+    if (!(store_scale > 0.0) || !(eps > 0.0)) return -INFINITY;
+    double lb;
+    switch (k_dtype) {
+        case UOT_F64: lb = -1075.0; break;
+        case UOT_F32: lb = -150.0; break;
+        case UOT_BF16: lb = -126.0; break;
+        case UOT_FP8_E4M3: lb = -10.0; break;
+        default: return -INFINITY;
+    }
+    return (lb * std::log(2.0) - std::log(store_scale) - 1.0) * eps;
 }
 
 static dim3 row_grid(int64_t n, int64_t cols) {
@@ -387,23 +453,24 @@ static dim3 row_grid(int64_t n, int64_t cols) {
 hipError_t launch_kernel_build(const double* C, int64_t ldc, int64_t n, int64_t m, double eps,
                                const double* f, const double* g, int k_dtype, void* K, int64_t ldk,
                                double store_scale, hipStream_t stream) {
-    dim3 grid = row_grid(n, ldk), block(256);
+    dim3 grid = row_grid(n, (ldk + 3) / 4), block(256);
+    const double cut = zero_cut(k_dtype, eps, store_scale);
     switch (k_dtype) {
         case UOT_F64:
             hipLaunchKernelGGL(kernel_build<double>, grid, block, 0, stream, C, ldc, n, m, eps, f, g, (double*)K, ldk,
-                               store_scale);
+                               store_scale, cut);
             break;
         case UOT_F32:
             hipLaunchKernelGGL(kernel_build<float>, grid, block, 0, stream, C, ldc, n, m, eps, f, g, (float*)K, ldk,
-                               store_scale);
+                               store_scale, cut);
             break;
         case UOT_BF16:
             hipLaunchKernelGGL(kernel_build<bf16_t>, grid, block, 0, stream, C, ldc, n, m, eps, f, g, (bf16_t*)K,
-                               ldk, store_scale);
+                               ldk, store_scale, cut);
             break;
         case UOT_FP8_E4M3:
             hipLaunchKernelGGL(kernel_build<fp8_t>, grid, block, 0, stream, C, ldc, n, m, eps, f, g, (fp8_t*)K, ldk,
-                               store_scale);
+                               store_scale, cut);
             break;
         default: return hipErrorInvalidValue;
     }
@@ -470,6 +537,78 @@ __global__ __launch_bounds__(256) void colmin_kernel(const double* __restrict__ 
     atomicMin(&gmin_keys[j], min_key(mn));
 }
 
+// Row and column minima in one read of C, for rows of up to 1024 CPT
+// columns.  Each 1024-lane workgroup takes a strip of rows; a row is held in
+// registers (lane t: columns t, t + 1024, ...) while the next row's loads
+// are in flight; g sits in LDS.  Its minimum of C_ij - g_j gives f_i (u_i is rescaled as in
+// rowmin_kernel), and the same registers then update the lane's running
+// minima of C_ij - f_i, which go to the column keys with one atomic min per
+// column at the end.  The results equal those of the two separate kernels:
+// a minimum does not depend on the order it is taken in.
+template <int CPT>
+__global__ __launch_bounds__(1024) void rowcolmin_kernel(const double* __restrict__ C, int64_t ldc, int64_t n,
+                                                         int64_t m, double eps, double* __restrict__ f,
+                                                         const double* __restrict__ g, double* __restrict__ u,
+                                                         int first, unsigned long long* __restrict__ gmin_keys,
+                                                         int64_t rows_per_block) {
+    __shared__ double wmin[2][16];
+    extern __shared__ double gsh[];            // g, 1024 CPT entries
+    const int t = threadIdx.x;
+    double cmin[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const int64_t j = (int64_t)c * 1024 + t;
+        gsh[c * 1024 + t] = j < m ? g[j] : 0.0;
+        cmin[c] = INFINITY;
+    }
+    __syncthreads();
+    const int64_t i0 = (int64_t)blockIdx.x * rows_per_block;
+    int64_t i1 = i0 + rows_per_block;
+    if (i1 > n) i1 = n;
+    double x[2][CPT];
+    auto load = [&](int q, int64_t i) {
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            const int64_t j = (int64_t)c * 1024 + t;
+            x[q][c] = (j < m && i < i1) ? C[i * ldc + j] : INFINITY;
+        }
+    };
+    int slot = 0;
+    auto row = [&](int q, int64_t i) {
+        double mn = INFINITY;
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) mn = fmin(mn, x[q][c] - gsh[c * 1024 + t]);
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) mn = fmin(mn, __shfl_xor(mn, off, 64));
+        if ((t & 63) == 0) wmin[slot][t >> 6] = mn;
+        __syncthreads();
+        double fnew = wmin[slot][0];
+#pragma unroll
+        for (int w = 1; w < 16; ++w) fnew = fmin(fnew, wmin[slot][w]);
+        slot ^= 1;
+        if (t == 0) {
+            const double fold = first ? 0.0 : f[i];
+            if (u[i] > 0.0) u[i] = exp(log(u[i]) + (fold - fnew) / eps);
+            f[i] = fnew;
+        }
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) cmin[c] = fmin(cmin[c], x[q][c] - fnew);
+    };
+    load(0, i0);
+    for (int64_t i = i0; i < i1; i += 2) {
+        load(1, i + 1);
+        row(0, i);
+        if (i + 1 >= i1) break;
+        load(0, i + 2);
+        row(1, i + 1);
+    }
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const int64_t j = (int64_t)c * 1024 + t;
+        if (j < m && i1 > i0) atomicMin(&gmin_keys[j], min_key(cmin[c]));
+    }
+}
+
 __global__ void fill_bits_kernel(unsigned long long* p, int64_t count, unsigned long long bits) {
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x)
         p[t] = bits;
@@ -489,31 +628,49 @@ __global__ void gshift_kernel(const unsigned long long* __restrict__ gmin_keys, 
 hipError_t launch_rebuild(const double* C, int64_t ldc, int64_t n, int64_t m, double eps, double* f, double* g,
                           double* u, double* v, void* gmin_scratch, int k_dtype, void* K, int64_t ldk,
                           double store_scale, int first, hipStream_t stream) {
-    const int rblocks = (int)(n < 65536 ? n : 65536);
-    hipLaunchKernelGGL(rowmin_kernel, dim3(rblocks), dim3(256), 0, stream, C, ldc, n, m, eps, f, g, u, first);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
     unsigned long long* gb = (unsigned long long*)gmin_scratch;
     const unsigned long long inf_bits = 0xfff0000000000000ull;   // min_key(+inf)
     int fb = (int)((m + 255) / 256);
     if (fb > 1024) fb = 1024;
     hipLaunchKernelGGL(fill_bits_kernel, dim3(fb), dim3(256), 0, stream, gb, m, inf_bits);
-    const int64_t rows_per_block = 256;
-    dim3 cgrid((unsigned)((m + 255) / 256), (unsigned)((n + rows_per_block - 1) / rows_per_block));
-    hipLaunchKernelGGL(colmin_kernel, cgrid, dim3(256), 0, stream, C, ldc, n, m, f, gb, rows_per_block);
+    if (m <= 1024 * 8) {
+        // one read of C, one strip per CU
+        const int64_t rpb = (n + 255) / 256;
+        const unsigned blocks = (unsigned)((n + rpb - 1) / rpb);
+        if (m <= 1024 * 2)
+            hipLaunchKernelGGL(rowcolmin_kernel<2>, dim3(blocks), dim3(1024), 2 * 1024 * sizeof(double), stream, C,
+                               ldc, n, m, eps, f, g, u, first, gb, rpb);
+        else if (m <= 1024 * 4)
+            hipLaunchKernelGGL(rowcolmin_kernel<4>, dim3(blocks), dim3(1024), 4 * 1024 * sizeof(double), stream, C,
+                               ldc, n, m, eps, f, g, u, first, gb, rpb);
+        else
+            hipLaunchKernelGGL(rowcolmin_kernel<8>, dim3(blocks), dim3(1024), 8 * 1024 * sizeof(double), stream, C,
+                               ldc, n, m, eps, f, g, u, first, gb, rpb);
+    } else {
+        const int rblocks = (int)(n < 65536 ? n : 65536);
+        hipLaunchKernelGGL(rowmin_kernel, dim3(rblocks), dim3(256), 0, stream, C, ldc, n, m, eps, f, g, u, first);
+        const int64_t rows_per_block = 256;
+        dim3 cgrid((unsigned)((m + 255) / 256), (unsigned)((n + rows_per_block - 1) / rows_per_block));
+        hipLaunchKernelGGL(colmin_kernel, cgrid, dim3(256), 0, stream, C, ldc, n, m, f, gb, rows_per_block);
+    }
     hipLaunchKernelGGL(gshift_kernel, dim3(fb), dim3(256), 0, stream, gb, g, v, m, eps, first);
-    e = hipGetLastError();
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_kernel_build(C, ldc, n, m, eps, f, g, k_dtype, K, ldk, store_scale, stream);
 }
 
-__global__ __launch_bounds__(1024) void absorb_check_kernel(const double* u, int64_t n, const double* v, int64_t m,
-                                                           double* out) {
-    __shared__ double red[2][16];
+// max |log u_i| and max |log v_j| (over positive entries) into out[0], out[1]
+// as the bit patterns of non-negative doubles, whose unsigned order is their
+// numeric order: each workgroup takes a slice and atomically maxes its result
+// (exact and order independent).  out must start at +0.
+__global__ __launch_bounds__(256) void absorb_check_kernel(const double* u, int64_t n, const double* v, int64_t m,
+                                                          unsigned long long* out) {
+    __shared__ double red[2][4];
     double mu = 0.0, mv = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += 1024)
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride)
         if (u[i] > 0.0) mu = fmax(mu, fabs(log(u[i])));
-    for (int64_t j = threadIdx.x; j < m; j += 1024)
+    for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < m; j += stride)
         if (v[j] > 0.0) mv = fmax(mv, fabs(log(v[j])));
     mu = wave_max_f64(mu);
     mv = wave_max_f64(mv);
@@ -524,18 +681,23 @@ __global__ __launch_bounds__(1024) void absorb_check_kernel(const double* u, int
     __syncthreads();
     if (threadIdx.x == 0) {
         double a = 0.0, b = 0.0;
-        for (int w = 0; w < 16; ++w) {
+        for (int w = 0; w < 4; ++w) {
             a = fmax(a, red[0][w]);
             b = fmax(b, red[1][w]);
         }
-        out[0] = a;
-        out[1] = b;
+        atomicMax(&out[0], (unsigned long long)__double_as_longlong(a));
+        atomicMax(&out[1], (unsigned long long)__double_as_longlong(b));
     }
 }
 
 hipError_t launch_absorb_check(const double* u, int64_t n, const double* v, int64_t m, double* out,
                                hipStream_t stream) {
-    hipLaunchKernelGGL(absorb_check_kernel, dim3(1), dim3(1024), 0, stream, u, n, v, m, out);
+    unsigned long long* keys = (unsigned long long*)out;
+    hipLaunchKernelGGL(fill_bits_kernel, dim3(1), dim3(64), 0, stream, keys, (int64_t)2, 0ull);
+    int64_t blocks = (std::max(n, m) + 255) / 256;
+    if (blocks > 256) blocks = 256;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(absorb_check_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, u, n, v, m, keys);
     return hipGetLastError();
 }
 
