@@ -136,6 +136,22 @@ __global__ __launch_bounds__(256) void mgemm_kernel(MGemm G) {
             }
 }
 
+// Tile of this workgroup.  Workgroups are dispatched round-robin over the
+// 8 XCDs (linear id mod 8), so the linear id is remapped to make each XCD
+// run a contiguous range of tiles: the two column tiles of a row tile and
+// neighbouring row tiles of a k-chunk, which share operand rows, then meet
+// in the same L2.
+struct TileIdx {
+    uint32_t x, y, z;
+};
+__device__ __forceinline__ TileIdx xcd_tile() {
+    const uint32_t gx = gridDim.x, gy = gridDim.y, gz = gridDim.z;
+    const uint32_t total = gx * gy * gz;
+    const uint32_t id = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const uint32_t L = (total % 8 == 0) ? (id % 8) * (total / 8) + id / 8 : id;
+    return TileIdx{L % gx, (L / gx) % gy, L / (gx * gy)};
+}
+
 // Same product with the workgroup's operand tiles staged through LDS
 // (double-buffered, one barrier per stage): each A row and each
 // right-hand side is fetched from memory once per workgroup and read by
@@ -159,9 +175,10 @@ __global__ __launch_bounds__(256) void mgemm_lds_kernel(MGemm G) {
     const int lr = l & 31;
     const int lh = l >> 5;
     const int wm = w & 1, wn = w >> 1;
-    const int64_t tile_r = (int64_t)blockIdx.y * kMTileRows;
-    const int64_t tile_c = (int64_t)blockIdx.x * kMTileCols;
-    const int64_t k_begin = (int64_t)blockIdx.z * G.kchunk;
+    const TileIdx ti = xcd_tile();
+    const int64_t tile_r = (int64_t)ti.y * kMTileRows;
+    const int64_t tile_c = (int64_t)ti.x * kMTileCols;
+    const int64_t k_begin = (int64_t)ti.z * G.kchunk;
     int64_t k_end = k_begin + G.kchunk;
     if (k_end > G.kdim_pad) k_end = G.kdim_pad;
 
@@ -214,16 +231,7 @@ __global__ __launch_bounds__(256) void mgemm_lds_kernel(MGemm G) {
 #pragma unroll
             for (int q = 0; q < 16; ++q) acc[t][u][q] = 0.0f;
 
-    const int nst = (int)((k_end - k_begin + BK - 1) / BK);
-    if (nst > 0) {
-        fetch(k_begin);
-        stash(0);
-        __syncthreads();
-    }
-    for (int st = 0; st < nst; ++st) {
-        const int buf = st & 1;
-        const bool more = st + 1 < nst;
-        if (more) fetch(k_begin + (int64_t)(st + 1) * BK);
+    auto compute = [&](int buf) {
         const unsigned char* base = lds + buf * STAGE;
         // two MFMA k-steps per stage: 16 values (BF16) or 8 (FP32, 4 per lane half)
 #pragma unroll
@@ -259,13 +267,24 @@ __global__ __launch_bounds__(256) void mgemm_lds_kernel(MGemm G) {
                                 __uint_as_float(af[t][q]), __uint_as_float(xf[0][u][q]), acc[t][u], 0, 0, 0);
             }
         }
-        if (more) {
-            stash(buf ^ 1);
-        }
+    };
+
+    const int nst = (int)((k_end - k_begin + BK - 1) / BK);
+    if (nst > 0) {
+        fetch(k_begin);
+        stash(0);
+        __syncthreads();
+    }
+    for (int st = 0; st < nst; ++st) {
+        const int buf = st & 1;
+        const bool more = st + 1 < nst;
+        if (more) fetch(k_begin + (int64_t)(st + 1) * BK);
+        compute(buf);
+        if (more) stash(buf ^ 1);
         __syncthreads();
     }
 
-    float* P = G.part + (int64_t)blockIdx.z * G.r_pad * G.ld_part;
+    float* P = G.part + (int64_t)ti.z * G.r_pad * G.ld_part;
     const int64_t row0 = tile_r + wm * 64, col0 = tile_c + wn * 64;
 #pragma unroll
     for (int t = 0; t < 2; ++t)
