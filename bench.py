@@ -308,6 +308,7 @@ def batched(uot, workloads, torch, dev, args):
                         f"tau=1, {T} iterations, one persistent launch (HIP graph replay)",
             "ms_per_solve": round(ms, 3), "problem_iters_per_s": round(len(probs) * T / (ms * 1e-3), 1),
             "k_bytes_tb_s": round(kbytes / (ms * 1e-3) / 1e12, 3), "tail_idle_fraction": round(tail, 4),
+            "split_problems": solver.nsplit, "queue_entries": solver.items,
             "plain_one_by_one_ms_est": round(single_ms, 1),
             "speedup_over_one_by_one": round(single_ms / ms, 2)}
 

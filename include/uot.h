@@ -156,7 +156,9 @@ typedef struct uot_batched_meta {
     int32_t count;            /* problems in the block */
     int32_t k_dtype;          /* their common K dtype */
     int64_t m_lds;            /* FP64 values per LDS vector the launch needs */
-    int64_t reserved[2];
+    int32_t items;            /* queue entries (a split problem has one per part) */
+    int32_t nsplit;           /* problems split over several workgroups */
+    int64_t pool_bytes;       /* workspace bytes their exchanges use */
 } uot_batched_meta;
 
 /* Status text, and a thread-local description of the last error. */
@@ -337,9 +339,18 @@ uot_status uot_sinkhorn_backward(const uot_problem* prob, const uot_options* opt
  * workgroup per problem).
  *
  * Each workgroup takes problems from a device queue in longest-first order
- * (work n*m*sizeof(K) per iteration) and runs all of a problem's iterations
- * by itself; no grid-wide synchronisation, no host round trip.  Products,
- * row sums and column sums are FP64 on the widened stored K.  Every problem
+ * (estimated time: the rows each row group of the problem's tile shape steps
+ * through, weighted by the chunks per lane) and runs all of a problem's
+ * iterations by itself; no grid-wide synchronisation, no host round trip.
+ * A problem whose estimated time exceeds the average per resident
+ * workgroup is split by rows into up to 4 queue entries that run side by
+ * side on as many workgroups and exchange their column sums once per
+ * iteration (at most 256 split problems, whose parts take at most 3/4 of
+ * the resident workgroups; split problems are queued first, so all parts
+ * of a problem run at the same time).  Products, row sums and column sums are FP64 on
+ * the widened stored K; a split problem adds its parts' column sums in part
+ * order, so its result is the same FP64 iteration up to summation order.
+ * Every problem
  * runs exactly opt->max_iter iterations, or stops after the first check
  * (every check_every iterations) whose relative L1 change of the column
  * marginal is <= opt->tol, then forms r = u*(K v), c = v*(K^T u) and the
@@ -355,7 +366,8 @@ uot_status uot_sinkhorn_backward(const uot_problem* prob, const uot_options* opt
  *   absorption, checkpoint, warm-start and cooperative options must be off
  *   (else UOT_ERR_UNSUPPORTED).
  * Workspace: uot_sinkhorn_batched_workspace_size(count) bytes, 256-byte
- * aligned.  This call copies the descriptors from pageable host memory and
+ * aligned (queue head, descriptors, exchange pool of the split problems).
+ * This call copies the descriptors from pageable host memory and
  * synchronises `stream` once before launching; use the packed form below
  * to capture the launch in a HIP graph.
  * Errors: UOT_ERR_ARG, UOT_ERR_DTYPE, UOT_ERR_ALIGN, UOT_ERR_WORKSPACE,
@@ -375,9 +387,14 @@ uot_status uot_sinkhorn_batched(const uot_problem* probs, int32_t count, const u
  * sizeof(uot_batched_meta) bytes to 16-byte aligned device memory), then a
  * uot_batched_meta.  The descriptors hold the problems' device pointers:
  * they must stay valid while the block is used.
- * uot_sinkhorn_batched_packed enqueues the queue reset and the persistent
- * launch.  trace (optional, device, 2*count uint64): per problem (in queue
- * order) the device wall clock when a workgroup took it and when it
+ * meta->items queue entries are written (count plus one more per extra part
+ * of a split problem; the index word of each descriptor names its problem).
+ * Splitting needs the device's resident workgroup count, so a pack without
+ * a device splits nothing.
+ * uot_sinkhorn_batched_packed enqueues the reset of the queue and of the
+ * split problems' counters, and the persistent launch; ws as for
+ * uot_sinkhorn_batched.  trace (optional, device, 2*meta->items uint64): per
+ * queue entry the device wall clock when a workgroup took it and when it
  * finished; uot_device_wall_clock_khz gives the clock's rate.
  * uot_batched_tune runs only the autotuning step (results are kept for the
  * process, per K dtype and column-count bucket, and used by later packs).

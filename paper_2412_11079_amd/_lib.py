@@ -49,7 +49,8 @@ class Profile(ctypes.Structure):
 
 
 class BatchedMeta(ctypes.Structure):
-    _fields_ = [("count", _i32), ("k_dtype", _i32), ("m_lds", _i64), ("reserved", _i64 * 2)]
+    _fields_ = [("count", _i32), ("k_dtype", _i32), ("m_lds", _i64), ("items", _i32), ("nsplit", _i32),
+                ("pool_bytes", _i64)]
 
 
 # Every symbol that include/uot.h declares, with its ctypes signature.

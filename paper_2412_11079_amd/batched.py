@@ -129,10 +129,13 @@ class BatchedSolver:
         meta_off = nbytes - ctypes.sizeof(_lib.BatchedMeta)
         self.meta = _lib.BatchedMeta.from_buffer_copy(bytes(host)[meta_off:])
         self.desc = torch.frombuffer(bytearray(bytes(host)[:meta_off]), dtype=torch.uint8).to(device)
-        words = np.frombuffer(bytes(host)[:count * _DESC_WORDS * 8], dtype=np.int64).reshape(count, _DESC_WORDS)
-        self.order = [int(x) for x in words[:, _DESC_INDEX_WORD]]
-        self.trace = torch.zeros(2 * count, dtype=torch.int64, device=device) if trace else None
+        items = int(self.meta.items)
+        words = np.frombuffer(bytes(host)[:items * _DESC_WORDS * 8], dtype=np.int64).reshape(items, _DESC_WORDS)
+        self.order = [int(x) for x in words[:, _DESC_INDEX_WORD]]      # problem of each queue entry
+        self.trace = torch.zeros(2 * items, dtype=torch.int64, device=device) if trace else None
         self.count = count
+        self.items = items
+        self.nsplit = int(self.meta.nsplit)
         self.device = device
         self._keep = (list(Ks), list(a_list), list(b_list))
 
@@ -152,29 +155,36 @@ class BatchedSolver:
 
     def shapes(self) -> List[int]:
         """Tile shape assigned to each problem (caller's order)."""
-        words = self.desc.cpu().numpy()[:self.count * _DESC_WORDS * 8].view(np.int64).reshape(self.count, _DESC_WORDS)
+        words = self.desc.cpu().numpy()[:self.items * _DESC_WORDS * 8].view(np.int64).reshape(self.items, _DESC_WORDS)
         shape_word = words[:, _DESC_SHAPE_WORD]
         out = [0] * self.count
-        for q in range(self.count):
+        for q in range(self.items):
             out[self.order[q]] = int(shape_word[q] >> 32)
         return out
 
+    def parts(self) -> List[int]:
+        """Queue entries (workgroups) each problem runs on (caller's order)."""
+        out = [0] * self.count
+        for q in range(self.items):
+            out[self.order[q]] += 1
+        return out
+
     def tail_idle_fraction(self) -> Optional[float]:
-        """1 - (sum of per-problem busy times) / (workgroups x makespan),
+        """1 - (sum of per-entry busy times) / (workgroups x makespan),
         from the device wall-clock stamps of the last traced run."""
         if self.trace is None:
             return None
         t = self.trace.cpu().numpy().reshape(-1, 2)
         busy = float(np.sum(t[:, 1] - t[:, 0]))
         span = float(t[:, 1].max() - t[:, 0].min())
-        grid = min(self.count, _max_grid_estimate(self))
+        grid = min(self.items, _max_grid_estimate(self))
         return 1.0 - busy / (grid * span) if span > 0 else 0.0
 
 
-# BatchDesc layout (csrc/batch.h, size and offsets asserted there): 18
+# BatchDesc layout (csrc/batch.h, size and offsets asserted there): 22
 # 8-byte words; word 16 packs fi_is_one (low half) and shape (high half),
 # word 17 is the caller's index of the problem.
-_DESC_WORDS = 18
+_DESC_WORDS = 22
 _DESC_SHAPE_WORD = 16
 _DESC_INDEX_WORD = 17
 

@@ -890,11 +890,45 @@ int batch_shape_for(int64_t m, int k_dtype) {
     return batch_default_shape(m, k_dtype);
 }
 
-size_t batch_desc_bytes(int32_t count) { return align_up(sizeof(BatchDesc) * (size_t)std::max(count, 1), kAlign); }
+// Splitting of large batched problems across workgroups (see pack_batch).
+constexpr int kMaxParts = 4;            // parts per split problem
+constexpr int32_t kMaxSplit = 256;      // split problems per batch
+constexpr int64_t kMaxBatchM = 4096;    // widest batched row (FP8; FP32 and BF16 hold 2048)
 
-// Descriptors in longest-first order (work n*m*sizeof(K) per iteration).
+int32_t batch_max_splits(int32_t count) { return std::min(count, kMaxSplit); }
+// Queue entries: every problem, plus up to kMaxParts - 1 more per split problem.
+int32_t batch_max_items(int32_t count) { return count + (kMaxParts - 1) * batch_max_splits(count); }
+size_t batch_desc_bytes(int32_t count) {
+    return align_up(sizeof(BatchDesc) * (size_t)std::max(batch_max_items(count), 1), kAlign);
+}
+size_t batch_pool_bytes(int32_t count) {
+    const int32_t s = batch_max_splits(count);
+    return align_up(kBatchHeaderBytes * (size_t)s, kAlign) + (size_t)s * align_up(batch_xch_bytes(kMaxParts, kMaxBatchM), kAlign);
+}
+
+// Queue entries of a batch.  A workgroup's time on a problem grows with the
+// rows each of its row groups steps through, ceil(n / rg) per iteration,
+// and with the chunks per lane (measured on the batched workload: about
+// 0.7 us per row step at one chunk, 1.05 us at two, per iteration), so the
+// estimated cost ceil(n / rg) (3 + nc) orders the queue, longest first.
+// With `allow_split` (and a device to count the resident workgroups), a
+// problem whose cost exceeds the average cost per workgroup is split by
+// rows into up to kMaxParts parts that run on as many workgroups and
+// exchange their column sums once per iteration.  Split problems go first
+// in the queue, each with its parts consecutive, and all their parts
+// together take at most 3/4 of the resident workgroups, so every part is
+// running while its siblings wait for it.
+struct BatchPack {
+    std::vector<BatchDesc> d;
+    int64_t m_lds = 0;
+    int32_t nsplit = 0;
+    size_t pool_used = 0;
+};
+
+int batch_grid_estimate(int k_dtype, int64_t m_cap);
+
 uot_status pack_batch(const uot_problem* probs, int32_t count, const uot_options* o, const uot_outputs* outs,
-                      std::vector<BatchDesc>& d, int64_t& m_lds) {
+                      bool allow_split, BatchPack& pk) {
     uot_status st = check_batch_options(o);
     if (st != UOT_OK) return st;
     if (count < 0) return fail(UOT_ERR_ARG, "count must be >= 0");
@@ -905,11 +939,53 @@ uot_status pack_batch(const uot_problem* probs, int32_t count, const uot_options
         if (st != UOT_OK) return st;
         order[i] = i;
     }
-    auto work = [&](int32_t i) { return probs[i].n * probs[i].m * (int64_t)elem_size(probs[i].k_dtype); };
-    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return work(x) > work(y); });
-    d.assign(count, BatchDesc{});
-    m_lds = 0;
     const int kd = count > 0 ? probs[0].k_dtype : UOT_F32;
+    std::vector<int64_t> cost(count);
+    for (int32_t i = 0; i < count; ++i) {
+        const int sh = batch_shape_for(probs[i].m, kd);
+        const int rg = sh >= 0 ? batch_shape_rows(sh) : 1;
+        const int nc = sh >= 0 ? batch_shape_chunks(sh) : 1;
+        cost[i] = (probs[i].n + rg - 1) / rg * (3 + nc);
+    }
+    auto work = [&](int32_t i) { return cost[i]; };
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return work(x) > work(y); });
+
+    // parts per problem (in queue order)
+    std::vector<int> parts(count, 1);
+    int grid = 0;
+    if (allow_split && count > 1) {
+        int64_t m_cap = 0;
+        for (int32_t i = 0; i < count; ++i) {
+            const int sh = batch_shape_for(probs[i].m, kd);
+            if (sh >= 0) m_cap = std::max(m_cap, batch_shape_max_m(sh, kd));
+        }
+        grid = batch_grid_estimate(kd, m_cap);
+    }
+    if (grid > 0 && count > 1) {
+        int64_t total = 0;
+        for (int32_t i = 0; i < count; ++i) total += work(i);
+        const int64_t avg = std::max<int64_t>(1, total / grid);
+        int budget = grid * 3 / 4;                   // workgroups the split parts may hold
+        int32_t nsplit = 0;
+        for (int32_t q = 0; q < count && nsplit < kMaxSplit; ++q) {
+            const uot_problem& p = probs[order[q]];
+            int pp = (int)std::min<int64_t>(kMaxParts, (work(order[q]) + avg - 1) / avg);
+            pp = (int)std::min<int64_t>(pp, p.n / 16);
+            // a part's time per iteration must stay well above the exchange's
+            // few microseconds: at least 512 cost units (about 100 us) each
+            pp = (int)std::min<int64_t>(pp, work(order[q]) / 512);
+            if (pp < 2 || p.m > kMaxBatchM || pp > budget) break;
+            parts[q] = pp;
+            budget -= pp;
+            ++nsplit;
+        }
+    }
+
+    pk.d.clear();
+    pk.m_lds = 0;
+    pk.nsplit = 0;
+    const int32_t nsplit_all = (int32_t)std::count_if(parts.begin(), parts.end(), [](int x) { return x > 1; });
+    size_t xoff = align_up(kBatchHeaderBytes * (size_t)nsplit_all, kAlign);
     for (int32_t q = 0; q < count; ++q) {
         const uot_problem& p = probs[order[q]];
         const uot_outputs& out = outs[order[q]];
@@ -918,7 +994,7 @@ uot_status pack_batch(const uot_problem* probs, int32_t count, const uot_options
         if (shape < 0)
             return fail(UOT_ERR_UNSUPPORTED, "problem %d: m = %lld exceeds the batched row capacity (%lld)",
                         order[q], (long long)p.m, (long long)batch_shape_max_m(batch_shape_count() - 1, kd));
-        BatchDesc& b = d[q];
+        BatchDesc b{};
         b.K = p.K;
         b.ldk = p.ldk;
         b.n = p.n;
@@ -938,9 +1014,42 @@ uot_status pack_batch(const uot_problem* probs, int32_t count, const uot_options
         b.tau = p.tau;
         b.shape = shape;
         b.index = order[q];
-        m_lds = std::max(m_lds, batch_shape_max_m(shape, kd));
+        b.part = 0;
+        b.parts = 1;
+        pk.m_lds = std::max(pk.m_lds, batch_shape_max_m(shape, kd));
+        if (parts[q] == 1) {
+            pk.d.push_back(b);
+            continue;
+        }
+        const int P = parts[q];
+        b.parts = P;
+        b.split = pk.nsplit++;
+        b.xch = (int64_t)xoff;
+        xoff += align_up(batch_xch_bytes(P, p.m), kAlign);
+        const int64_t rows = (p.n + P - 1) / P;
+        const int es = elem_size(kd);
+        for (int k = 0; k < P; ++k) {
+            BatchDesc c = b;
+            const int64_t r0 = k * rows;
+            c.part = k;
+            c.n = std::min(rows, p.n - r0);
+            c.K = (const char*)p.K + r0 * p.ldk * es;
+            c.a = (const double*)p.a + r0;
+            c.u = (double*)out.u + r0;
+            c.r = out.r + r0;
+            pk.d.push_back(c);
+        }
     }
+    pk.pool_used = xoff;
     return UOT_OK;
+}
+
+// Resident workgroups of the batched kernel for a batch's LDS need (0
+// without a device).
+int batch_grid_estimate(int k_dtype, int64_t m_cap) {
+    const size_t lds = batch_lds_bytes(m_cap);
+    if ((int64_t)lds > max_lds_bytes()) return 0;
+    return std::max(0, batch_max_grid(k_dtype, lds));
 }
 
 struct BatchRun {
@@ -959,23 +1068,30 @@ uot_status batch_launch_config(int k_dtype, int64_t m_lds, int32_t count, BatchR
     return UOT_OK;
 }
 
-uot_status run_batch_packed(const BatchDesc* desc_dev, int32_t count, int k_dtype, int64_t m_lds,
-                            const uot_options* o, void* ws, size_t ws_bytes, uint64_t* trace, hipStream_t stream) {
-    if (count == 0) return UOT_OK;
-    if (!ws || ws_bytes < kAlign || !aligned(ws, kAlign)) return fail(UOT_ERR_WORKSPACE, "workspace too small or misaligned");
+// items: queue entries; nsplit, pool_bytes: the split problems and the bytes
+// of exchange pool they use.  Workspace: the queue head, then (from
+// kAlign + pool_offset) the exchange pool.
+uot_status run_batch_packed(const BatchDesc* desc_dev, int32_t items, int32_t nsplit, size_t pool_offset,
+                            size_t pool_bytes, int k_dtype, int64_t m_lds, const uot_options* o, void* ws,
+                            size_t ws_bytes, uint64_t* trace, hipStream_t stream) {
+    if (items == 0) return UOT_OK;
+    if (!ws || ws_bytes < kAlign + pool_offset + pool_bytes || !aligned(ws, kAlign))
+        return fail(UOT_ERR_WORKSPACE, "workspace too small or misaligned");
     BatchRun R;
-    uot_status st = batch_launch_config(k_dtype, m_lds, count, R);
+    uot_status st = batch_launch_config(k_dtype, m_lds, items, R);
     if (st != UOT_OK) return st;
     BatchLaunch B;
     memset(&B, 0, sizeof(B));
     B.desc = desc_dev;
-    B.count = count;
+    B.count = items;
     B.max_iter = o->max_iter;
     B.tol = o->tol;
     B.check_every = std::max(o->check_every, 1);
     B.m_lds = m_lds;
     B.next = (uint32_t*)ws;
     B.trace = trace;
+    B.pool = (unsigned char*)ws + kAlign + pool_offset;
+    B.nsplit = nsplit;
     UOT_HIP(launch_batch(k_dtype, B, R.grid, R.lds, stream), "batched launch");
     return UOT_OK;
 }
@@ -1010,24 +1126,26 @@ uot_status autotune_batch(const uot_problem* probs, int32_t count, const uot_opt
         float best_ms = 0.0f;
         for (int s = 0; s < batch_shape_count() && st == UOT_OK; ++s) {
             if (!batch_shape_ok(s, kd) || batch_shape_max_m(s, kd) < mmax) continue;
-            std::vector<BatchDesc> d;
-            int64_t m_lds = 0;
+            BatchPack pk;
             std::vector<uot_problem> ps;
             std::vector<uot_outputs> os;
             for (int32_t i : ids) {
                 ps.push_back(probs[i]);
                 os.push_back(outs[i]);
             }
-            st = pack_batch(ps.data(), (int32_t)ps.size(), &t, os.data(), d, m_lds);
+            st = pack_batch(ps.data(), (int32_t)ps.size(), &t, os.data(), false, pk);      // no splitting
             if (st != UOT_OK) break;
+            std::vector<BatchDesc>& d = pk.d;
             for (auto& b : d) b.shape = s;
-            m_lds = batch_shape_max_m(s, kd);
+            const int64_t m_lds = batch_shape_max_m(s, kd);
             hipError_t e = hipMemcpy(ddev, d.data(), sizeof(BatchDesc) * d.size(), hipMemcpyHostToDevice);
             if (e != hipSuccess) { st = hip_fail(e, "tuning copy"); break; }
             float ms = 0.0f;
             for (int rep = 0; rep < 2 && st == UOT_OK; ++rep) {       // first run warms up
                 e = hipEventRecord(e0, stream);
-                if (e == hipSuccess) st = run_batch_packed(ddev, (int32_t)d.size(), kd, m_lds, &t, ws, ws_bytes, nullptr, stream);
+                if (e == hipSuccess)
+                    st = run_batch_packed(ddev, (int32_t)d.size(), 0, dbytes, 0, kd, m_lds, &t, ws, ws_bytes, nullptr,
+                                          stream);
                 if (st == UOT_OK && e == hipSuccess) e = hipEventRecord(e1, stream);
                 if (st == UOT_OK && e == hipSuccess) e = hipEventSynchronize(e1);
                 if (st == UOT_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
@@ -1346,24 +1464,26 @@ uot_status uot_batched_pack(const uot_problem* probs, int32_t count, const uot_o
                             const uot_outputs* outs, void* desc_host, size_t desc_bytes) {
     if (!desc_host) return fail(UOT_ERR_ARG, "desc_host must not be NULL");
     if (count < 0 || desc_bytes < uot_batched_desc_bytes(count)) return fail(UOT_ERR_ARG, "desc_bytes too small");
-    std::vector<BatchDesc> d;
-    int64_t m_lds = 0;
-    uot_status st = pack_batch(probs, count, opt, outs, d, m_lds);
+    BatchPack pk;
+    uot_status st = pack_batch(probs, count, opt, outs, true, pk);
     if (st != UOT_OK) return st;
     memset(desc_host, 0, desc_bytes);
-    if (count > 0) memcpy(desc_host, d.data(), sizeof(BatchDesc) * d.size());
+    if (!pk.d.empty()) memcpy(desc_host, pk.d.data(), sizeof(BatchDesc) * pk.d.size());
     uot_batched_meta meta;
     memset(&meta, 0, sizeof(meta));
     meta.count = count;
     meta.k_dtype = count > 0 ? probs[0].k_dtype : UOT_F32;
-    meta.m_lds = m_lds;
+    meta.m_lds = pk.m_lds;
+    meta.items = (int32_t)pk.d.size();
+    meta.nsplit = pk.nsplit;
+    meta.pool_bytes = (int64_t)pk.pool_used;
     memcpy((char*)desc_host + batch_desc_bytes(count), &meta, sizeof(meta));
     return UOT_OK;
 }
 
 size_t uot_sinkhorn_batched_workspace_size(int32_t count) {
     if (count < 0) return 0;
-    return kAlign + batch_desc_bytes(count);
+    return kAlign + batch_desc_bytes(count) + batch_pool_bytes(count);
 }
 
 uot_status uot_sinkhorn_batched_packed(const void* desc_dev, const uot_batched_meta* meta, const uot_options* opt,
@@ -1372,11 +1492,16 @@ uot_status uot_sinkhorn_batched_packed(const void* desc_dev, const uot_batched_m
     uot_status st = check_batch_options(opt);
     if (st != UOT_OK) return st;
     if (meta->count < 0 || (meta->count > 0 && !desc_dev)) return fail(UOT_ERR_ARG, "bad descriptor block");
+    if (meta->items < meta->count || meta->items > batch_max_items(meta->count) || meta->nsplit < 0 ||
+        meta->nsplit > batch_max_splits(meta->count) || meta->pool_bytes < 0 ||
+        (size_t)meta->pool_bytes > batch_pool_bytes(meta->count))
+        return fail(UOT_ERR_ARG, "bad descriptor block meta (items, splits or pool size)");
     if (!aligned(desc_dev, 16)) return fail(UOT_ERR_ALIGN, "descriptors must be 16-byte aligned");
     if (elem_size(meta->k_dtype) == 0) return fail(UOT_ERR_DTYPE, "bad K dtype in meta");
     if (trace && !aligned(trace, 8)) return fail(UOT_ERR_ALIGN, "trace must be 8-byte aligned");
-    return run_batch_packed((const BatchDesc*)desc_dev, meta->count, meta->k_dtype, meta->m_lds, opt, ws, ws_bytes,
-                            trace, (hipStream_t)stream);
+    return run_batch_packed((const BatchDesc*)desc_dev, meta->items, meta->nsplit, batch_desc_bytes(meta->count),
+                            (size_t)meta->pool_bytes, meta->k_dtype, meta->m_lds, opt, ws, ws_bytes, trace,
+                            (hipStream_t)stream);
 }
 
 uot_status uot_sinkhorn_batched(const uot_problem* probs, int32_t count, const uot_options* opt,
@@ -1390,15 +1515,16 @@ uot_status uot_sinkhorn_batched(const uot_problem* probs, int32_t count, const u
         uot_status st = autotune_batch(probs, count, opt, outs, ws, ws_bytes, s);
         if (st != UOT_OK) return st;
     }
-    std::vector<BatchDesc> d;
-    int64_t m_lds = 0;
-    uot_status st = pack_batch(probs, count, opt, outs, d, m_lds);
+    BatchPack pk;
+    uot_status st = pack_batch(probs, count, opt, outs, true, pk);
     if (st != UOT_OK) return st;
     BatchDesc* ddev = (BatchDesc*)((char*)ws + kAlign);
     // pageable source: the copy has consumed it when the call returns
-    UOT_HIP(hipMemcpyAsync(ddev, d.data(), sizeof(BatchDesc) * d.size(), hipMemcpyHostToDevice, s), "descriptor copy");
+    UOT_HIP(hipMemcpyAsync(ddev, pk.d.data(), sizeof(BatchDesc) * pk.d.size(), hipMemcpyHostToDevice, s),
+            "descriptor copy");
     UOT_HIP(hipStreamSynchronize(s), "descriptor copy");
-    return run_batch_packed(ddev, count, probs[0].k_dtype, m_lds, opt, ws, ws_bytes, nullptr, s);
+    return run_batch_packed(ddev, (int32_t)pk.d.size(), pk.nsplit, batch_desc_bytes(count), pk.pool_used,
+                            probs[0].k_dtype, pk.m_lds, opt, ws, ws_bytes, nullptr, s);
 }
 
 uot_status uot_batched_tune(const uot_problem* probs, int32_t count, const uot_options* opt, const uot_outputs* outs,

@@ -65,6 +65,30 @@ __device__ __forceinline__ double block_sum(double x, double* scratch) {
     return t;
 }
 
+// Barrier of the parts of a split problem (workgroups on any XCD): each
+// part adds 1 to the problem's counter once its column sums are written,
+// then waits until all P parts of this round have arrived (target P t in
+// round t).  Release and acquire at agent scope around the counter make the
+// sums visible across L2s; the wait is bounded (flag on timeout).
+__device__ __forceinline__ void part_barrier(uint32_t* hdr, uint32_t target) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        atomicAdd(&hdr[0], 1u);
+        uint32_t spins = 0;
+        while (__hip_atomic_load(&hdr[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > kBarrierSpinLimit) {
+                atomicOr(&hdr[1], UOT_FLAG_BARRIER_TIMEOUT);
+                break;
+            }
+        }
+        __threadfence();
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
 __device__ __forceinline__ double kl_term(double x, double y) {
     // x log(x/y) - x + y with 0 log 0 = 0
     if (x > 0.0) return x * log(x / y) - x + y;
@@ -243,9 +267,18 @@ struct BatchSolve {
         const int mpad = nc * lr * V;
         for (int j = tid; j < mpad; j += kBatchWG) vl[j] = (j < m) ? 1.0 : 0.0;
         const double tol = B.tol;
+        // Split problem: the parts' column sums (by iteration parity), this
+        // part's own copy of the column marginal, the objective row terms.
+        const bool split = P.parts > 1;
+        const int parts = split ? P.parts : 1;
+        const int64_t mx = (m + 1) / 2 * 2;
+        uint32_t* hdr = split ? (uint32_t*)(B.pool + kBatchHeaderBytes * (size_t)P.split) : nullptr;
+        double* xw = split ? (double*)(B.pool + P.xch) : nullptr;
+        double* cm = split ? xw + 2 * parts * mx + P.part * mx : P.c;     // previous column marginal
+        double* xo = split ? xw + 3 * parts * mx : nullptr;
         // previous column marginal of the stopping test: c_0 = 0
         if (tol > 0.0)
-            for (int j = tid; j < m; j += kBatchWG) P.c[j] = 0.0;
+            for (int j = tid; j < m; j += kBatchWG) cm[j] = 0.0;
         if (tid == 0) sh.flags = 0u;
         __syncthreads();
 
@@ -284,6 +317,28 @@ struct BatchSolve {
             } else {
                 __syncthreads();     // every row's use of v is complete
             }
+            // Split problem: publish this part's column sums, wait for the
+            // other parts; every part then adds all parts' sums in part order
+            // into wl.
+            if (split) {
+                double* xt = xw + (t & 1) * parts * mx;
+                if (grp == 0) {
+#pragma unroll
+                    for (int c = 0; c < NCM; ++c)
+#pragma unroll
+                        for (int e = 0; e < V; ++e) {
+                            const int j = col[c] + e;
+                            if (c < nc && j < m) xt[P.part * mx + j] = (rg > 1) ? wl[j] : acc[c * V + e];
+                        }
+                }
+                part_barrier(hdr, (uint32_t)(parts * t));
+                for (int j = tid; j < m; j += kBatchWG) {
+                    double ws = 0.0;
+                    for (int q = 0; q < parts; ++q) ws += xt[q * mx + j];
+                    wl[j] = ws;
+                }
+                __syncthreads();
+            }
             // Column half-step (group 0 owns each column once), marginal c = v w.
             double dsum = 0.0, csum = 0.0;
             if (grp == 0) {
@@ -293,19 +348,22 @@ struct BatchSolve {
                     for (int e = 0; e < V; ++e) {
                         const int j = col[c] + e;
                         if (c < nc && j < m) {
-                            const double w = ((rg > 1) ? wl[j] : acc[c * V + e]) * P.k_scale;
+                            const double w = ((rg > 1 || split) ? wl[j] : acc[c * V + e]) * P.k_scale;
                             const double bj = P.b[j];
                             const double vj = scale_factor(bj, w, P.fi, P.fi_is_one, 0.0);
                             if (bj > 0.0 && !(w > 0.0)) fl |= UOT_FLAG_ZERO_SUM;
                             if (!isfinite(vj)) fl |= UOT_FLAG_NONFINITE;
                             vl[j] = vj;
-                            P.v[j] = vj;
                             const double cj = vj * w;
                             if (tol > 0.0) {
-                                dsum += fabs(cj - P.c[j]);
+                                dsum += fabs(cj - cm[j]);
                                 csum += fabs(cj);
                             }
-                            P.c[j] = cj;
+                            cm[j] = cj;
+                            if (P.part == 0) {
+                                P.v[j] = vj;
+                                if (split) P.c[j] = cj;
+                            }
                         }
                     }
             }
@@ -335,25 +393,42 @@ struct BatchSolve {
                 for (int e = 0; e < V; ++e) {
                     const int j = col[c] + e;
                     if (c < nc && j < m) {
-                        const double cj = P.c[j];
+                        const double cj = cm[j];
                         if (cj > 0.0) clv += cj * log(vl[j]);
                         klc += kl_term(cj, P.b[j]);
                     }
                 }
         }
         if (fl) atomicOr(&sh.flags, fl);
-        const double s_rlu = block_sum(rlu, sh.scratch);
-        const double s_r = block_sum(rsum, sh.scratch);
+        double s_rlu = block_sum(rlu, sh.scratch);
+        double s_r = block_sum(rsum, sh.scratch);
         const double s_clv = block_sum(clv, sh.scratch);
-        double L = P.eps * (s_rlu + s_clv - s_r);
-        if (!P.fi_is_one) {
-            const double s_klr = block_sum(klr, sh.scratch);
-            const double s_klc = block_sum(klc, sh.scratch);
-            L += P.tau * (s_klr + s_klc);
+        double s_klr = block_sum(klr, sh.scratch);
+        const double s_klc = block_sum(klc, sh.scratch);
+        uint32_t part_flags = 0u;
+        if (split) {
+            // row terms of all parts, added in part order by part 0
+            if (tid == 0) {
+                xo[4 * P.part] = s_rlu;
+                xo[4 * P.part + 1] = s_r;
+                xo[4 * P.part + 2] = s_klr;
+                if (sh.flags) atomicOr(&hdr[1], sh.flags);
+            }
+            part_barrier(hdr, (uint32_t)(parts * (it + 1)));
+            if (P.part != 0) return;
+            s_rlu = s_r = s_klr = 0.0;
+            for (int q = 0; q < parts; ++q) {
+                s_rlu += xo[4 * q];
+                s_r += xo[4 * q + 1];
+                s_klr += xo[4 * q + 2];
+            }
+            part_flags = __hip_atomic_load(&hdr[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
+        double L = P.eps * (s_rlu + s_clv - s_r);
+        if (!P.fi_is_one) L += P.tau * (s_klr + s_klc);
         if (tid == 0) {
             *P.loss = L;
-            uint32_t flags = sh.flags;
+            uint32_t flags = sh.flags | part_flags;
             if (!isfinite(L)) flags |= UOT_FLAG_NONFINITE;
             if (tol > 0.0 && !stopped) flags |= UOT_FLAG_NOT_CONVERGED;
             P.info->iters = it;
@@ -389,8 +464,11 @@ __global__ __launch_bounds__(kBatchWG, 2) void batch_kernel(BatchLaunch B) {
     }
 }
 
-__global__ void batch_reset_kernel(uint32_t* next) {
+// Queue head and the split problems' counters and flags to 0.
+__global__ void batch_reset_kernel(uint32_t* next, uint32_t* headers, int32_t words) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *next = 0u;
+    for (int32_t w = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x); w < words; w += gridDim.x * blockDim.x)
+        headers[w] = 0u;
 }
 
 template <typename KT>
@@ -435,6 +513,7 @@ int64_t batch_shape_max_m(int shape, int k_dtype) {
 }
 
 int batch_shape_rows(int shape) { return kBatchShapes[shape].rg; }
+int batch_shape_chunks(int shape) { return kBatchShapes[shape].nc; }
 
 size_t batch_lds_bytes(int64_t m_lds) { return sizeof(double) * 2 * (size_t)m_lds; }
 
@@ -457,7 +536,8 @@ hipError_t launch_batch(int k_dtype, const BatchLaunch& B, int grid, size_t lds,
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, stream, B.next);
+    const int32_t hwords = (int32_t)(B.nsplit * kBatchHeaderBytes / sizeof(uint32_t));
+    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(256), 0, stream, B.next, (uint32_t*)B.pool, hwords);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     void* args[] = {(void*)&B};

@@ -110,6 +110,28 @@ def test_batched_tolerance_stop_matches_oracle_iterations():
     assert any(res.info(i)["iters"] < 400 for i in range(len(probs)))
 
 
+def test_batched_split_problems_match_oracle():
+    """Problems far above the average work per workgroup are split by rows
+    over several workgroups, whose parts exchange column sums every
+    iteration; the results are still the FP64 iteration on the stored
+    kernel (fixed count and tolerance stop), and a small problem is not
+    split."""
+    probs = _sizes_problems([1800, 900, 40, 2048], [1900, 1100, 30, 64], seed=9, T=80)
+    Kr = [_oracle_kernel(p, "f32") for p in probs]
+    Ks = [_stored_on_gpu(K, torch.float32) for K in Kr]
+    for tol in (0.0, 1e-5):
+        solver = uot.BatchedSolver(Ks, [to_dev(p.a) for p in probs], [to_dev(p.b) for p in probs],
+                                   eps=[p.eps for p in probs], tau=[p.tau for p in probs], max_iter=80, tol=tol,
+                                   trace=True)
+        solver.run()
+        torch.cuda.synchronize()
+        parts = solver.parts()
+        say(f"  tol={tol}: parts {parts}, {solver.items} queue entries")
+        assert parts[0] > 1 and parts[1] > 1 and parts[2] == 1 and solver.items == sum(parts)
+        _check_against_oracle(solver.result(), probs, Kr, 1e-9 if tol > 0 else 1e-10, tol=tol,
+                              label=f"split tol={tol}")
+
+
 def test_batched_zero_mass_entries():
     probs = _sizes_problems([40, 90], [70, 33], seed=6)
     probs[0].a[3] = 0.0

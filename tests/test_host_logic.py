@@ -64,16 +64,20 @@ def test_batched_pack_orders_longest_first_and_assigns_shapes():
     assert st == 0, _lib.lib().uot_last_error()
     w = _words(blob, len(ns))
     order = [int(x) for x in w[:, _DESC_INDEX_WORD]]
-    work = [ns[i] * ms[i] for i in order]
-    assert work == sorted(work, reverse=True)
-    assert order.index(2) < order.index(3)          # equal work keeps the caller's order
     # FP32 capacities: (rg 4, nc 1) 256, (4, 2) 512, (2, 2) 1024, (1, 2) 2048 columns
     expect = {16: 0, 257: 1, 512: 1, 1000: 4, 2048: 7}
     shapes = (w[:, _DESC_SHAPE_WORD] >> 32).astype(int)
     for q, i in enumerate(order):
         assert shapes[q] == expect[ms[i]], (ms[i], shapes[q])
+    # estimated time: row steps ceil(n / rg) weighted by (3 + chunks per lane)
+    rg_nc = {0: (4, 1), 1: (4, 2), 4: (2, 2), 7: (1, 2)}
+    cost = [-(-ns[i] // rg_nc[expect[ms[i]]][0]) * (3 + rg_nc[expect[ms[i]]][1]) for i in order]
+    assert cost == sorted(cost, reverse=True)
+    assert order.index(2) < order.index(3)          # equal cost keeps the caller's order
     meta = _lib.BatchedMeta.from_buffer_copy(blob[nbytes - ctypes.sizeof(_lib.BatchedMeta):])
     assert meta.count == len(ns) and meta.k_dtype == _lib.UOT_F32 and meta.m_lds == 2048
+    # without a device the resident workgroup count is unknown: nothing is split
+    assert meta.items == len(ns) and meta.nsplit == 0 and meta.pool_bytes == 0
 
 
 @pytest.mark.parametrize("dt,cap", [(_lib.UOT_F64, 2048), (_lib.UOT_F32, 2048), (_lib.UOT_BF16, 2048),
