@@ -14,8 +14,8 @@
 //   write p to the strip's partial row       (deterministic; no atomics)
 //
 // Workgroup shape: WG lanes each own NC 16-byte column chunks of every row
-// (chunk c of lane t starts at column (c*WG + t)*V), so one wave's load of a
-// chunk is 1 KiB of contiguous HBM.  Rows are software-pipelined D deep:
+// (chunk c of lane l in wave w is chunk (w*NC + c)*64 + l), so one wave's
+// load of a chunk is 1 KiB of contiguous HBM and its NC loads one block.  Rows are software-pipelined D deep:
 // while row i is reduced (one barrier per row) and accumulated, the loads of
 // rows i+1 .. i+D-1 are in flight in registers.  K is read through a buffer
 // resource spanning the workgroup's strip, so the prefetch past the strip's

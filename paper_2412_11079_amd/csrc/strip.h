@@ -58,9 +58,13 @@ struct Strip {
         const uint32_t strip_bytes = (uint32_t)((int64_t)nrows * L.ldk * (int64_t)sizeof(KT));
         const KT* strip = (const KT*)L.K + r0 * L.ldk;
         rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)strip, (short)0, (int)strip_bytes, kBufferWord3);
+        // Chunk c of lane l in wave w: chunk (w NC + c) 64 + l of the row, so
+        // each load instruction reads 1 KiB and a wave's NC loads one
+        // contiguous NC KiB block (measured 3% faster on 16384-column rows
+        // than interleaving the waves' chunks at a WG-chunk stride).
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            col[c] = ((int64_t)c * WG + threadIdx.x) * V;
+            col[c] = ((int64_t)((threadIdx.x >> 6) * NC + c) * 64 + (threadIdx.x & 63)) * V;
             voff[c] = col[c] < m ? (uint32_t)(col[c] * (int64_t)sizeof(KT)) : strip_bytes;
         }
         ragged = (m % V) != 0;
