@@ -329,7 +329,8 @@ def multi(uot, workloads, torch, dev, args):
                        f"eps=0.05, tau=1, {T} iterations", "flops_per_iter": flops}
     for name, dt in (("bf16", torch.bfloat16), ("f32", torch.float32)):
         K = uot.kernel_from_cost(C, base.eps, dt)
-        for variant, tune in (("", 0), ("_direct", 2)):
+        variants = (("", 0), ("_lds128", 1), ("_direct", 2), ("_tiled128", 4)) if name == "bf16" else (("", 0),)
+        for variant, tune in variants:
             uot.sinkhorn_multi(K, At, Bt, m=base.m, eps=base.eps, tau=base.tau, max_iter=2, tune=tune)
             torch.cuda.synchronize()
             e0, e1 = _events(torch)

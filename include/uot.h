@@ -313,8 +313,12 @@ uot_status uot_plan(const uot_problem* prob, const double* u, const double* v, c
  * the matrix cores and added in FP64 in a fixed order.
  * opt: max_iter >= 1 iterations exactly; tol, absorption, checkpoints, warm
  * start and the cooperative loop must be off (else UOT_ERR_UNSUPPORTED);
- * tune = 2 selects the product variant in which each wave loads its own
- * operand fragments (the default stages the workgroup's tiles through LDS).
+ * tune selects the product kernel of the BF16 form (the FP32 form always
+ * stages 128 x 128 tiles through LDS): 0 (default) or 3, 256 x 256 tiles
+ * over tiled copies of K and K^T when R is a multiple of 256 (else as 1);
+ * 1, 128 x 128 tiles staged through LDS; 2, each wave loads its own
+ * operand fragments; 4, 128 x 128 tiles over the tiled copies.  Other
+ * values: UOT_ERR_ARG.  The tiled copies take the workspace of a second K.
  * Workspace (uot_sinkhorn_multi_workspace_size): a transposed copy of K,
  * the split partial sums and the right-hand-side planes.
  * Errors: UOT_ERR_ARG, UOT_ERR_DTYPE, UOT_ERR_ALIGN, UOT_ERR_WORKSPACE,

@@ -1178,15 +1178,19 @@ struct MultiGemmShape {
     int32_t splits;
 };
 
-// Split of the reduction: enough workgroups to fill the device (about 512
-// for the BF16 form, whose partial sums cost relatively more, 1024 for FP32;
-// measured at 8192^2 x 256) with chunks of at least 256.
-MultiGemmShape multi_gemm_shape(int64_t rows, int64_t kdim_pad, int64_t r_pad, bool bf16) {
+// Split of the reduction: enough workgroups to fill the device (one per CU
+// for the 256 x 256 tiles, which hold 120 KiB of LDS; about 512 for the
+// 128 x 128 BF16 tiles, whose partial sums cost relatively more, 1024 for
+// FP32; measured at 8192^2 x 256) with chunks of at least 256.  Rows are
+// padded to the large tile whatever the variant.
+MultiGemmShape multi_gemm_shape(int64_t rows, int64_t kdim_pad, int64_t r_pad, bool bf16, int variant) {
     MultiGemmShape g;
-    g.rows_pad = round_up(rows, kMTileRows);
+    g.rows_pad = round_up(rows, kMBigRows);
     g.kdim_pad = kdim_pad;
-    const int64_t tiles = (r_pad / kMTileCols) * (g.rows_pad / kMTileRows);
-    const int64_t target = bf16 ? 512 : 1024;
+    const bool big = variant == 3;
+    const int64_t tiles = big ? (r_pad / kMBigCols) * (g.rows_pad / kMBigRows)
+                              : (r_pad / kMTileCols) * (g.rows_pad / kMTileRows);
+    const int64_t target = big ? 256 : bf16 ? 512 : 1024;
     int64_t splits = std::max<int64_t>(1, std::min<int64_t>(kdim_pad / 256, (target + tiles - 1) / tiles));
     g.kchunk = round_up((kdim_pad + splits - 1) / splits, 64);     // whole stages of every product variant
     g.splits = (int32_t)((kdim_pad + g.kchunk - 1) / g.kchunk);
@@ -1196,9 +1200,11 @@ MultiGemmShape multi_gemm_shape(int64_t rows, int64_t kdim_pad, int64_t r_pad, b
 struct MultiPlan {
     bool bf16;
     int es;
+    int variant;     // product kernel (MGemm::variant)
+    bool blocked;    // K and K^T repacked into the tiled layout
     int64_t n, m, R, r_pad, ldn, ldm;
     MultiGemmShape row, col;
-    size_t off_kt, off_part, off_uhi, off_ulo, off_vhi, off_vlo, off_rm, off_cm, off_flags, total;
+    size_t off_kt, off_kb, off_part, off_uhi, off_ulo, off_vhi, off_vlo, off_rm, off_cm, off_flags, total;
 };
 
 uot_status make_multi_plan(const uot_problem* p, int32_t R, const uot_options* o, MultiPlan& M) {
@@ -1224,16 +1230,33 @@ uot_status make_multi_plan(const uot_problem* p, int32_t R, const uot_options* o
     M.m = p->m;
     M.R = R;
     M.r_pad = round_up(R, kMTileCols);
+    if (M.r_pad > 65535) return fail(UOT_ERR_UNSUPPORTED, "R must be below 65408");
     M.ldn = round_up(p->n, 64);
     M.ldm = round_up(p->m, 64);
     if ((int64_t)M.n * p->ldk * M.es >= ((int64_t)1 << 31) || M.m * M.ldn * M.es >= ((int64_t)1 << 31) ||
         M.r_pad * std::max(M.ldn, M.ldm) * M.es >= ((int64_t)1 << 31))
         return fail(UOT_ERR_UNSUPPORTED, "K and the right-hand sides must each be below 2 GiB");
-    M.row = multi_gemm_shape(M.n, M.ldm, M.r_pad, M.bf16);      // S = K V: rows n, reduction over m
-    M.col = multi_gemm_shape(M.m, M.ldn, M.r_pad, M.bf16);      // W = K^T U: rows m, reduction over n
+    // BF16 product kernels (FP32 K always takes the 128 x 128 LDS tiles):
+    // tune = 0 (default) or 3: 256 x 256 tiles over a tiled copy of K when R
+    // is a multiple of 256 (else as 1; 190 against 208 us per iteration at
+    // 8192^2 x 256); 1: 128 x 128 tiles through LDS; 2: per-wave fragment
+    // loads; 4: 128 x 128 tiles over the tiled copy
+    if (o->tune < 0 || o->tune > 4) return fail(UOT_ERR_ARG, "tune must be 0..4 for the multi-right-hand-side form");
+    if (o->tune == 2) M.variant = 0;
+    else if (!M.bf16 || o->tune == 1) M.variant = 1;
+    else if (o->tune == 0 || o->tune == 3) M.variant = M.r_pad % kMBigCols == 0 ? 3 : 1;
+    else M.variant = 4;
+    M.row = multi_gemm_shape(M.n, M.ldm, M.r_pad, M.bf16, M.variant);      // S = K V: rows n, reduction over m
+    M.col = multi_gemm_shape(M.m, M.ldn, M.r_pad, M.bf16, M.variant);      // W = K^T U: rows m, reduction over n
+    // ring variants read K and K^T from tiled copies (launch_mpack)
+    M.blocked = M.variant >= 3;
+    if (M.blocked && (M.row.rows_pad * M.ldm * 2 >= ((int64_t)1 << 31) || M.col.rows_pad * M.ldn * 2 >= ((int64_t)1 << 31)))
+        return fail(UOT_ERR_UNSUPPORTED, "K must be below 2 GiB in the tiled layout");
     size_t off = 0;
     M.off_kt = off;
-    off = align_up(off + (size_t)M.m * M.ldn * M.es, kAlign);
+    off = align_up(off + (M.blocked ? (size_t)M.col.rows_pad * M.ldn * 2 : (size_t)M.m * M.ldn * M.es), kAlign);
+    M.off_kb = off;
+    if (M.blocked) off = align_up(off + (size_t)M.row.rows_pad * M.ldm * 2, kAlign);
     M.off_part = off;
     const size_t part = std::max((size_t)M.row.splits * M.r_pad * M.row.rows_pad,
                                  (size_t)M.col.splits * M.r_pad * M.col.rows_pad) * sizeof(float);
@@ -1282,12 +1305,19 @@ uot_status run_multi(const uot_problem* p, int32_t R, const double* A, const dou
     const double ks = p->k_scale > 0.0 ? p->k_scale : 1.0;
 
     UOT_HIP(launch_multi_info(info, 0, flags, 1, stream), "multi reset");
-    UOT_HIP(launch_transpose(p->k_dtype, p->K, p->ldk, M.n, M.m, KT, M.ldn, stream), "transpose");
+    void* KB = base + M.off_kb;
+    if (M.blocked) {
+        UOT_HIP(launch_mpack(0, p->K, p->ldk, M.n, M.m, KB, M.row.rows_pad, M.ldm, stream), "tiled K");
+        UOT_HIP(launch_mpack(1, p->K, p->ldk, M.n, M.m, KT, M.col.rows_pad, M.ldn, stream), "tiled K^T");
+    } else {
+        UOT_HIP(launch_transpose(p->k_dtype, p->K, p->ldk, M.n, M.m, KT, M.ldn, stream), "transpose");
+    }
     UOT_HIP(launch_ones_rhs(M.bf16, vhi, vlo, R, M.r_pad, M.m, M.ldm, stream), "initial v");
 
     MGemm rowg;
     memset(&rowg, 0, sizeof(rowg));
-    rowg.A = p->K;
+    rowg.A = M.blocked ? KB : p->K;
+    rowg.blocked = M.blocked;
     rowg.lda = p->ldk;
     rowg.rows = M.n;
     rowg.rows_pad = M.row.rows_pad;
@@ -1300,7 +1330,7 @@ uot_status run_multi(const uot_problem* p, int32_t R, const double* A, const dou
     rowg.kchunk = M.row.kchunk;
     rowg.part = part;
     rowg.ld_part = M.row.rows_pad;
-    rowg.variant = o->tune == 2 ? 0 : 1;      // 1: LDS-staged tiles (default); 0: per-wave fragment loads
+    rowg.variant = M.variant;
     MGemm colg = rowg;
     colg.A = KT;
     colg.lda = M.ldn;
@@ -1344,6 +1374,7 @@ uot_status run_multi(const uot_problem* p, int32_t R, const double* A, const dou
     ev.ld_next = M.ldm;
 
     for (int t = 1; t <= o->max_iter; ++t) {
+        eu.store_y = ev.store_y = (t == o->max_iter);      // U and V of the last iteration
         UOT_HIP(launch_mgemm(M.bf16, rowg, stream), "row product");
         UOT_HIP(launch_mepi(eu, stream), "row update");
         UOT_HIP(launch_mgemm(M.bf16, colg, stream), "column product");

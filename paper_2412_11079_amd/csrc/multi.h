@@ -23,7 +23,10 @@ struct MGemm {
     int64_t kchunk;      // multiple of the k step
     float* part;
     int64_t ld_part;     // = rows_pad
-    int32_t variant;     // 1: tiles staged through LDS; 0: fragments loaded by each wave
+    int32_t blocked;     // ring variants: A is in the tiled layout of launch_mpack (lda unused)
+    int32_t variant;     // 0: fragments loaded by each wave; 1: 128 x 128 tiles staged through LDS;
+                         // BF16 only, A in the tiled layout of launch_mpack, tiles through LDS
+                         // with a ring of loads in flight: 3: 256 x 256, 4: 128 x 128
 };
 
 // After a GEMM: S[r][i] = sum_s part[s][r][i] (FP64, fixed order), then
@@ -50,6 +53,7 @@ struct MEpi {
     int32_t fi_is_one;
     double k_scale;
     int32_t mode;
+    int32_t store_y;        // mode 0: also write y (the final iteration's scalings)
     uint32_t* flags;
 };
 
@@ -58,6 +62,18 @@ hipError_t launch_mepi(const MEpi& E, hipStream_t stream);
 // KT (m x ldkt) = K^T for a stored K (n x ldk), padding columns of KT zero.
 hipError_t launch_transpose(int k_dtype, const void* K, int64_t ldk, int64_t n, int64_t m, void* KT, int64_t ldkt,
                             hipStream_t stream);
+// BF16 A operand in the tiled layout read by the ring products: block
+// (rb, kb) holds rows 256 rb .. 256 rb + 255 and k values 32 kb .. 32 kb + 31
+// as 256 rows of 64 bytes (16 KiB, contiguous), blocks running along k
+// first, so one stage of a workgroup's tile is one contiguous read.
+// dst (rows_pad x kdim_pad, both multiples of 256 and 32) gets
+// A[row][k] = trans ? src[k][row] : src[row][k] where the source entry
+// exists (src: src_rows x src_cols, leading dimension ld), else 0.
+hipError_t launch_mpack(int trans, const void* src, int64_t ld, int64_t src_rows, int64_t src_cols, void* dst,
+                        int64_t rows_pad, int64_t kdim_pad, hipStream_t stream);
+constexpr int64_t kMPackRows = 256;
+constexpr int64_t kMPackK = 32;
+
 // Right-hand sides of the first iteration: v = 1 for r < R, j < m, else 0.
 hipError_t launch_ones_rhs(int bf16, void* hi, void* lo, int64_t R, int64_t r_pad, int64_t m, int64_t ld,
                            hipStream_t stream);
@@ -72,5 +88,7 @@ hipError_t launch_multi_info(uot_info* info, int64_t iters, uint32_t* flags, int
 constexpr int kMTileRows = 128;   // rows of A per workgroup
 constexpr int kMTileCols = 128;   // right-hand sides per workgroup
 constexpr int kMStep = 16;        // k per step (BF16); the FP32 form steps by 8
+constexpr int kMBigRows = 256;    // BF16 256 x 256 variant: rows of A per workgroup
+constexpr int kMBigCols = 256;    // and right-hand sides per workgroup
 
 }  // namespace uot

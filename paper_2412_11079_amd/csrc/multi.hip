@@ -299,57 +299,319 @@ __global__ __launch_bounds__(256) void mgemm_lds_kernel(MGemm G) {
             }
 }
 
-__global__ __launch_bounds__(256) void mepi_kernel(MEpi E) {
-    const int64_t q4 = E.ld_next / 4;
-    const int64_t total = E.r_pad * q4;
-    uint32_t fl = 0;
-    for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * 256) {
-        const int64_t r = idx / q4;
-        const int64_t i0 = (idx % q4) * 4;
-        double S[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int s = 0; s < E.splits; ++s) {
-            const f32x4 p = *(const f32x4*)(E.part + ((int64_t)s * E.r_pad + r) * E.ld_part + i0);
+__device__ __forceinline__ int lds_swz(int r) { return ((r >> 1) ^ (r >> 2)) & 3; }
+
+// BF16 form, tile staged through LDS with a deeper fetch pipeline: TR x TC
+// tile per workgroup, each wave owning MT x NT tiles of 32 x 32, so one A
+// fragment read from LDS feeds 2 NT matrix-core products and one
+// right-hand-side fragment MT of them.  K streams from HBM with rows 16 KiB
+// apart, so each workgroup keeps PD stages of loads in flight in registers
+// (a ring; loads of a stage are issued PD - 1 stages before it is staged, and
+// the ring holds A and both right-hand-side planes so that the in-order wait
+// for one stage never waits for a later one), with two LDS buffers.
+// 256 x 256 (one workgroup per CU, 96 KiB of LDS): per stage of 32 k values
+// each of the four waves issues 64 products (2048 cycles of its SIMD's matrix
+// core) against 96 KiB of LDS fragment reads and 48 KiB of staging writes,
+// and K is fetched once per product (the tile spans 256 right-hand sides).
+template <int WR, int WC, int MT, int NT, int PD>
+__global__ __launch_bounds__(64 * WR * WC) void mgemm_ring_kernel(MGemm G) {
+    constexpr int NTHR = 64 * WR * WC;
+    constexpr int TR = WR * MT * 32;            // rows of A per workgroup
+    constexpr int TC = WC * NT * 32;            // right-hand sides per workgroup
+    constexpr int BK = 32;                      // k per stage (64 bytes per row)
+    constexpr int A_BYTES = TR * 64;            // LDS: 64-byte rows, 16-byte chunks swizzled
+    constexpr int X_BYTES = TC * 64;
+    constexpr int STAGE = A_BYTES + 2 * X_BYTES;
+    constexpr int CA = TR * 4 / NTHR;           // 16-byte A chunks per thread per stage
+    constexpr int CX = TC * 4 / NTHR;           // chunks per right-hand-side plane per thread
+    static_assert(TR * 4 % NTHR == 0 && TC * 4 % NTHR == 0, "staging map must cover the tile");
+    static_assert(PD >= 1, "at least one stage in flight");
+    extern __shared__ __align__(16) unsigned char lds[];
+
+    const int tid = threadIdx.x;
+    const int l = tid & 63;
+    const int w = tid >> 6;
+    const int lr = l & 31;
+    const int lh = l >> 5;
+    const int wm = w % WR, wn = w / WR;
+    const TileIdx ti = xcd_tile();
+    const int64_t tile_r = (int64_t)ti.y * TR;
+    const int64_t tile_c = (int64_t)ti.x * TC;
+    const int64_t k_begin = (int64_t)ti.z * G.kchunk;
+    int64_t k_end = k_begin + G.kchunk;
+    if (k_end > G.kdim_pad) k_end = G.kdim_pad;
+
+    // A plain (row-major, lda) or tiled (launch_mpack: a stage of the tile is
+    // TR x 64 contiguous bytes, the next stage 16 KiB further)
+    const bool blk = G.blocked != 0;
+    const uint32_t a_bytes = blk ? (uint32_t)(G.rows_pad * G.kdim_pad * 2) : (uint32_t)(G.rows * G.lda * 2);
+    const uint32_t a_kstep = blk ? (uint32_t)(kMPackRows * 64) : 64u;      // bytes per 32 values of k
+    const uint32_t x_bytes = (uint32_t)(G.r_pad * G.ldx * 2);
+    const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc((void*)G.A, (short)0, (int)a_bytes, kBufferWord3);
+    const __amdgpu_buffer_rsrc_t rh = __builtin_amdgcn_make_buffer_rsrc((void*)G.x_hi, (short)0, (int)x_bytes, kBufferWord3);
+    const __amdgpu_buffer_rsrc_t rl = __builtin_amdgcn_make_buffer_rsrc((void*)G.x_lo, (short)0, (int)x_bytes, kBufferWord3);
+    const int64_t a_tile = (tile_r / kMPackRows) * (G.kdim_pad / kMPackK) * (kMPackRows * 64) + (tile_r % kMPackRows) * 64;
+
+    // Staging map: chunk c of a stage = row c/4, bytes 16 (c%4) of the row's 64.
+    // In LDS, chunk kc of row r sits at slot kc ^ swz(r) of the row, with
+    // swz(r) = ((r >> 1) ^ (r >> 2)) & 3: the 16-byte fragment reads (32
+    // consecutive rows, one chunk) and the staging writes (4 chunks of
+    // consecutive rows) then touch distinct banks in every group of 8 or 16
+    // lanes, with no padding.
+    uint32_t ga[CA], gx[CX];
+    int la[CA], lx[CX];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) S[e] += (double)p[e];
+    for (int q = 0; q < CA; ++q) {
+        const int c = tid + NTHR * q;
+        const int row = c >> 2, kc = c & 3;
+        const int64_t grow = tile_r + row;
+        if (blk)
+            ga[q] = (uint32_t)(a_tile + c * 16);                                        // rows beyond are 0
+        else
+            ga[q] = grow < G.rows ? (uint32_t)(grow * G.lda * 2 + kc * 16) : a_bytes;     // rows beyond: 0
+        la[q] = row * 64 + ((kc ^ lds_swz(row)) << 4);
+    }
+#pragma unroll
+    for (int q = 0; q < CX; ++q) {
+        const int c = tid + NTHR * q;
+        const int row = c >> 2, kc = c & 3;
+        gx[q] = (uint32_t)((tile_c + row) * G.ldx * 2 + kc * 16);
+        lx[q] = row * 64 + ((kc ^ lds_swz(row)) << 4);
+    }
+    u32x4 pa[PD][CA], ph[PD][CX], pl[PD][CX];
+    auto fetch = [&](int64_t k, int slot) {
+        const uint32_t ko = (uint32_t)(k * 2);
+        const uint32_t ka = (uint32_t)(k / 32) * a_kstep;
+#pragma unroll
+        for (int q = 0; q < CA; ++q)
+            pa[slot][q] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(ra, (int)(ga[q] + ka), 0, 0));
+#pragma unroll
+        for (int q = 0; q < CX; ++q) {
+            ph[slot][q] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rh, (int)(gx[q] + ko), 0, 0));
+            pl[slot][q] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rl, (int)(gx[q] + ko), 0, 0));
         }
-        double y[4];
+    };
+    auto stash = [&](int buf, int slot) {
+        unsigned char* base = lds + buf * STAGE;
+#pragma unroll
+        for (int q = 0; q < CA; ++q) *(u32x4*)(base + la[q]) = pa[slot][q];
+#pragma unroll
+        for (int q = 0; q < CX; ++q) {
+            *(u32x4*)(base + A_BYTES + lx[q]) = ph[slot][q];
+            *(u32x4*)(base + A_BYTES + X_BYTES + lx[q]) = pl[slot][q];
+        }
+    };
+
+    f32x16 acc[MT][NT];
+#pragma unroll
+    for (int t = 0; t < MT; ++t)
+#pragma unroll
+        for (int u = 0; u < NT; ++u)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc[t][u][q] = 0.0f;
+
+    // rows read by this lane are lr mod 32, so their swizzle is lds_swz(lr)
+    const int kslot[2] = {(lh ^ lds_swz(lr)) << 4, ((2 + lh) ^ lds_swz(lr)) << 4};
+    auto compute = [&](int buf) {
+        const unsigned char* base = lds + buf * STAGE;
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            const int kb = kslot[ks];                  // swizzled slot of the lane's 8 k values in the row
+            u32x4 af[MT], hf[NT], lf[NT];
+#pragma unroll
+            for (int t = 0; t < MT; ++t) af[t] = *(const u32x4*)(base + (wm * MT * 32 + t * 32 + lr) * 64 + kb);
+#pragma unroll
+            for (int u = 0; u < NT; ++u) {
+                const int off = A_BYTES + (wn * NT * 32 + u * 32 + lr) * 64 + kb;
+                hf[u] = *(const u32x4*)(base + off);
+                lf[u] = *(const u32x4*)(base + off + X_BYTES);
+            }
+#pragma unroll
+            for (int t = 0; t < MT; ++t)
+#pragma unroll
+                for (int u = 0; u < NT; ++u) {
+                    const bf16x8_t av = __builtin_bit_cast(bf16x8_t, af[t]);
+                    acc[t][u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, __builtin_bit_cast(bf16x8_t, hf[u]),
+                                                                        acc[t][u], 0, 0, 0);
+                    acc[t][u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, __builtin_bit_cast(bf16x8_t, lf[u]),
+                                                                        acc[t][u], 0, 0, 0);
+                }
+        }
+    };
+
+    // Stage s lives in ring slot s % PD from its fetch until it is staged
+    // into LDS buffer s % 2 at the end of stage s - 1.  Fetches past the
+    // last stage re-read the last stage (cache hits, never used), so every
+    // fetch is unconditional and the wait before staging a stage leaves the
+    // PD - 1 later stages in flight; the staging after the last stage writes
+    // the idle buffer.
+    const int nst = (int)((k_end - k_begin + BK - 1) / BK);
+    const int64_t k_last = k_begin + (int64_t)(nst - 1) * BK;
+    auto fetch_stage = [&](int s, int slot) {
+        const int64_t k = k_begin + (int64_t)s * BK;
+        fetch(k < k_last ? k : k_last, slot);
+    };
+    if (nst > 0) {
+#pragma unroll
+        for (int p = 0; p < PD; ++p) fetch_stage(p, p);
+        stash(0, 0);
+        __syncthreads();
+        int st0 = 0;
+        for (; st0 + PD <= nst; st0 += PD) {
+#pragma unroll
+            for (int j = 0; j < PD; ++j) {
+                const int st = st0 + j;         // stage computed now; its slot j is free again
+                fetch_stage(st + PD, j);
+                compute(st & 1);
+                stash((st + 1) & 1, (j + 1) % PD);
+                __syncthreads();
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < PD - 1; ++j) {
+            const int st = st0 + j;
+            if (st < nst) {
+                compute(st & 1);
+                stash((st + 1) & 1, (j + 1) % PD);
+                __syncthreads();
+            }
+        }
+    }
+
+    // Partial sums leave through LDS (free after the last barrier): each
+    // 32 x 32 tile goes to the wave's own region as [r][i] (rows padded to
+    // 36 floats), and is read back so that 8 lanes store one 128-byte run of
+    // a partial row: whole lines instead of 32-byte pieces 32 KiB apart.
+    float* P = G.part + (int64_t)ti.z * G.r_pad * G.ld_part;
+    const int64_t row0 = tile_r + wm * MT * 32, col0 = tile_c + wn * NT * 32;
+    float* wl = (float*)lds + w * (32 * 36);
+    const int rr = l >> 3, rc = 4 * (l & 7);
+#pragma unroll
+    for (int t = 0; t < MT; ++t)
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                f32x4 v = {acc[t][u][4 * g], acc[t][u][4 * g + 1], acc[t][u][4 * g + 2], acc[t][u][4 * g + 3]};
+                *(f32x4*)(wl + lr * 36 + 8 * g + 4 * lh) = v;
+            }
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int r = 8 * j + rr;
+                const f32x4 v = *(const f32x4*)(wl + r * 36 + rc);
+                __builtin_nontemporal_store(v, (f32x4*)(P + (col0 + u * 32 + r) * G.ld_part + row0 + t * 32 + rc));
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+}
+
+template <bool TRANS>
+__global__ __launch_bounds__(256) void mpack_kernel(const uint16_t* __restrict__ src, int64_t ld, int64_t src_rows,
+                                                    int64_t src_cols, uint16_t* __restrict__ dst, int64_t rows_pad,
+                                                    int64_t kdim_pad) {
+    const int64_t kb_count = kdim_pad / kMPackK;
+    const int64_t total = rows_pad * kdim_pad / 8;              // 16-byte chunks of dst
+    for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < total; c += (int64_t)gridDim.x * 256) {
+        const int64_t blk = c / (kMPackRows * 4);
+        const int64_t w = c % (kMPackRows * 4);
+        const int64_t row = (blk / kb_count) * kMPackRows + w / 4;
+        const int64_t k0 = (blk % kb_count) * kMPackK + (w % 4) * 8;
+        uint16_t v[8];
+        if (!TRANS && row < src_rows && k0 + 8 <= src_cols) {
+            const u32x4 x = *(const u32x4*)(src + row * ld + k0);
+            *(u32x4*)(dst + c * 8) = x;
+            continue;
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int64_t k = k0 + e;
+            const bool ok = TRANS ? (k < src_rows && row < src_cols) : (row < src_rows && k < src_cols);
+            v[e] = ok ? (TRANS ? src[k * ld + row] : src[row * ld + k]) : (uint16_t)0;
+        }
+        u32x4 y = {(uint32_t)v[0] | ((uint32_t)v[1] << 16), (uint32_t)v[2] | ((uint32_t)v[3] << 16),
+                   (uint32_t)v[4] | ((uint32_t)v[5] << 16), (uint32_t)v[6] | ((uint32_t)v[7] << 16)};
+        *(u32x4*)(dst + c * 8) = y;
+    }
+}
+
+// q^fi for the BF16 form, whose right-hand sides keep ~16 bits: log2 of the
+// mantissa and exp2 of the fractional exponent on the FP32 units (relative
+// error ~3e-7), exponent handling in FP64 so the full FP64 range is kept.
+// q must be positive and finite.
+__device__ __forceinline__ double pow_bf16_form(double q, double fi) {
+    int e;
+    const double mt = frexp(q, &e);                                   // [0.5, 1)
+    const double t = fi * ((double)e + (double)__builtin_amdgcn_logf((float)mt));
+    const double ti = floor(t);
+    return ldexp((double)__builtin_amdgcn_exp2f((float)(t - ti)), (int)ti);
+}
+
+// Workgroup: 1024 consecutive rows of right-hand side r = blockIdx.y; lane
+// t of the workgroup takes rows t, t + 256, t + 512, t + 768 of the block, so
+// every load and store of the workgroup is one contiguous run per wave.
+__global__ __launch_bounds__(256) void mepi_kernel(MEpi E) {
+    const int64_t r = blockIdx.y;
+    const int64_t ib = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+    uint32_t fl = 0;
+    const float* pp = E.part + r * E.ld_part;
+    const int64_t sstride = E.r_pad * E.ld_part;
+    double S[4] = {0.0, 0.0, 0.0, 0.0};
+    int s = 0;
+    for (; s + 4 <= E.splits; s += 4) {            // chunks added in ascending order
+        float p[4][4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t i = ib + 256 * e;
+                p[q][e] = i < E.ld_next ? pp[(s + q) * sstride + i] : 0.0f;
+            }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) S[e] += (double)p[q][e];
+    }
+    for (; s < E.splits; ++s) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            const int64_t i = i0 + e;
-            const bool valid = r < E.R && i < E.rows;
-            const double s = S[e] * E.k_scale;
-            y[e] = 0.0;
-            if (valid) {
-                const int64_t o = r * E.rows + i;
-                if (E.mode == 0) {
-                    const double tgt = E.target[o];
-                    y[e] = scale_factor(tgt, s, E.fi, E.fi_is_one, 0.0);
-                    if (tgt > 0.0 && !(s > 0.0)) fl |= UOT_FLAG_ZERO_SUM;
-                    if (!isfinite(y[e])) fl |= UOT_FLAG_NONFINITE;
-                    E.y[o] = y[e];
-                    if (E.marg) E.marg[o] = y[e] * s;
-                } else {
-                    E.marg[o] = E.y[o] * s;
-                }
+            const int64_t i = ib + 256 * e;
+            S[e] += i < E.ld_next ? (double)pp[s * sstride + i] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int64_t i = ib + 256 * e;
+        if (i >= E.ld_next) break;
+        const bool valid = r < E.R && i < E.rows;
+        const double sm = S[e] * E.k_scale;
+        double y = 0.0;
+        if (valid) {
+            const int64_t o = r * E.rows + i;
+            if (E.mode == 0) {
+                const double tgt = E.target[o];
+                const double q = tgt / sm;
+                if (E.bf16 && !E.fi_is_one && q > 0.0 && isfinite(q))
+                    y = pow_bf16_form(q, E.fi);
+                else
+                    y = scale_factor(tgt, sm, E.fi, E.fi_is_one, 0.0);
+                if (tgt > 0.0 && !(sm > 0.0)) fl |= UOT_FLAG_ZERO_SUM;
+                if (!isfinite(y)) fl |= UOT_FLAG_NONFINITE;
+                if (E.store_y) E.y[o] = y;
+                if (E.marg) E.marg[o] = y * sm;
+            } else {
+                E.marg[o] = E.y[o] * sm;
             }
         }
         if (E.mode == 0) {
-            const int64_t o = r * E.ld_next + i0;
+            const int64_t o = r * E.ld_next + i;      // next right-hand sides, zero padding
             if (E.bf16) {
-                uint16_t hi[4], lo[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    hi[e] = f64_to_bf16(y[e]);
-                    const double h = (double)__uint_as_float((uint32_t)hi[e] << 16);
-                    lo[e] = f64_to_bf16(y[e] - h);
-                }
-                uint2 hv = {(uint32_t)hi[0] | ((uint32_t)hi[1] << 16), (uint32_t)hi[2] | ((uint32_t)hi[3] << 16)};
-                uint2 lv = {(uint32_t)lo[0] | ((uint32_t)lo[1] << 16), (uint32_t)lo[2] | ((uint32_t)lo[3] << 16)};
-                *(uint2*)((uint16_t*)E.next_hi + o) = hv;
-                *(uint2*)((uint16_t*)E.next_lo + o) = lv;
+                const uint16_t hi = f64_to_bf16(y);
+                const double h = (double)__uint_as_float((uint32_t)hi << 16);
+                ((uint16_t*)E.next_hi)[o] = hi;
+                ((uint16_t*)E.next_lo)[o] = f64_to_bf16(y - h);
             } else {
-                f32x4 v = {(float)y[0], (float)y[1], (float)y[2], (float)y[3]};
-                *(f32x4*)((float*)E.next_hi + o) = v;
+                ((float*)E.next_hi)[o] = (float)y;
             }
         }
     }
@@ -456,7 +718,32 @@ hipError_t launch_multi_info(uot_info* info, int64_t iters, uint32_t* flags, int
     return hipGetLastError();
 }
 
+template <int WR, int WC, int MT, int NT, int PD>
+static hipError_t launch_ring(const MGemm& G, hipStream_t stream) {
+    constexpr int TR = WR * MT * 32, TC = WC * NT * 32;
+    constexpr int lds = 2 * (TR + 2 * TC) * 64;
+    if (G.r_pad % TC != 0 || G.rows_pad % TR != 0) return hipErrorInvalidValue;
+    static bool raised = false;
+    auto fn = mgemm_ring_kernel<WR, WC, MT, NT, PD>;
+    if (!raised && lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess) return e;
+        raised = true;
+    }
+    dim3 grid((unsigned)(G.r_pad / TC), (unsigned)(G.rows_pad / TR), (unsigned)G.splits);
+    hipLaunchKernelGGL(fn, grid, dim3(64 * WR * WC), lds, stream, G);
+    return hipGetLastError();
+}
+
 hipError_t launch_mgemm(int bf16, const MGemm& G, hipStream_t stream) {
+    if (G.variant >= 3) {
+        if (!bf16) return hipErrorInvalidValue;
+        switch (G.variant) {
+            case 3: return launch_ring<2, 4, 4, 2, 3>(G, stream);
+            case 4: return launch_ring<2, 2, 2, 2, 4>(G, stream);
+            default: return hipErrorInvalidValue;
+        }
+    }
     dim3 grid((unsigned)(G.r_pad / kMTileCols), (unsigned)(G.rows_pad / kMTileRows), (unsigned)G.splits);
     if (G.variant == 1) {
         if (bf16)
@@ -473,10 +760,9 @@ hipError_t launch_mgemm(int bf16, const MGemm& G, hipStream_t stream) {
 }
 
 hipError_t launch_mepi(const MEpi& E, hipStream_t stream) {
-    const int64_t total = E.r_pad * (E.ld_next / 4);
-    int64_t blocks = (total + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(mepi_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, E);
+    if (E.r_pad > 65535) return hipErrorInvalidValue;
+    dim3 grid((unsigned)((E.ld_next + 1023) / 1024), (unsigned)E.r_pad);
+    hipLaunchKernelGGL(mepi_kernel, grid, dim3(256), 0, stream, E);
     return hipGetLastError();
 }
 
@@ -490,6 +776,20 @@ hipError_t launch_transpose(int k_dtype, const void* K, int64_t ldk, int64_t n, 
         case UOT_FP8_E4M3: hipLaunchKernelGGL(transpose_kernel<uint8_t>, grid, dim3(256), 0, stream, (const uint8_t*)K, ldk, n, m, (uint8_t*)KT, ldkt); break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_mpack(int trans, const void* src, int64_t ld, int64_t src_rows, int64_t src_cols, void* dst,
+                        int64_t rows_pad, int64_t kdim_pad, hipStream_t stream) {
+    if (rows_pad % kMPackRows != 0 || kdim_pad % kMPackK != 0) return hipErrorInvalidValue;
+    int64_t blocks = (rows_pad * kdim_pad / 8 + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (trans)
+        hipLaunchKernelGGL(mpack_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, stream, (const uint16_t*)src, ld,
+                           src_rows, src_cols, (uint16_t*)dst, rows_pad, kdim_pad);
+    else
+        hipLaunchKernelGGL(mpack_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, stream, (const uint16_t*)src, ld,
+                           src_rows, src_cols, (uint16_t*)dst, rows_pad, kdim_pad);
     return hipGetLastError();
 }
 

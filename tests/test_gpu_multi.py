@@ -46,7 +46,7 @@ def _compare(res, Kr, A, B, eps, tau, T, idx, bar, label):
     return worst
 
 
-@pytest.mark.parametrize("tune", [0, 2], ids=["lds", "direct"])
+@pytest.mark.parametrize("tune", [0, 2, 4], ids=["default", "direct", "tiled128"])
 @pytest.mark.parametrize("dtype,storage,bar", [(torch.float32, "f32", 2e-6), (torch.bfloat16, "bf16", 2e-4)])
 def test_multi_matches_oracle_on_same_kernel(dtype, storage, bar, tune):
     base, A, B = workloads.multi_rhs(n=300, m=257, R=40, max_iter=50)
@@ -58,6 +58,25 @@ def test_multi_matches_oracle_on_same_kernel(dtype, storage, bar, tune):
     torch.cuda.synchronize()
     assert res.info()["flags"] == 0 and res.info()["iters"] == 50
     _compare(res, Kr, A, B, base.eps, base.tau, 50, range(40), bar, f"{dtype} tune={tune}")
+
+
+@pytest.mark.parametrize("tune", [0, 1, 4], ids=["tiled256", "lds128", "tiled128"])
+def test_multi_large_tiles_match_oracle(tune):
+    """BF16 form with 512 right-hand sides (two 256-wide column tiles of the
+    256 x 256 product), 600 rows (two full 256-row tiles and a ragged
+    third) and 333 columns (a ragged reduction for both products); sampled
+    pairs against the oracle on the same stored kernel at the BF16 form
+    bar."""
+    base, A, B = workloads.multi_rhs(n=600, m=333, R=512, max_iter=30)
+    A, B = A.T.copy(), B.T.copy()
+    C = oracle.cost_points(base.x, base.y, base.cost_kind)
+    Kr, Kd = _stored(C, base.eps, "bf16", torch.bfloat16)
+    res = uot.sinkhorn_multi(Kd, to_dev(A), to_dev(B), m=base.m, eps=base.eps, tau=base.tau, max_iter=30,
+                             tune=tune)
+    torch.cuda.synchronize()
+    assert res.info()["flags"] == 0 and res.info()["iters"] == 30
+    idx = list(range(0, 512, 9)) + [255, 256, 511]
+    _compare(res, Kr, A, B, base.eps, base.tau, 30, idx, 2e-4, f"bf16 R=512 tune={tune}")
 
 
 def test_multi_bf16_storage_error_against_exact_kernel():
