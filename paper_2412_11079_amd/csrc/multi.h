@@ -7,8 +7,17 @@ namespace uot {
 
 // Out^T[r][i] = sum_k A[i][k] X^T[r][k]: A (rows x kdim, row-major, lda)
 // times R right-hand sides held k-contiguous (X^T, R_pad x ldx), split over
-// kdim into `splits` chunks; each chunk's FP32 sum goes to
-// part[s][r][i] (splits x R_pad x ld_part).
+// kdim into `splits` chunks; chunk s's FP32 sum for (r, i) goes to
+// part[mpart_index(r, i, s, ld_part, splits)] (splits x R_pad x ld_part
+// floats in all).
+// Partial-sum layout: for each right-hand side r and block of 32 rows i,
+// the splits' 32 sums follow one another (128 bytes each), so a GEMM
+// workgroup stores whole 128-byte runs and the epilogue reads all chunks of
+// 32 rows as one contiguous run.  ld_part is a multiple of 32.
+__host__ __device__ inline int64_t mpart_index(int64_t r, int64_t i, int s, int64_t ld_part, int splits) {
+    return ((r * (ld_part >> 5) + (i >> 5)) * splits + s) * 32 + (i & 31);
+}
+
 struct MGemm {
     const void* A;
     int64_t lda;

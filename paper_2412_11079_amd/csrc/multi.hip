@@ -122,7 +122,7 @@ __global__ __launch_bounds__(256) void mgemm_kernel(MGemm G) {
     }
 
     // acc[t][u][q]: row 8 (q/4) + 4 lh + q%4 of tile t, right-hand side lr of tile u.
-    float* P = G.part + (int64_t)blockIdx.z * G.r_pad * G.ld_part;
+    const int split = (int)blockIdx.z;
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(256) void mgemm_kernel(MGemm G) {
                 const int64_t i0 = row0 + t * 32 + 8 * g + 4 * lh;
                 const int64_t r = col0 + u * 32 + lr;
                 f32x4 v = {acc[t][u][4 * g], acc[t][u][4 * g + 1], acc[t][u][4 * g + 2], acc[t][u][4 * g + 3]};
-                __builtin_nontemporal_store(v, (f32x4*)(P + r * G.ld_part + i0));
+                __builtin_nontemporal_store(v, (f32x4*)(G.part + mpart_index(r, i0, split, G.ld_part, G.splits)));
             }
 }
 
@@ -150,6 +150,37 @@ __device__ __forceinline__ TileIdx xcd_tile() {
     const uint32_t id = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
     const uint32_t L = (total % 8 == 0) ? (id % 8) * (total / 8) + id / 8 : id;
     return TileIdx{L % gx, (L / gx) % gy, L / (gx * gy)};
+}
+
+// Partial sums of a wave's MT x NT tiles of 32 x 32 (acc[t][u][q]: row
+// 8 (q/4) + 4 lh + q%4 of tile t, right-hand side lr of tile u) leave through
+// the wave's own LDS region (32 x 36 floats, free after the main loop's last
+// barrier): written as [r][i], read back so that 8 lanes store one 128-byte
+// run of the partial layout: whole lines instead of 16-byte pieces.
+template <int MT, int NT>
+__device__ __forceinline__ void store_partials_via_lds(const f32x16 (&acc)[MT][NT], float* wl, const MGemm& G,
+                                                       int split, int64_t row0, int64_t col0, int l) {
+    const int lr = l & 31, lh = l >> 5;
+    const int rr = l >> 3, rc = 4 * (l & 7);
+#pragma unroll
+    for (int t = 0; t < MT; ++t)
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                f32x4 v = {acc[t][u][4 * g], acc[t][u][4 * g + 1], acc[t][u][4 * g + 2], acc[t][u][4 * g + 3]};
+                *(f32x4*)(wl + lr * 36 + 8 * g + 4 * lh) = v;
+            }
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int r = 8 * j + rr;
+                const f32x4 v = *(const f32x4*)(wl + r * 36 + rc);
+                __builtin_nontemporal_store(
+                    v, (f32x4*)(G.part + mpart_index(col0 + u * 32 + r, row0 + t * 32 + rc, split, G.ld_part, G.splits)));
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
 }
 
 // Same product with the workgroup's operand tiles staged through LDS
@@ -284,19 +315,8 @@ __global__ __launch_bounds__(256) void mgemm_lds_kernel(MGemm G) {
         __syncthreads();
     }
 
-    float* P = G.part + (int64_t)ti.z * G.r_pad * G.ld_part;
-    const int64_t row0 = tile_r + wm * 64, col0 = tile_c + wn * 64;
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-        for (int u = 0; u < 2; ++u)
-#pragma unroll
-            for (int g = 0; g < 4; ++g) {
-                const int64_t i0 = row0 + t * 32 + 8 * g + 4 * lh;
-                const int64_t r = col0 + u * 32 + lr;
-                f32x4 v = {acc[t][u][4 * g], acc[t][u][4 * g + 1], acc[t][u][4 * g + 2], acc[t][u][4 * g + 3]};
-                __builtin_nontemporal_store(v, (f32x4*)(P + r * G.ld_part + i0));
-            }
+    static_assert(2 * STAGE >= 4 * 32 * 36 * 4, "epilogue regions must fit in the staging LDS");
+    store_partials_via_lds<2, 2>(acc, (float*)lds + w * (32 * 36), G, (int)ti.z, tile_r + wm * 64, tile_c + wn * 64, l);
 }
 
 __device__ __forceinline__ int lds_swz(int r) { return ((r >> 1) ^ (r >> 2)) & 3; }
@@ -478,32 +498,9 @@ __global__ __launch_bounds__(64 * WR * WC) void mgemm_ring_kernel(MGemm G) {
         }
     }
 
-    // Partial sums leave through LDS (free after the last barrier): each
-    // 32 x 32 tile goes to the wave's own region as [r][i] (rows padded to
-    // 36 floats), and is read back so that 8 lanes store one 128-byte run of
-    // a partial row: whole lines instead of 32-byte pieces 32 KiB apart.
-    float* P = G.part + (int64_t)ti.z * G.r_pad * G.ld_part;
-    const int64_t row0 = tile_r + wm * MT * 32, col0 = tile_c + wn * NT * 32;
-    float* wl = (float*)lds + w * (32 * 36);
-    const int rr = l >> 3, rc = 4 * (l & 7);
-#pragma unroll
-    for (int t = 0; t < MT; ++t)
-#pragma unroll
-        for (int u = 0; u < NT; ++u) {
-#pragma unroll
-            for (int g = 0; g < 4; ++g) {
-                f32x4 v = {acc[t][u][4 * g], acc[t][u][4 * g + 1], acc[t][u][4 * g + 2], acc[t][u][4 * g + 3]};
-                *(f32x4*)(wl + lr * 36 + 8 * g + 4 * lh) = v;
-            }
-            __builtin_amdgcn_wave_barrier();
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int r = 8 * j + rr;
-                const f32x4 v = *(const f32x4*)(wl + r * 36 + rc);
-                __builtin_nontemporal_store(v, (f32x4*)(P + (col0 + u * 32 + r) * G.ld_part + row0 + t * 32 + rc));
-            }
-            __builtin_amdgcn_wave_barrier();
-        }
+    static_assert(2 * STAGE >= NTHR / 64 * 32 * 36 * 4, "epilogue regions must fit in the staging LDS");
+    store_partials_via_lds<MT, NT>(acc, (float*)lds + w * (32 * 36), G, (int)ti.z, tile_r + wm * MT * 32,
+                                   tile_c + wn * NT * 32, l);
 }
 
 template <bool TRANS>
@@ -550,12 +547,26 @@ __device__ __forceinline__ double pow_bf16_form(double q, double fi) {
 // Workgroup: 1024 consecutive rows of right-hand side r = blockIdx.y; lane
 // t of the workgroup takes rows t, t + 256, t + 512, t + 768 of the block, so
 // every load and store of the workgroup is one contiguous run per wave.
+// Workgroup: 1024 consecutive rows of right-hand side r = blockIdx.y; lane
+// t of the workgroup takes rows t, t + 256, t + 512, t + 768 of the block.
+// The chunk sums of 32 consecutive rows sit side by side (mpart_index), so a
+// wave's partial reads for all chunks form one contiguous run.
 __global__ __launch_bounds__(256) void mepi_kernel(MEpi E) {
     const int64_t r = blockIdx.y;
     const int64_t ib = (int64_t)blockIdx.x * 1024 + threadIdx.x;
     uint32_t fl = 0;
-    const float* pp = E.part + r * E.ld_part;
-    const int64_t sstride = E.r_pad * E.ld_part;
+    double tg[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int64_t i = ib + 256 * e;
+        tg[e] = (E.mode == 0 && r < E.R && i < E.rows) ? E.target[r * E.rows + i] : 0.0;
+    }
+    const float* pp[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int64_t i = ib + 256 * e;
+        pp[e] = E.part + mpart_index(r, i < E.ld_next ? i : 0, 0, E.ld_part, E.splits);
+    }
     double S[4] = {0.0, 0.0, 0.0, 0.0};
     int s = 0;
     for (; s + 4 <= E.splits; s += 4) {            // chunks added in ascending order
@@ -563,10 +574,7 @@ __global__ __launch_bounds__(256) void mepi_kernel(MEpi E) {
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int64_t i = ib + 256 * e;
-                p[q][e] = i < E.ld_next ? pp[(s + q) * sstride + i] : 0.0f;
-            }
+            for (int e = 0; e < 4; ++e) p[q][e] = pp[e][(s + q) * 32];
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -574,10 +582,7 @@ __global__ __launch_bounds__(256) void mepi_kernel(MEpi E) {
     }
     for (; s < E.splits; ++s) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int64_t i = ib + 256 * e;
-            S[e] += i < E.ld_next ? (double)pp[s * sstride + i] : 0.0;
-        }
+        for (int e = 0; e < 4; ++e) S[e] += (double)pp[e][s * 32];
     }
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -589,7 +594,7 @@ __global__ __launch_bounds__(256) void mepi_kernel(MEpi E) {
         if (valid) {
             const int64_t o = r * E.rows + i;
             if (E.mode == 0) {
-                const double tgt = E.target[o];
+                const double tgt = tg[e];
                 const double q = tgt / sm;
                 if (E.bf16 && !E.fi_is_one && q > 0.0 && isfinite(q))
                     y = pow_bf16_form(q, E.fi);
