@@ -126,6 +126,9 @@ def test_multi_argument_errors():
     with pytest.raises(uot.UOTError) as e:
         uot.sinkhorn_multi(K32, to_dev(A), to_dev(B), eps=base.eps, tau=base.tau, max_iter=0)
     assert e.value.status == 1
+    with pytest.raises(uot.UOTError) as e:            # product kernels are 0..4
+        uot.sinkhorn_multi(K32, to_dev(A), to_dev(B), eps=base.eps, tau=base.tau, max_iter=5, tune=5)
+    assert e.value.status == 1
 
 
 def test_multi_full_size_sampled():
