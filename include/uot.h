@@ -319,8 +319,9 @@ uot_status uot_plan(const uot_problem* prob, const double* u, const double* v, c
  * 1, 128 x 128 tiles staged through LDS; 2, each wave loads its own
  * operand fragments; 4, 128 x 128 tiles over the tiled copies.  Other
  * values: UOT_ERR_ARG.  The tiled copies take the workspace of a second K.
- * Workspace (uot_sinkhorn_multi_workspace_size): a transposed copy of K,
- * the split partial sums and the right-hand-side planes.
+ * Workspace (uot_sinkhorn_multi_workspace_size): a transposed copy of K
+ * (or, for the tiled BF16 products, tiled copies of K and K^T), the split
+ * partial sums and the right-hand-side planes.
  * Errors: UOT_ERR_ARG, UOT_ERR_DTYPE, UOT_ERR_ALIGN, UOT_ERR_WORKSPACE,
  * UOT_ERR_UNSUPPORTED, UOT_ERR_HIP.
  */
