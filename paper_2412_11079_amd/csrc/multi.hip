@@ -728,12 +728,10 @@ static hipError_t launch_ring(const MGemm& G, hipStream_t stream) {
     constexpr int TR = WR * MT * 32, TC = WC * NT * 32;
     constexpr int lds = 2 * (TR + 2 * TC) * 64;
     if (G.r_pad % TC != 0 || G.rows_pad % TR != 0) return hipErrorInvalidValue;
-    static bool raised = false;
     auto fn = mgemm_ring_kernel<WR, WC, MT, NT, PD>;
-    if (!raised && lds > 65536) {
+    if (lds > 65536) {      // on every call: the limit is per device, and callers may use several
         hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         if (e != hipSuccess) return e;
-        raised = true;
     }
     dim3 grid((unsigned)(G.r_pad / TC), (unsigned)(G.rows_pad / TR), (unsigned)G.splits);
     hipLaunchKernelGGL(fn, grid, dim3(64 * WR * WC), lds, stream, G);
