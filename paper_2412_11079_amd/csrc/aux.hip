@@ -402,13 +402,27 @@ __global__ void kernel_build(const double* __restrict__ C, int64_t ldc, int64_t 
         for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < chunks;
              q += (int64_t)gridDim.x * blockDim.x) {
             const int64_t j0 = 4 * q;
+            // C's four entries as two 16-byte loads where the row allows it
+            const double* crow = C + i * ldc + j0;
+            double cv[4];
+            if (j0 + 4 <= m && ((uintptr_t)crow & 15) == 0) {
+                const f64x2 c01 = *(const f64x2*)crow;
+                const f64x2 c23 = *(const f64x2*)(crow + 2);
+                cv[0] = c01[0];
+                cv[1] = c01[1];
+                cv[2] = c23[0];
+                cv[3] = c23[1];
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) cv[e] = j0 + e < m ? crow[e] : 0.0;
+            }
             double val[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int64_t j = j0 + e;
                 val[e] = 0.0;
                 if (j < m) {
-                    double x = fi_ - C[i * ldc + j];
+                    double x = fi_ - cv[e];
                     if (g) x += g[j];
                     if (!(x < cut)) val[e] = store_scale * exp(x / eps);
                 }
