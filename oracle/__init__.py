@@ -79,6 +79,13 @@ def _load():
                                               ctypes.c_int, ctypes.c_double, _dp, _dp, _dp, _dp,
                                               _dp, ctypes.POINTER(_i64), _dp]
         lib.orc_sinkhorn_absorbed.restype = _i64
+        lib.orc_grad_target_sqeuclid.argtypes = [_dp, _dp, _dp, _i64, _i64, _i64, _dp]
+        lib.orc_grad_target_sqeuclid.restype = None
+        lib.orc_potential_marginals.argtypes = [_dp, _dp, _dp, _i64, _i64, ctypes.c_double, _dp, _dp]
+        lib.orc_potential_marginals.restype = None
+        lib.orc_loss_potentials.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp, _i64, _i64, ctypes.c_double,
+                                            ctypes.c_double]
+        lib.orc_loss_potentials.restype = ctypes.c_double
         _lib = lib
     return _lib
 
@@ -227,6 +234,33 @@ def grad_points_sqeuclid(G, x, y) -> np.ndarray:
     gx = np.empty((n, d))
     _load().orc_grad_points_sqeuclid(_p(G), _p(x), _p(y), n, m, d, _p(gx))
     return gx
+
+
+def grad_target_sqeuclid(G, x, y) -> np.ndarray:
+    """dL/dy_j = 2 sum_i G_ij (y_j - x_i) for an un-normalised squared-Euclidean cost."""
+    G, x, y = map(_f64, (G, x, y))
+    n, d = x.shape
+    m = y.shape[0]
+    gy = np.empty((m, d))
+    _load().orc_grad_target_sqeuclid(_p(G), _p(x), _p(y), n, m, d, _p(gy))
+    return gy
+
+
+def potential_marginals(C, f, g, eps: float):
+    """Row and column sums of the plan exp((f_i + g_j - C_ij)/eps); returns (r, c)."""
+    C, f, g = map(_f64, (C, f, g))
+    n, m = C.shape
+    r = np.empty(n)
+    c = np.empty(m)
+    _load().orc_potential_marginals(_p(C), _p(f), _p(g), n, m, float(eps), _p(r), _p(c))
+    return r, c
+
+
+def loss_potentials(f, g, r, c, a, b, eps: float, tau: float) -> float:
+    """The objective from the potentials f = eps log u, g = eps log v and the marginals."""
+    f, g, r, c, a, b = map(_f64, (f, g, r, c, a, b))
+    return float(_load().orc_loss_potentials(_p(f), _p(g), _p(r), _p(c), _p(a), _p(b), f.shape[0],
+                                             g.shape[0], float(eps), float(tau)))
 
 
 _STORAGE_KINDS = {"bf16": 1, "e4m3": 2, "f32": 3}

@@ -459,6 +459,79 @@ ORC_EXPORT void orc_grad_points_sqeuclid(const double* G, const double* x, const
     }
 }
 
+/* Gradient with respect to the target points of the same cost:
+ * dL/dy_j = 2 sum_i G_ij (y_j - x_i) (C_ij depends on y_j through
+ * ||x_i - y_j||^2, whose derivative in y_j is 2 (y_j - x_i)). */
+ORC_EXPORT void orc_grad_target_sqeuclid(const double* G, const double* x, const double* y,
+                                         int64_t n, int64_t m, int64_t d, double* grad_y) {
+    const int64_t BLK = 64;
+    int64_t nblk = (m + BLK - 1) / BLK;
+    #pragma omp parallel for schedule(static)
+    for (int64_t blk = 0; blk < nblk; ++blk) {
+        int64_t j0 = blk * BLK, j1 = j0 + BLK < m ? j0 + BLK : m;
+        for (int64_t j = j0; j < j1; ++j)
+            for (int64_t k = 0; k < d; ++k) grad_y[j * d + k] = 0.0;
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = j0; j < j1; ++j)
+                for (int64_t k = 0; k < d; ++k)
+                    grad_y[j * d + k] += G[i * m + j] * (y[j * d + k] - x[i * d + k]);
+        for (int64_t j = j0; j < j1; ++j)
+            for (int64_t k = 0; k < d; ++k) grad_y[j * d + k] *= 2.0;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Marginals and objective from potentials                              */
+/* ------------------------------------------------------------------ */
+
+/* Plan written through the potentials of its total scalings, f = eps log u,
+ * g = eps log v:  P_ij = u_i K_ij v_j = exp((f_i + g_j - C_ij)/eps), finite
+ * even where u, v overflow.  r = P 1 and c = P^T 1, each summed in
+ * ascending index order.  f_i or g_j = -inf gives a zero row or column. */
+ORC_EXPORT void orc_potential_marginals(const double* C, const double* f, const double* g,
+                                        int64_t n, int64_t m, double eps, double* r, double* c) {
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double acc = 0.0;
+        for (int64_t j = 0; j < m; ++j) acc += exp((f[i] + g[j] - C[i * m + j]) / eps);
+        r[i] = acc;
+    }
+    const int64_t BLK = 64;
+    int64_t nblk = (m + BLK - 1) / BLK;
+    #pragma omp parallel for schedule(static)
+    for (int64_t blk = 0; blk < nblk; ++blk) {
+        int64_t j0 = blk * BLK, j1 = j0 + BLK < m ? j0 + BLK : m;
+        double acc[64];
+        for (int64_t j = j0; j < j1; ++j) acc[j - j0] = 0.0;
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = j0; j < j1; ++j) acc[j - j0] += exp((f[i] + g[j] - C[i * m + j]) / eps);
+        for (int64_t j = j0; j < j1; ++j) c[j] = acc[j - j0];
+    }
+}
+
+/* The objective of orc_loss_identity with the log scalings given as
+ * potentials (log u = f/eps, log v = g/eps):
+ *   sum_i r_i f_i + sum_j c_j g_j - eps sum_i r_i + tau KL~(r|a) + tau KL~(c|b). */
+ORC_EXPORT double orc_loss_potentials(const double* f, const double* g, const double* r,
+                                      const double* c, const double* a, const double* b,
+                                      int64_t n, int64_t m, double eps, double tau) {
+    double sr = 0.0, sc = 0.0, mass = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (r[i] > 0.0) sr += r[i] * f[i];
+        mass += r[i];
+    }
+    for (int64_t j = 0; j < m; ++j)
+        if (c[j] > 0.0) sc += c[j] * g[j];
+    double L = sr + sc - eps * mass;
+    if (!isinf(tau)) {
+        double kr = 0.0, kc = 0.0;
+        for (int64_t i = 0; i < n; ++i) kr += orc_kl_term(r[i], a[i]);
+        for (int64_t j = 0; j < m; ++j) kc += orc_kl_term(c[j], b[j]);
+        L += tau * (kr + kc);
+    }
+    return L;
+}
+
 /* ------------------------------------------------------------------ */
 /* Low-precision storage of the kernel                                  */
 /* ------------------------------------------------------------------ */

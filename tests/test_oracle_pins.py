@@ -249,6 +249,52 @@ def test_adjoint_points_matches_central_differences():
     np.testing.assert_allclose(gx, fd, rtol=0, atol=2e-7 * max(1.0, np.max(np.abs(fd))))
 
 
+def test_adjoint_target_points_matches_central_differences():
+    """dL/dy from G against central differences of the loss in each target
+    coordinate (rectangular: a swapped x/y or a wrong sign fails)."""
+    prob = workloads.grad(n=6, m=8, max_iter=7)
+    eps, tau, T = prob.eps, prob.tau, prob.max_iter
+
+    def loss_y(y):
+        C = oracle.cost_points(prob.x, y, 0, False)
+        return _fd_loss(C, prob.a, prob.b, eps, tau, T)
+
+    C, K = _problem_arrays(prob)
+    res = oracle.sinkhorn(K, prob.a, prob.b, eps, tau, T, trace=True)
+    _, _, G = oracle.adjoint(K, prob.a, prob.b, eps, tau, res)
+    gy = oracle.grad_target_sqeuclid(G, prob.x, prob.y)
+    h = 1e-6
+    fd = np.zeros_like(prob.y)
+    for j in range(prob.y.shape[0]):
+        for k in range(3):
+            E = np.zeros_like(prob.y)
+            E[j, k] = h
+            fd[j, k] = (loss_y(prob.y + E) - loss_y(prob.y - E)) / (2 * h)
+    np.testing.assert_allclose(gy, fd, rtol=0, atol=2e-7 * max(1.0, np.max(np.abs(fd))))
+
+
+def test_potential_marginals_and_loss_match_plain_run():
+    """Marginals summed from exp((f+g-C)/eps) equal u (K v) and v (K^T u) of a
+    plain run, and the potential form of the objective equals its
+    definition summed over the plan."""
+    prob = workloads.random_small(13, 9, seed=31, eps=0.07, tau=0.6)
+    C, K = _problem_arrays(prob)
+    res = oracle.sinkhorn(K, prob.a, prob.b, prob.eps, prob.tau, 25)
+    f, g = prob.eps * np.log(res.u), prob.eps * np.log(res.v)
+    r, c = oracle.potential_marginals(C, f, g, prob.eps)
+    np.testing.assert_allclose(r, res.r, rtol=1e-13)
+    np.testing.assert_allclose(c, res.c, rtol=1e-13)
+    L_direct, _ = oracle.loss_direct(C, K, res.u, res.v, prob.a, prob.b, prob.eps, prob.tau)
+    L = oracle.loss_potentials(f, g, r, c, prob.a, prob.b, prob.eps, prob.tau)
+    assert L == pytest.approx(L_direct, rel=1e-12)
+    # a zero scaling (f = -inf) removes its row from both marginals
+    f2 = f.copy()
+    f2[3] = -np.inf
+    r2, c2 = oracle.potential_marginals(C, f2, g, prob.eps)
+    assert r2[3] == 0.0
+    np.testing.assert_allclose(c2, c - np.exp((f[3] + g - C[3]) / prob.eps), rtol=1e-12)
+
+
 def test_adjoint_envelope_at_convergence():
     # At the optimum dL/dC = P, dL/da = tau (1 - r/a), dL/db = tau (1 - c/b).
     prob = workloads.random_small(9, 7, seed=22, eps=0.3, tau=1.0)
