@@ -239,6 +239,35 @@ size_t uot_sinkhorn_workspace_size(const uot_problem* prob, const uot_options* o
 uot_status uot_sinkhorn(const uot_problem* prob, const uot_options* opt,
                         const uot_outputs* out, void* ws, size_t ws_bytes, void* stream);
 
+/*
+ * For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): uot_sinkhorn without a
+ * workspace argument.  Its scratch is a device array of the library,
+ * UOT_NOALLOC_SCRATCH_BYTES (64 MiB), one copy per GPU held until the
+ * process ends; the call makes no hipMalloc, hipFree or other allocation
+ * and never waits on `stream`.
+ *   - Same problem, options and outputs as uot_sinkhorn, same kernels and
+ *     results (bit for bit), on the current device (hipGetDevice); `stream`
+ *     must belong to it.
+ *   - The problem's workspace (uot_sinkhorn_workspace_size) must be at most
+ *     UOT_NOALLOC_SCRATCH_BYTES, else UOT_ERR_WORKSPACE (e.g. a 16384^2 FP32
+ *     K with FP32 accumulation needs about 17 MiB; a K built inside the
+ *     call from C needs n x ldk more and rarely fits).
+ *   - With tol > 0 all max_iter iterations are enqueued; the launches after
+ *     the stopping test passed return at once (info.iters as uot_sinkhorn).
+ *   - Absorption (opt->absorb_log_threshold > 0) is refused with
+ *     UOT_ERR_UNSUPPORTED: it decides on the host.
+ *   - Every call on one GPU uses that GPU's scratch, which keeps the last
+ *     call's contents (each call re-initialises what it reads first): calls
+ *     that overlap on one GPU (two streams, two host threads) race and must
+ *     be ordered by the caller.
+ * Errors: as uot_sinkhorn, plus UOT_ERR_WORKSPACE (above the scratch size),
+ * UOT_ERR_UNSUPPORTED (absorption; device index above 63), UOT_ERR_HIP.
+ */
+#define UOT_NOALLOC_SCRATCH_BYTES (64ull << 20)
+uot_status uot_sinkhorn_noalloc(const uot_problem* prob, const uot_options* opt,
+                                const uot_outputs* out, void* stream);
+
 /* uot_sinkhorn with HIP-event timing of the streaming kernels written to
  * *prof (host pointer).  Synchronises `stream` before returning. */
 uot_status uot_sinkhorn_profiled(const uot_problem* prob, const uot_options* opt,

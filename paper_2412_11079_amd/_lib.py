@@ -12,6 +12,7 @@ UOT_F64, UOT_F32, UOT_BF16, UOT_FP8_E4M3 = range(4)
 UOT_COST_SQEUCLID, UOT_COST_COSINE = 0, 1
 UOT_ACC_F32, UOT_ACC_F64 = 0, 1
 UOT_FLAG_NONFINITE, UOT_FLAG_ZERO_SUM, UOT_FLAG_NOT_CONVERGED, UOT_FLAG_BARRIER_TIMEOUT = 1, 2, 8, 16
+UOT_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
@@ -63,6 +64,8 @@ SIGNATURES = {
     "uot_sinkhorn_workspace_size": ([ctypes.POINTER(Problem), ctypes.POINTER(Options)], _sz),
     "uot_sinkhorn": ([ctypes.POINTER(Problem), ctypes.POINTER(Options), ctypes.POINTER(Outputs), _vp, _sz, _vp],
                      _i32),
+    "uot_sinkhorn_noalloc": ([ctypes.POINTER(Problem), ctypes.POINTER(Options), ctypes.POINTER(Outputs), _vp],
+                             _i32),
     "uot_sinkhorn_profiled": ([ctypes.POINTER(Problem), ctypes.POINTER(Options), ctypes.POINTER(Outputs), _vp,
                                _sz, _vp, ctypes.POINTER(Profile)], _i32),
     "uot_kernel_to_f32": ([_vp, _i32, _i64, _dbl, _vp, _vp], _i32),

@@ -92,6 +92,21 @@ hipError_t events(size_t count, std::vector<hipEvent_t>& out) {
     return hipSuccess;
 }
 
+// Scratch of the no-allocation entry point (uot_sinkhorn_noalloc): one copy
+// per GPU, held until the process ends, shared by every such call on that
+// GPU.  Its host-side name is not a device address: host code uses only the
+// address hipGetSymbolAddress returns for the current device.
+constexpr size_t kScratchBytes = (size_t)UOT_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+bool g_scratch_ready[kMaxDevices];
+
+// Device address of the current device's scratch (looked up once per device).
+uot_status scratch_for_current_device(void** ptr);
+
 // Launch plan for one solve.
 struct Plan {
     int k_dtype;
@@ -276,8 +291,11 @@ uot_status make_plan(const uot_problem* p, const uot_options* o, Plan& P) {
 
 double fi_of(double eps, double tau) { return isinf(tau) ? 1.0 : tau / (tau + eps); }
 
+// no_sync: never wait on the stream (the caller may not allow it): with
+// tol > 0 every iteration up to max_iter is enqueued and the launches after
+// the stop return at once; absorption, which decides on the host, is refused.
 uot_status run_sinkhorn(const uot_problem* p, const uot_options* o, const uot_outputs* out, void* ws,
-                        size_t ws_bytes, hipStream_t stream, uot_profile* prof) {
+                        size_t ws_bytes, hipStream_t stream, uot_profile* prof, bool no_sync = false) {
     Plan P;
     uot_status st = make_plan(p, o, P);
     if (st != UOT_OK) return st;
@@ -286,8 +304,10 @@ uot_status run_sinkhorn(const uot_problem* p, const uot_options* o, const uot_ou
     if (ws_bytes < P.total || (P.total > 0 && !ws))
         return fail(UOT_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", P.total, ws_bytes);
     if (!aligned(ws, kAlign)) return fail(UOT_ERR_ALIGN, "workspace must be 256-byte aligned");
+    if (no_sync && (P.stab || prof))
+        return fail(UOT_ERR_UNSUPPORTED, "absorption and profiling wait on the stream");
     uint32_t* flag_host = nullptr;
-    if (o->tol > 0.0) {
+    if (o->tol > 0.0 && !no_sync) {
         flag_host = pinned_flag();
         if (!flag_host) return hip_fail(g_pinned_err, "hipHostMalloc");
     }
@@ -549,6 +569,22 @@ uot_status run_sinkhorn(const uot_problem* p, const uot_options* o, const uot_ou
         }
         UOT_HIP(hipEventElapsedTime(&prof->loop_ms, ev[0], ev[evi - 1]), "hipEventElapsedTime");
     }
+    return UOT_OK;
+}
+
+uot_status scratch_for_current_device(void** ptr) {
+    int dev = 0;
+    UOT_HIP(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(UOT_ERR_UNSUPPORTED, "device index %d (at most %d devices)", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ready[dev]) {
+        void* p = nullptr;
+        UOT_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (!p || !aligned(p, kAlign)) return fail(UOT_ERR_HIP, "scratch symbol has no aligned device address");
+        g_scratch_ptr[dev] = p;
+        g_scratch_ready[dev] = true;
+    }
+    *ptr = g_scratch_ptr[dev];
     return UOT_OK;
 }
 
@@ -1456,6 +1492,22 @@ size_t uot_sinkhorn_workspace_size(const uot_problem* prob, const uot_options* o
 uot_status uot_sinkhorn(const uot_problem* prob, const uot_options* opt, const uot_outputs* out, void* ws,
                         size_t ws_bytes, void* stream) {
     return run_sinkhorn(prob, opt, out, ws, ws_bytes, (hipStream_t)stream, nullptr);
+}
+
+uot_status uot_sinkhorn_noalloc(const uot_problem* prob, const uot_options* opt, const uot_outputs* out,
+                                void* stream) {
+    Plan P;
+    uot_status st = make_plan(prob, opt, P);
+    if (st != UOT_OK) return st;
+    if (P.stab)
+        return fail(UOT_ERR_UNSUPPORTED, "the no-allocation entry point runs without absorption (it waits on the host)");
+    if (P.total > kScratchBytes)
+        return fail(UOT_ERR_WORKSPACE, "problem needs %zu bytes of scratch; the no-allocation entry point holds %zu",
+                    P.total, kScratchBytes);
+    void* ws = nullptr;
+    st = scratch_for_current_device(&ws);
+    if (st != UOT_OK) return st;
+    return run_sinkhorn(prob, opt, out, ws, kScratchBytes, (hipStream_t)stream, nullptr, true);
 }
 
 uot_status uot_sinkhorn_profiled(const uot_problem* prob, const uot_options* opt, const uot_outputs* out,
