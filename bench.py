@@ -230,19 +230,34 @@ def fwd_bwd(uot, workloads, torch, dev, args):
         e0.record()
         r = fwd()
         e1.record()
-        ga, gb, gx = uot.sinkhorn_backward(r, g, x=x, y=y)
+        uot.sinkhorn_backward(r, g, x=x, y=y)
         e2.record()
         torch.cuda.synchronize()
         f_ms += e0.elapsed_time(e1)
         b_ms += e1.elapsed_time(e2)
     f_ms /= reps
     b_ms /= reps
+    # the same reverse pass also forming the dense dL/dC and dL/dy
+    c_ms = 0.0
+    for _ in range(reps):
+        r = fwd()
+        e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(2))
+        e1.record()
+        gr = uot.sinkhorn_backward(r, g, x=x, y=y, want_C=True, want_y=True)
+        e2.record()
+        torch.cuda.synchronize()
+        c_ms += e1.elapsed_time(e2)
+        del gr
+    c_ms /= reps
     kb = prob.n * prob.m * 4
     # forward: T passes; reverse: T recompute + T adjoint passes + 1 column + 1 seed pass
     passes = prob.max_iter * 3 + 3
     return {"workload": f"grad: N=M={prob.n} FP32 K, {prob.max_iter} iterations, checkpoints every "
                         f"{prob.checkpoint_every}, gradients for x, a, b",
             "fwd_ms": round(f_ms, 3), "bwd_ms": round(b_ms, 3), "fwd_bwd_ms": round(f_ms + b_ms, 3),
+            "bwd_with_cost_grad_ms": round(c_ms, 3),
+            "cost_grad_tflop_s": round(2.0 * prob.n * prob.m * (2 * prob.max_iter + 2) / ((c_ms - b_ms) * 1e-3) / 1e12, 2)
+            if c_ms > b_ms else None,
             "k_passes": passes, "k_bytes_tb_s": round(passes * kb / ((f_ms + b_ms) * 1e-3) / 1e12, 3)}
 
 

@@ -285,20 +285,44 @@ uot_status uot_sinkhorn_profiled(const uot_problem* prob, const uot_options* opt
  * checkpoints of the forward call (same problem and options, including
  * checkpoint_every; the forward must not have been given u0/v0).
  *
+ * The adjoint of K, Kbar, is a sum of 2T + 2 rank-1 terms (two per
+ * iteration, two from the objective); dL/dC_ij = -Kbar_ij K_ij / eps.  When
+ * grad_C or grad_y is requested the reverse passes store the terms' factors
+ * in the workspace ((2T + 2) (n + m) doubles) and one FP64 matrix product
+ * on the matrix cores with inner dimension 2T + 2 forms dL/dC, K applied in
+ * its epilogue.
+ *
  *   u, v        forward results u_T, v_T (device, n and m)
  *   ckpt        the forward's outputs.ckpt
  *   grad_loss   device scalar g; outputs are g times dL/d(input)
  *   grad_a      device n or NULL;  grad_b  device m or NULL
+ *   grad_C      device n x ldgc FP64 (row-major, ldgc >= m; columns [m, ldgc)
+ *               untouched) or NULL: g dL/dC, with C the cost that built K
+ *               (K = exp(-C/eps), the stored K used in the product)
  *   x, y, dim   source (n x dim) and target (m x dim) points, row-major FP64,
  *               of a squared-Euclidean cost C_ij = ||x_i - y_j||^2 that was
  *               not max-normalised; dim 0 (no point gradient), 2 or 3
- *   grad_x      device n x dim or NULL: dL/dx via dL/dC_ij = -Kbar_ij K_ij / eps
+ *   grad_x      device n x dim or NULL: dL/dx_i = 2 sum_j G_ij (x_i - y_j),
+ *               G = dL/dC, from row sums formed inside the reverse passes
+ *   grad_y      device m x dim or NULL: dL/dy_j = 2 sum_i G_ij (y_j - x_i),
+ *               from column sums in the product's epilogue (needs x)
  *
  * Requirements: max_iter >= 1, checkpoint_every >= 1, tol <= 0, histogram
  * entries > 0, rows of at most 8192 columns (FP32 or FP64 K).
  * Errors: UOT_ERR_ARG, UOT_ERR_UNSUPPORTED, UOT_ERR_WORKSPACE, UOT_ERR_ALIGN,
- * UOT_ERR_HIP.  Workspace: uot_sinkhorn_backward_workspace_size bytes.
+ * UOT_ERR_HIP.  Workspace: uot_sinkhorn_backward_workspace_size bytes, with
+ * cost_grad != 0 when grad_C or grad_y will be requested.
  */
+size_t uot_sinkhorn_backward_workspace_size(const uot_problem* prob, const uot_options* opt, int64_t dim,
+                                            int32_t cost_grad);
+uot_status uot_sinkhorn_backward(const uot_problem* prob, const uot_options* opt,
+                                 const double* u, const double* v, const double* ckpt,
+                                 const double* grad_loss, double* grad_a, double* grad_b,
+                                 double* grad_C, int64_t ldgc,
+                                 const double* x, const double* y, int64_t dim,
+                                 double* grad_x, double* grad_y,
+                                 void* ws, size_t ws_bytes, void* stream);
+
 /*
  * Decode `count` stored kernel entries (a multiple of 16 bytes' worth) to
  * FP32 exactly as the streaming passes read them, times k_scale.  For
@@ -359,12 +383,6 @@ uot_status uot_sinkhorn_multi(const uot_problem* shared, int32_t R, const double
                               const uot_options* opt, double* U, double* V, double* losses, uot_info* info,
                               void* ws, size_t ws_bytes, void* stream);
 
-size_t uot_sinkhorn_backward_workspace_size(const uot_problem* prob, const uot_options* opt, int64_t dim);
-uot_status uot_sinkhorn_backward(const uot_problem* prob, const uot_options* opt,
-                                 const double* u, const double* v, const double* ckpt,
-                                 const double* grad_loss, double* grad_a, double* grad_b,
-                                 const double* x, const double* y, int64_t dim, double* grad_x,
-                                 void* ws, size_t ws_bytes, void* stream);
 
 /*
  * Many independent problems of uneven size, solved in ONE persistent launch

@@ -17,7 +17,7 @@ from . import _lib
 from ._lib import (UOT_ACC_F32, UOT_ACC_F64, UOT_BF16, UOT_COST_COSINE, UOT_COST_SQEUCLID, UOT_F32, UOT_F64,
                    UOT_FLAG_NONFINITE, UOT_FLAG_NOT_CONVERGED, UOT_FLAG_ZERO_SUM, UOT_FP8_E4M3, UOTError)
 
-__all__ = ["sinkhorn", "sinkhorn_backward", "UOTLoss", "uot_loss", "cost_from_points", "kernel_from_cost",
+__all__ = ["sinkhorn", "sinkhorn_backward", "Gradients", "UOTLoss", "UOTCostLoss", "uot_loss", "uot_loss_cost", "cost_from_points", "kernel_from_cost",
            "kernel_to_f32", "sinkhorn_batched", "BatchedSolver", "BatchedResult", "plan", "sinkhorn_multi",
            "SinkhornResult", "UOTError", "lib_path",
            "UOT_F64", "UOT_F32", "UOT_BF16", "UOT_FP8_E4M3", "UOT_COST_SQEUCLID", "UOT_COST_COSINE"]
@@ -307,12 +307,24 @@ def sinkhorn_multi(K: torch.Tensor, A: torch.Tensor, B: torch.Tensor, *, m: Opti
     return res
 
 
+@dataclass
+class Gradients:
+    """Outputs of sinkhorn_backward, each g times dL/d(input) or None."""
+    grad_a: Optional[torch.Tensor] = None
+    grad_b: Optional[torch.Tensor] = None
+    grad_x: Optional[torch.Tensor] = None
+    grad_C: Optional[torch.Tensor] = None
+    grad_y: Optional[torch.Tensor] = None
+
+
 def sinkhorn_backward(res: SinkhornResult, grad_loss: torch.Tensor, *, x: Optional[torch.Tensor] = None,
-                      y: Optional[torch.Tensor] = None, want_a: bool = True, want_b: bool = True):
+                      y: Optional[torch.Tensor] = None, want_a: bool = True, want_b: bool = True,
+                      want_x: bool = True, want_C: bool = False, want_y: bool = False) -> Gradients:
     """Reverse pass of ``sinkhorn(..., checkpoint_every=k)`` (include/uot.h,
     uot_sinkhorn_backward).  ``grad_loss`` is a device FP64 scalar.  With the
     points ``x`` (n x d) and ``y`` (m x d) of an un-normalised squared-Euclidean
-    cost, also returns dL/dx.  Returns (grad_a, grad_b, grad_x)."""
+    cost, also dL/dx (``want_x``) and dL/dy (``want_y``); ``want_C`` gives
+    the dense dL/dC (n x m FP64)."""
     if res.ckpt is None:
         raise ValueError("the forward call needs checkpoint_every > 0")
     prob, opt = res._problem, res._options
@@ -329,30 +341,37 @@ def sinkhorn_backward(res: SinkhornResult, grad_loss: torch.Tensor, *, x: Option
         if y is None or x.dtype != torch.float64 or x.shape != (n, dim):
             raise ValueError("x must be an (n, d) float64 tensor matching y")
         x = x.contiguous()
+    if want_y and x is None:
+        raise ValueError("want_y needs the points x and y")
+    cost_grad = 1 if (want_C or want_y) else 0
     L = _lib.lib()
-    need = L.uot_sinkhorn_backward_workspace_size(ctypes.byref(prob), ctypes.byref(opt), dim)
+    need = L.uot_sinkhorn_backward_workspace_size(ctypes.byref(prob), ctypes.byref(opt), dim, cost_grad)
     if need == 0:
         _lib.check(L.uot_sinkhorn_backward(ctypes.byref(prob), ctypes.byref(opt), None, None, None, None, None,
-                                           None, None, None, dim, None, None, 0, None))
+                                           None, None, 0, None, None, dim, None, None, None, 0, None))
     ws = _workspace(need, device)
-    ga = torch.empty(n, dtype=torch.float64, device=device) if want_a else None
-    gb = torch.empty(m, dtype=torch.float64, device=device) if want_b else None
-    gx = torch.empty((n, dim), dtype=torch.float64, device=device) if x is not None else None
+    out = Gradients()
+    out.grad_a = torch.empty(n, dtype=torch.float64, device=device) if want_a else None
+    out.grad_b = torch.empty(m, dtype=torch.float64, device=device) if want_b else None
+    out.grad_x = torch.empty((n, dim), dtype=torch.float64, device=device) if (x is not None and want_x) else None
+    out.grad_y = torch.empty((m, dim), dtype=torch.float64, device=device) if want_y else None
+    out.grad_C = torch.empty((n, m), dtype=torch.float64, device=device) if want_C else None
     _lib.check(L.uot_sinkhorn_backward(ctypes.byref(prob), ctypes.byref(opt), _ptr(res.u), _ptr(res.v),
-                                       _ptr(res.ckpt), _ptr(g), _ptr(ga), _ptr(gb), _ptr(x), _ptr(y), dim,
-                                       _ptr(gx), _ptr(ws), ws.numel(), _stream(device)))
-    ga_keep = (ws, g, x, y)
-    del ga_keep
-    return ga, gb, gx
+                                       _ptr(res.ckpt), _ptr(g), _ptr(out.grad_a), _ptr(out.grad_b),
+                                       _ptr(out.grad_C), m, _ptr(x), _ptr(y), dim, _ptr(out.grad_x),
+                                       _ptr(out.grad_y), _ptr(ws), ws.numel(), _stream(device)))
+    out._keep = (ws, g, x, y)   # buffers must outlive the enqueued work
+    return out
 
 
 class UOTLoss(torch.autograd.Function):
     """UOT objective of the unrolled loop on points, with gradients w.r.t. the
-    source points x, and the histograms a and b (the target points y get none).
+    source points x, the target points y and the histograms a and b.
 
     Forward: squared-Euclidean cost of (x, y) (not normalised), Gibbs kernel
     in ``k_dtype``, ``max_iter`` fused iterations with v and K^T u saved every
-    ``checkpoint_every``; backward: the library's reverse pass."""
+    ``checkpoint_every``; backward: the library's reverse pass (dL/dy through
+    the dense cost gradient, formed only when y needs a gradient)."""
 
     @staticmethod
     def forward(ctx, x, y, a, b, eps: float, tau: float, max_iter: int, checkpoint_every: int = 50,
@@ -366,24 +385,58 @@ class UOTLoss(torch.autograd.Function):
                        eps=eps, tau=tau, max_iter=max_iter, checkpoint_every=checkpoint_every)
         ctx.res = res
         ctx.save_for_backward(x64, y64)
-        ctx.dtypes = (x.dtype, a.dtype, b.dtype)
+        ctx.dtypes = (x.dtype, y.dtype, a.dtype, b.dtype)
         return res.loss.clone().to(x.dtype)
 
     @staticmethod
     def backward(ctx, grad):
         x64, y64 = ctx.saved_tensors
-        need_x, _, need_a, need_b = ctx.needs_input_grad[:4]
-        ga, gb, gx = sinkhorn_backward(ctx.res, grad.detach().to(torch.float64), x=x64 if need_x else None,
-                                       y=y64 if need_x else None, want_a=need_a, want_b=need_b)
-        xd, ad, bd = ctx.dtypes
-        return (gx.to(xd) if gx is not None else None, None, ga.to(ad) if ga is not None else None,
-                gb.to(bd) if gb is not None else None, None, None, None, None, None)
+        need_x, need_y, need_a, need_b = ctx.needs_input_grad[:4]
+        pts = need_x or need_y
+        gr = sinkhorn_backward(ctx.res, grad.detach().to(torch.float64), x=x64 if pts else None,
+                               y=y64 if pts else None, want_a=need_a, want_b=need_b, want_x=need_x,
+                               want_y=need_y)
+        xd, yd, ad, bd = ctx.dtypes
+        cast = lambda t, d: t.to(d) if t is not None else None  # noqa: E731
+        return (cast(gr.grad_x, xd), cast(gr.grad_y, yd), cast(gr.grad_a, ad), cast(gr.grad_b, bd),
+                None, None, None, None, None)
+
+
+class UOTCostLoss(torch.autograd.Function):
+    """UOT objective of the unrolled loop on a dense FP64 cost C, with
+    gradients w.r.t. C (dense, on the matrix cores), a and b."""
+
+    @staticmethod
+    def forward(ctx, C, a, b, eps: float, tau: float, max_iter: int, checkpoint_every: int = 50,
+                k_dtype: torch.dtype = torch.float32):
+        C64 = C.detach().to(torch.float64).contiguous()
+        K = kernel_from_cost(C64, eps, k_dtype)
+        res = sinkhorn(a.detach().to(torch.float64).contiguous(), b.detach().to(torch.float64).contiguous(), K,
+                       m=C64.shape[1], eps=eps, tau=tau, max_iter=max_iter, checkpoint_every=checkpoint_every)
+        ctx.res = res
+        ctx.dtypes = (C.dtype, a.dtype, b.dtype)
+        return res.loss.clone().to(C.dtype)
+
+    @staticmethod
+    def backward(ctx, grad):
+        need_C, need_a, need_b = ctx.needs_input_grad[:3]
+        gr = sinkhorn_backward(ctx.res, grad.detach().to(torch.float64), want_a=need_a, want_b=need_b,
+                               want_C=need_C)
+        cd, ad, bd = ctx.dtypes
+        cast = lambda t, d: t.to(d) if t is not None else None  # noqa: E731
+        return (cast(gr.grad_C, cd), cast(gr.grad_a, ad), cast(gr.grad_b, bd), None, None, None, None, None)
 
 
 def uot_loss(x, y, a, b, eps: float, tau: float, max_iter: int, checkpoint_every: int = 50,
              k_dtype: torch.dtype = torch.float32) -> torch.Tensor:
-    """Differentiable UOT objective (see UOTLoss)."""
+    """Differentiable UOT objective of two point clouds (see UOTLoss)."""
     return UOTLoss.apply(x, y, a, b, eps, tau, max_iter, checkpoint_every, k_dtype)
+
+
+def uot_loss_cost(C, a, b, eps: float, tau: float, max_iter: int, checkpoint_every: int = 50,
+                  k_dtype: torch.dtype = torch.float32) -> torch.Tensor:
+    """Differentiable UOT objective of a dense cost matrix (see UOTCostLoss)."""
+    return UOTCostLoss.apply(C, a, b, eps, tau, max_iter, checkpoint_every, k_dtype)
 
 
 from .batched import BatchedResult, BatchedSolver, sinkhorn_batched  # noqa: E402

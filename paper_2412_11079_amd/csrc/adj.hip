@@ -238,6 +238,7 @@ __global__ __launch_bounds__(WG) void adj_kernel(AdjLaunch L) {
             }
             qrow = rbar * ui;
             if (tid == 0) {
+                if (L.st_q) L.st_q[r0 + k] = qrow;
                 lseed[k] = useed;
                 labar[k] = abar;
                 if constexpr (DIM > 0) {
@@ -254,6 +255,7 @@ __global__ __launch_bounds__(WG) void adj_kernel(AdjLaunch L) {
             const double sbar = (ui > 0.0) ? -L.fi * ubar * ui / si : 0.0;
             qrow = sbar;
             if (tid == 0) {
+                if (L.st_q) L.st_q[r0 + k] = qrow;
                 if (ai > 0.0) labar[k] += L.fi * ubar * ui / ai;
                 if constexpr (DIM > 0) {
                     lgsum[k] += -inv_eps * (ui * T[0] + sbar * T[1]);
@@ -284,6 +286,7 @@ __global__ __launch_bounds__(WG) void adj_kernel(AdjLaunch L) {
     __syncthreads();
     for (int k = tid; k < nrows; k += WG) {
         const int64_t i = r0 + k;
+        if (L.st_u) L.st_u[i] = lu[k];
         if constexpr (PHASE == ADJ_SEED) L.useed[i] = lseed[k];
         L.abar[i] = labar[k];
         if constexpr (DIM > 0) {
@@ -293,6 +296,16 @@ __global__ __launch_bounds__(WG) void adj_kernel(AdjLaunch L) {
         }
     }
     st.store_partials((AT*)L.partials + (int64_t)blockIdx.x * L.ldp);
+    if (L.st_a) {
+        // Column factors: each workgroup copies its share of A and B.
+        const int64_t per = (m + gridDim.x - 1) / gridDim.x;
+        const int64_t j0 = (int64_t)blockIdx.x * per;
+        const int64_t j1 = j0 + per < m ? j0 + per : m;
+        for (int64_t j = j0 + tid; j < j1; j += WG) {
+            L.st_a[j] = L.A[j];
+            L.st_b[j] = L.B[j];
+        }
+    }
 }
 
 size_t adj_lds_bytes(int64_t rows_per_wg, int dim, int64_t m, int elem) {
@@ -439,6 +452,212 @@ hipError_t launch_adj_finish(const AdjFinish& F, hipStream_t stream) {
     int blocks = (int)((mx + 255) / 256);
     if (blocks > 2048) blocks = 2048;
     hipLaunchKernelGGL(adj_finish_kernel, dim3(blocks), dim3(256), 0, stream, F);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Cost gradient.  Kbar is the sum of 2T + 2 rank-1 terms whose factors the
+// reverse passes stored (slot s: row factor Lf[s], column factor Rf[s]), so
+//   dL/dC_ij = -(grad_loss / eps) K_ij sum_s Lf[s][i] Rf[s][j]
+// is one dense FP64 product with inner dimension 2T + 2 (a contraction: it
+// runs on the matrix cores, v_mfma_f64_16x16x4f64) and the kernel applied in
+// its epilogue.  Workgroup: 4 waves in 2 x 2 over a 128 x 128 output tile,
+// each wave 64 x 64 as 4 x 4 blocks of 16 x 16.  Fragment of a block
+// (16 rows x 4 slots): lane l holds Lf[s0 + l/16][i0 + l%16], read straight
+// from memory (four 128-byte runs per wave); the next 4 slots are in flight
+// while the 16 products of the current ones issue.  The inner dimension is
+// padded to a multiple of 4 with zero factors.  Output block: lane l holds
+// rows i0 + l/16 + 4 q, q < 4, of column j0 + l%16 (the FP64 form
+// interleaves its four result rows, unlike the FP32 16 x 16 forms).
+// ---------------------------------------------------------------------------
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+constexpr int GC_WG = 256;
+constexpr int GC_TILE = 128;
+
+int gradc_row_tiles(int64_t n) { return (int)((n + GC_TILE - 1) / GC_TILE); }
+
+__global__ void fill_f64_kernel(double* p, int64_t count, double value) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += stride) p[k] = value;
+}
+
+hipError_t launch_fill_f64(double* p, int64_t count, double value, hipStream_t stream) {
+    if (count <= 0) return hipSuccess;
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(fill_f64_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, p, count, value);
+    return hipGetLastError();
+}
+
+template <typename KT, int DIM>
+__global__ __launch_bounds__(GC_WG, 2) void gradc_kernel(GradCLaunch L) {
+    constexpr int ND = 1 + DIM;
+    __shared__ double red[2][ND][64];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wi = wave >> 1, wj = wave & 1;
+    const int64_t n = L.n, m = L.m;
+    const int64_t tiles_j = (m + GC_TILE - 1) / GC_TILE;
+    const int64_t tiles = tiles_j * ((n + GC_TILE - 1) / GC_TILE);
+    // Workgroups go to the 8 XCDs in turn: give each XCD a contiguous run of
+    // tiles (same row tile, so its row factors stay in that XCD's L2).
+    int64_t b = blockIdx.x;
+    if (tiles % 8 == 0) b = (b % 8) * (tiles / 8) + b / 8;
+    const int64_t ti = b / tiles_j, tj = b % tiles_j;
+    const int64_t i0 = ti * GC_TILE + wi * 64;
+    const int64_t j0 = tj * GC_TILE + wj * 64;
+    const int r16 = lane & 15, g4 = lane >> 4;
+
+    // Fragment addresses (rows and columns past the end read the last one;
+    // their results are never stored).
+    const double* pa[4];
+    const double* pb[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        int64_t i = i0 + 16 * q + r16;
+        int64_t j = j0 + 16 * q + r16;
+        pa[q] = L.Lf + (int64_t)g4 * n + (i < n ? i : n - 1);
+        pb[q] = L.Rf + (int64_t)g4 * m + (j < m ? j : m - 1);
+    }
+    f64x4_t acc[4][4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[p][q] = (f64x4_t){0.0, 0.0, 0.0, 0.0};
+
+    const int64_t steps = L.nterms / 4;     // nterms is padded to a multiple of 4
+    const int64_t sa = 4 * n, sb = 4 * m;
+    double a0[4], b0[4], a1[4], b1[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        a0[q] = pa[q][0];
+        b0[q] = pb[q][0];
+    }
+    for (int64_t st = 0; st < steps; st += 2) {
+        const bool more1 = st + 1 < steps;
+        const bool more2 = st + 2 < steps;
+        const int64_t o1 = more1 ? (st + 1) : st;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            a1[q] = pa[q][o1 * sa];
+            b1[q] = pb[q][o1 * sb];
+        }
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[p], b0[q], acc[p][q], 0, 0, 0);
+        if (!more1) break;
+        const int64_t o2 = more2 ? (st + 2) : st + 1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            a0[q] = pa[q][o2 * sa];
+            b0[q] = pb[q][o2 * sb];
+        }
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[p], b1[q], acc[p][q], 0, 0, 0);
+    }
+
+    // Epilogue: G = scale K (.) acc; column sums of G and G x_i for the target gradient.
+    const double scale = -(*L.grad_loss) * L.inv_eps;
+    const KT* Kp = (const KT*)L.K;
+    double cs[4][ND];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int d = 0; d < ND; ++d) cs[q][d] = 0.0;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t i = i0 + 16 * p + g4 + 4 * e;
+            if (i >= n) continue;
+            double xi[DIM > 0 ? DIM : 1];
+            if constexpr (DIM > 0) {
+                if (L.ysum)
+#pragma unroll
+                    for (int d = 0; d < DIM; ++d) xi[d] = L.x[i * DIM + d];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t j = j0 + 16 * q + r16;
+                if (j >= m) continue;
+                const double g = scale * (double)Kp[i * L.ldk + j] * acc[p][q][e];
+                if (L.G) L.G[i * L.ldg + j] = g;
+                cs[q][0] += g;
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) cs[q][1 + d] += g * xi[d];
+            }
+        }
+    }
+    if (!L.ysum) return;
+    // Sum the 4 row groups of the wave, then the two waves of a column range.
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            double v = cs[q][d];
+            v += __shfl_xor(v, 16);
+            v += __shfl_xor(v, 32);
+            cs[q][d] = v;
+        }
+    if (wi == 1 && g4 == 0)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int d = 0; d < ND; ++d) red[wj][d][16 * q + r16] = cs[q][d];
+    __syncthreads();
+    if (wi == 0 && g4 == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t j = j0 + 16 * q + r16;
+            if (j >= m) continue;
+#pragma unroll
+            for (int d = 0; d < ND; ++d) L.ysum[(ti * ND + d) * m + j] = cs[q][d] + red[wj][d][16 * q + r16];
+        }
+    }
+}
+
+template <typename KT>
+static hipError_t gradc_launch_t(const GradCLaunch& L, hipStream_t stream) {
+    const int64_t tiles = (int64_t)gradc_row_tiles(L.n) * ((L.m + GC_TILE - 1) / GC_TILE);
+    const int dim = L.ysum ? L.dim : 0;
+    switch (dim) {
+        case 0: hipLaunchKernelGGL((gradc_kernel<KT, 0>), dim3((unsigned)tiles), dim3(GC_WG), 0, stream, L); break;
+        case 2: hipLaunchKernelGGL((gradc_kernel<KT, 2>), dim3((unsigned)tiles), dim3(GC_WG), 0, stream, L); break;
+        case 3: hipLaunchKernelGGL((gradc_kernel<KT, 3>), dim3((unsigned)tiles), dim3(GC_WG), 0, stream, L); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gradc(const GradCLaunch& L, hipStream_t stream) {
+    if (L.nterms % 4 != 0 || L.nterms < 4) return hipErrorInvalidValue;
+    if (L.k_dtype == UOT_F32) return gradc_launch_t<float>(L, stream);
+    if (L.k_dtype == UOT_F64) return gradc_launch_t<double>(L, stream);
+    return hipErrorInvalidValue;
+}
+
+__global__ void grady_finish_kernel(const double* ysum, int32_t tiles, const double* y, int64_t m, int32_t dim,
+                                    double* grad_y) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    const int nd = 1 + dim;
+    double s0 = 0.0;
+    for (int t = 0; t < tiles; ++t) s0 += ysum[((int64_t)t * nd) * m + j];
+    for (int d = 0; d < dim; ++d) {
+        double sd = 0.0;
+        for (int t = 0; t < tiles; ++t) sd += ysum[((int64_t)t * nd + 1 + d) * m + j];
+        grad_y[j * dim + d] = 2.0 * (y[j * dim + d] * s0 - sd);
+    }
+}
+
+hipError_t launch_grady_finish(const double* ysum, int32_t tiles, const double* y, int64_t m, int32_t dim,
+                               double* grad_y, hipStream_t stream) {
+    hipLaunchKernelGGL(grady_finish_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, stream, ysum, tiles, y,
+                       m, dim, grad_y);
     return hipGetLastError();
 }
 

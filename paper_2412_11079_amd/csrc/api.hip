@@ -598,11 +598,14 @@ struct BwdPlan {
     int32_t G;
     int32_t dim;
     int k, nseg;
+    bool cost_grad;           // store the factors of Kbar for dL/dC or dL/dy
+    int64_t nterms;           // 2T + 2, padded to a multiple of 4
+    int32_t row_tiles;        // row tiles of the cost-gradient product
     size_t off_fwd, off_part, off_str, off_utr, off_wtr, off_vtr, off_useed, off_abar, off_gsum, off_gy,
-        off_bbar, off_cbar, off_wfin, off_avec, total;
+        off_bbar, off_cbar, off_wfin, off_avec, off_lf, off_rf, off_ysum, total;
 };
 
-uot_status make_bwd_plan(const uot_problem* p, const uot_options* o, int64_t dim, BwdPlan& B) {
+uot_status make_bwd_plan(const uot_problem* p, const uot_options* o, int64_t dim, bool cost_grad, BwdPlan& B) {
     uot_options fo = *o;
     fo.fused = 1;
     fo.persistent = 0;
@@ -645,20 +648,34 @@ uot_status make_bwd_plan(const uot_problem* p, const uot_options* o, int64_t dim
     B.off_cbar = off; off = align_up(off + d8 * m, kAlign);
     B.off_wfin = off; off = align_up(off + d8 * m, kAlign);
     B.off_avec = off; off = align_up(off + d8 * m, kAlign);
+    B.cost_grad = cost_grad;
+    B.nterms = round_up(2 * (int64_t)o->max_iter + 2, 4);
+    B.row_tiles = gradc_row_tiles(n);
+    B.off_lf = B.off_rf = B.off_ysum = off;
+    if (cost_grad) {
+        B.off_lf = off; off = align_up(off + d8 * (size_t)B.nterms * n, kAlign);
+        B.off_rf = off; off = align_up(off + d8 * (size_t)B.nterms * m, kAlign);
+        B.off_ysum = off; off = align_up(off + d8 * (size_t)B.row_tiles * (1 + (dim > 0 ? dim : 0)) * m, kAlign);
+    }
     B.total = off;
     return UOT_OK;
 }
 
 uot_status run_backward(const uot_problem* p, const uot_options* o, const double* uT, const double* vT,
                         const double* ckpt, const double* grad_loss, double* grad_a, double* grad_b,
-                        const double* x, const double* y, int64_t dim, double* grad_x, void* ws, size_t ws_bytes,
-                        hipStream_t stream) {
+                        double* grad_C, int64_t ldgc, const double* x, const double* y, int64_t dim,
+                        double* grad_x, double* grad_y, void* ws, size_t ws_bytes, hipStream_t stream) {
     BwdPlan B;
-    uot_status st = make_bwd_plan(p, o, dim, B);
+    const bool cost_grad = grad_C != nullptr || grad_y != nullptr;
+    uot_status st = make_bwd_plan(p, o, dim, cost_grad, B);
     if (st != UOT_OK) return st;
     if (!uT || !vT || !ckpt || !grad_loss) return fail(UOT_ERR_ARG, "u, v, ckpt and grad_loss are required");
     if (grad_x && (dim == 0 || !x)) return fail(UOT_ERR_ARG, "grad_x needs x and dim > 0");
+    if (grad_y && (dim == 0 || !x)) return fail(UOT_ERR_ARG, "grad_y needs x, y and dim > 0");
     if (dim > 0 && !y) return fail(UOT_ERR_ARG, "dim > 0 needs the target points y");
+    if (grad_C && ldgc < p->m) return fail(UOT_ERR_ARG, "ldgc (%lld) < m (%lld)", (long long)ldgc, (long long)p->m);
+    if ((grad_C && !aligned(grad_C, 8)) || (grad_y && !aligned(grad_y, 8)))
+        return fail(UOT_ERR_ALIGN, "grad_C and grad_y must be 8-byte aligned");
     if (ws_bytes < B.total || !ws) return fail(UOT_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", B.total, ws_bytes);
     if (!aligned(ws, kAlign)) return fail(UOT_ERR_ALIGN, "workspace must be 256-byte aligned");
     const Plan& P = B.F;
@@ -681,6 +698,13 @@ uot_status run_backward(const uot_problem* p, const uot_options* o, const double
     double* cbar = (double*)(base + B.off_cbar);
     double* wfin = (double*)(base + B.off_wfin);
     double* avec = (double*)(base + B.off_avec);
+    double* Lf = cost_grad ? (double*)(base + B.off_lf) : nullptr;
+    double* Rf = cost_grad ? (double*)(base + B.off_rf) : nullptr;
+    const int64_t used_terms = 2 * (int64_t)o->max_iter + 2;
+    if (cost_grad && B.nterms > used_terms) {
+        UOT_HIP(launch_fill_f64(Lf + used_terms * n, (B.nterms - used_terms) * n, 0.0, stream), "factor padding");
+        UOT_HIP(launch_fill_f64(Rf + used_terms * m, (B.nterms - used_terms) * m, 0.0, stream), "factor padding");
+    }
     const void* K = p->K;
     int64_t ldk = p->ldk;
     if (P.build_k) {
@@ -782,6 +806,13 @@ uot_status run_backward(const uot_problem* p, const uot_options* o, const double
         S.A = avec;
         S.B = vT;
         S.u = uT;
+        if (cost_grad) {
+            // slot 0: (rbar u_T) v_T^T, slot 1: u_T (cbar v_T)^T
+            S.st_q = Lf;
+            S.st_u = Lf + n;
+            S.st_a = Rf + m;
+            S.st_b = Rf;
+        }
         UOT_HIP(launch_adj(p->k_dtype, B.nc, ADJ_SEED, (int)dim, S, stream), "adjoint seed pass");
         AdjColLaunch C2 = Cc;
         C2.partials = A.partials;
@@ -819,6 +850,13 @@ uot_status run_backward(const uot_problem* p, const uot_options* o, const double
             S.u = utr + (size_t)q * n;
             S.s = str + (size_t)q * n;
             S.add_seed = (t == T) ? 1 : 0;
+            if (cost_grad) {
+                // slot 2t: u_t wbar_t^T, slot 2t + 1: sbar_t v_{t-1}^T
+                S.st_u = Lf + (int64_t)(2 * t) * n;
+                S.st_q = Lf + (int64_t)(2 * t + 1) * n;
+                S.st_a = Rf + (int64_t)(2 * t) * m;
+                S.st_b = Rf + (int64_t)(2 * t + 1) * m;
+            }
             UOT_HIP(launch_adj(p->k_dtype, B.nc, ADJ_STEP, (int)dim, S, stream), "adjoint step pass");
             if (t > 1) {
                 AdjColLaunch C3 = Cc;
@@ -847,6 +885,28 @@ uot_status run_backward(const uot_problem* p, const uot_options* o, const double
     Fin.m = m;
     Fin.dim = (int32_t)dim;
     UOT_HIP(launch_adj_finish(Fin, stream), "adjoint finish");
+    if (cost_grad) {
+        GradCLaunch G;
+        memset(&G, 0, sizeof(G));
+        G.K = K;
+        G.k_dtype = p->k_dtype;
+        G.ldk = ldk;
+        G.n = n;
+        G.m = m;
+        G.nterms = B.nterms;
+        G.Lf = Lf;
+        G.Rf = Rf;
+        G.grad_loss = grad_loss;
+        G.inv_eps = 1.0 / p->eps;
+        G.G = grad_C;
+        G.ldg = ldgc;
+        G.x = x;
+        G.dim = (int32_t)dim;
+        G.ysum = grad_y ? (double*)(base + B.off_ysum) : nullptr;
+        UOT_HIP(launch_gradc(G, stream), "cost gradient product");
+        if (grad_y)
+            UOT_HIP(launch_grady_finish(G.ysum, B.row_tiles, y, m, (int32_t)dim, grad_y, stream), "target gradient");
+    }
     return UOT_OK;
 }
 
@@ -1527,18 +1587,19 @@ uot_status uot_kernel_to_f32(const void* K, int32_t k_dtype, int64_t count, doub
     return UOT_OK;
 }
 
-size_t uot_sinkhorn_backward_workspace_size(const uot_problem* prob, const uot_options* opt, int64_t dim) {
+size_t uot_sinkhorn_backward_workspace_size(const uot_problem* prob, const uot_options* opt, int64_t dim,
+                                            int32_t cost_grad) {
     BwdPlan B;
-    if (make_bwd_plan(prob, opt, dim, B) != UOT_OK) return 0;
+    if (make_bwd_plan(prob, opt, dim, cost_grad != 0, B) != UOT_OK) return 0;
     return B.total;
 }
 
 uot_status uot_sinkhorn_backward(const uot_problem* prob, const uot_options* opt, const double* u, const double* v,
                                  const double* ckpt, const double* grad_loss, double* grad_a, double* grad_b,
-                                 const double* x, const double* y, int64_t dim, double* grad_x, void* ws,
-                                 size_t ws_bytes, void* stream) {
-    return run_backward(prob, opt, u, v, ckpt, grad_loss, grad_a, grad_b, x, y, dim, grad_x, ws, ws_bytes,
-                        (hipStream_t)stream);
+                                 double* grad_C, int64_t ldgc, const double* x, const double* y, int64_t dim,
+                                 double* grad_x, double* grad_y, void* ws, size_t ws_bytes, void* stream) {
+    return run_backward(prob, opt, u, v, ckpt, grad_loss, grad_a, grad_b, grad_C, ldgc, x, y, dim, grad_x, grad_y,
+                        ws, ws_bytes, (hipStream_t)stream);
 }
 
 size_t uot_batched_desc_bytes(int32_t count) { return count < 0 ? 0 : batch_desc_bytes(count) + sizeof(uot_batched_meta); }

@@ -349,6 +349,13 @@ struct AdjLaunch {
     int64_t ldp;
     double fi, eps, tau;
     int32_t tau_inf;
+    // Factors of this pass's two rank-1 terms of Kbar, stored for the cost
+    // gradient (NULL = not stored): step t adds u_t wbar_t^T + sbar_t v_{t-1}^T,
+    // the seed (rbar u_T) v_T^T + u_T (cbar v_T)^T.
+    double* st_q;             // n: the row factor the column partials use (step: sbar_t; seed: rbar u_T)
+    double* st_u;             // n: u
+    double* st_a;             // m: copy of A
+    double* st_b;             // m: copy of B
 };
 size_t adj_lds_bytes(int64_t rows_per_wg, int dim, int64_t m, int elem);
 int adj_chunks_max(int k_dtype);
@@ -383,6 +390,34 @@ struct AdjFinish {
     int32_t dim;
 };
 hipError_t launch_adj_finish(const AdjFinish& F, hipStream_t stream);
+
+// Cost gradient from the stored factors (adj.hip):
+//   G_ij = scale K_ij sum_s Lf[s][i] Rf[s][j],  scale = -grad_loss / eps,
+// a dense FP64 product on the matrix cores with the kernel applied in its
+// epilogue; optionally the per-row-tile column sums of G and G x_i that give
+// the target-point gradient.
+struct GradCLaunch {
+    const void* K;            // stored kernel (FP32 or FP64), k_scale 1
+    int32_t k_dtype;
+    int64_t ldk;
+    int64_t n, m;
+    int64_t nterms;           // rank of Kbar (2T + 2)
+    const double* Lf;         // nterms x n
+    const double* Rf;         // nterms x m
+    const double* grad_loss;  // device scalar
+    double inv_eps;
+    double* G;                // n x ldg, or NULL
+    int64_t ldg;
+    const double* x;          // n x dim source points (ysum != NULL)
+    int32_t dim;
+    double* ysum;             // row tiles x m x (1 + dim) column sums, or NULL
+};
+int gradc_row_tiles(int64_t n);
+hipError_t launch_fill_f64(double* p, int64_t count, double value, hipStream_t stream);
+hipError_t launch_gradc(const GradCLaunch& L, hipStream_t stream);
+// grad_y[j][d] = 2 (y_jd sum_i G_ij - sum_i G_ij x_id), the sums taken over row tiles in order.
+hipError_t launch_grady_finish(const double* ysum, int32_t tiles, const double* y, int64_t m, int32_t dim,
+                               double* grad_y, hipStream_t stream);
 
 // Largest co-resident grid for the shape (0 when the shape cannot run persistently).
 int persist_max_grid(int k_dtype, int acc64, int shape_idx, size_t lds);

@@ -23,25 +23,31 @@ def _norm_err(g, ref):
     return float(np.linalg.norm(g - ref) / np.linalg.norm(ref))
 
 
-def _oracle_grads(prob, T):
+def _oracle_grads(prob, T, full=False):
     C = oracle.cost_points(prob.x, prob.y, prob.cost_kind, prob.normalize_max)
     K = oracle.kernel(C, prob.eps)
     res = oracle.sinkhorn(K, prob.a, prob.b, prob.eps, prob.tau, T, trace=True)
     ga, gb, G = oracle.adjoint(K, prob.a, prob.b, prob.eps, prob.tau, res)
     gx = oracle.grad_points_sqeuclid(G, prob.x, prob.y)
+    if full:
+        return res, ga, gb, gx, G, oracle.grad_target_sqeuclid(G, prob.x, prob.y)
     return res, ga, gb, gx
 
 
-def _gpu_grads(prob, T, k, k_dtype, with_x=True):
+def _gpu_grads(prob, T, k, k_dtype, with_x=True, full=False, scale=1.0):
     x, y = to_dev(prob.x), to_dev(prob.y)
     C = uot.cost_from_points(x, y, prob.cost_kind, prob.normalize_max)
     K = uot.kernel_from_cost(C, prob.eps, k_dtype)
     res = uot.sinkhorn(to_dev(prob.a), to_dev(prob.b), K, m=prob.m, eps=prob.eps, tau=prob.tau, max_iter=T,
                        checkpoint_every=k)
-    g = torch.ones((), dtype=torch.float64, device="cuda")
-    ga, gb, gx = uot.sinkhorn_backward(res, g, x=x if with_x else None, y=y if with_x else None)
+    g = torch.full((), scale, dtype=torch.float64, device="cuda")
+    gr = uot.sinkhorn_backward(res, g, x=x if with_x else None, y=y if with_x else None, want_C=full,
+                               want_y=full and with_x)
     torch.cuda.synchronize()
-    return res, ga.cpu().numpy(), gb.cpu().numpy(), (gx.cpu().numpy() if gx is not None else None)
+    np_ = lambda t: t.cpu().numpy() if t is not None else None  # noqa: E731
+    if full:
+        return res, np_(gr.grad_a), np_(gr.grad_b), np_(gr.grad_x), np_(gr.grad_C), np_(gr.grad_y)
+    return res, np_(gr.grad_a), np_(gr.grad_b), np_(gr.grad_x)
 
 
 @pytest.mark.parametrize("n,m,T,k", [(300, 257, 20, 7), (129, 700, 9, 9), (64, 64, 1, 1)])
@@ -145,15 +151,66 @@ def test_backward_directional_finite_differences_gpu():
         assert fd == pytest.approx(float(np.sum(gb * db)), rel=1e-6, abs=1e-12)
 
 
+@pytest.mark.parametrize("n,m,T,k,k_dtype,tol", [
+    (300, 257, 20, 7, torch.float64, 1e-9),      # two row tiles and a ragged column tile
+    (129, 700, 9, 9, torch.float64, 1e-9),       # one row past a tile; 2T + 2 = 20 factors
+    (64, 64, 1, 1, torch.float64, 1e-9),         # a single tile, 4 factors
+    (16, 300, 2, 1, torch.float64, 1e-9),        # 6 factors padded to 8
+    (1000, 1500, 40, 8, torch.float32, 1e-5),
+    (777, 4093, 25, 10, torch.float32, 1e-5)])
+def test_cost_and_target_gradients_match_oracle(n, m, T, k, k_dtype, tol):
+    """dL/dC (dense, one FP64 product over the 2T + 2 stored factors) and
+    dL/dy against the oracle's adjoint, with grad_loss = -1.75."""
+    prob = workloads.grad(n=n, m=m, max_iter=T)
+    say(f"cost gradient {k_dtype} n={n} m={m} T={T} k={k}")
+    ref, ga0, gb0, gx0, G0, gy0 = _oracle_grads(prob, T, full=True)
+    res, ga, gb, gx, G, gy = _gpu_grads(prob, T, k, k_dtype, full=True, scale=-1.75)
+    for name, g, r in (("a", ga, ga0), ("b", gb, gb0), ("x", gx, gx0), ("C", G, G0), ("y", gy, gy0)):
+        e = _norm_err(g, -1.75 * r)
+        say(f"  grad_{name}: {e:.3e}")
+        assert e <= tol, name
+    # the cost gradient's rows sum to the same values the point gradient uses
+    assert _norm_err(2.0 * (prob.x * G.sum(1)[:, None] - G @ prob.y), gx) <= 10 * tol
+
+
+def test_cost_gradient_is_pinned_by_point_gradient_without_cost_grad():
+    """grad_a, grad_b and grad_x do not change when the factors are also stored."""
+    prob = workloads.grad(n=500, m=640, max_iter=12)
+    r1 = _gpu_grads(prob, 12, 4, torch.float32)
+    r2 = _gpu_grads(prob, 12, 4, torch.float32, full=True)
+    for g1, g2 in zip(r1[1:4], r2[1:4]):
+        assert np.array_equal(g1, g2)
+
+
+def test_autograd_cost_and_target_points():
+    prob = workloads.grad(n=300, m=260, max_iter=20)
+    x = to_dev(prob.x).requires_grad_(True)
+    y = to_dev(prob.y).requires_grad_(True)
+    a = to_dev(prob.a)
+    b = to_dev(prob.b)
+    L = uot.uot_loss(x, y, a, b, prob.eps, prob.tau, 20, checkpoint_every=5, k_dtype=torch.float64)
+    (0.5 * L).backward()
+    _, _, _, gx, G, gy = _gpu_grads(prob, 20, 5, torch.float64, full=True)
+    np.testing.assert_allclose(x.grad.cpu().numpy(), 0.5 * gx, rtol=1e-14, atol=0)
+    np.testing.assert_allclose(y.grad.cpu().numpy(), 0.5 * gy, rtol=1e-14, atol=0)
+    C = uot.cost_from_points(to_dev(prob.x), to_dev(prob.y)).requires_grad_(True)
+    a2 = to_dev(prob.a).requires_grad_(True)
+    L2 = uot.uot_loss_cost(C, a2, b, prob.eps, prob.tau, 20, checkpoint_every=5, k_dtype=torch.float64)
+    (0.5 * L2).backward()
+    assert float(L2) == float(L)
+    np.testing.assert_allclose(C.grad.cpu().numpy(), 0.5 * G, rtol=1e-14, atol=0)
+
+
 def test_backward_full_size_against_oracle():
     """Differentiation workload at full size: 8192^2 FP32, 500 iterations,
-    checkpoints every 50, against the oracle's adjoint run at full size."""
+    checkpoints every 50, against the oracle's adjoint run at full size
+    (every gradient, the dense dL/dC included)."""
     prob = workloads.grad()
     say("full-size backward: oracle adjoint on the host ...")
-    ref, ga0, gb0, gx0 = _oracle_grads(prob, prob.max_iter)
+    ref, ga0, gb0, gx0, G0, gy0 = _oracle_grads(prob, prob.max_iter, full=True)
     say("  GPU ...")
-    res, ga, gb, gx = _gpu_grads(prob, prob.max_iter, prob.checkpoint_every, torch.float32)
-    for name, g, r in (("a", ga, ga0), ("b", gb, gb0), ("x", gx, gx0)):
+    res, ga, gb, gx, G, gy = _gpu_grads(prob, prob.max_iter, prob.checkpoint_every, torch.float32, full=True)
+    for name, g, r in (("a", ga, ga0), ("b", gb, gb0), ("x", gx, gx0), ("C", G, G0), ("y", gy, gy0)):
         e = _norm_err(g, r)
         say(f"  grad_{name}: {e:.3e}")
         assert e <= 1e-5, name
