@@ -52,6 +52,9 @@ def parse():
     p.add_argument("--no-multi", action="store_true", help="skip the multi-right-hand-side timing")
     p.add_argument("--no-precision", action="store_true", help="skip the low-precision timing")
     p.add_argument("--only", default="", help="comma list of sections to run alone (profiling)")
+    p.add_argument("--cpu-leg", type=int, default=0, help=argparse.SUPPRESS)
+    p.add_argument("--cpu-rows", type=int, default=0, help=argparse.SUPPRESS)
+    p.add_argument("--cpu-reps", type=int, default=1, help=argparse.SUPPRESS)
     p.add_argument("--calib-copy", action="store_true",
                    help="only run a plain device copy of known size (counter calibration)")
     return p.parse_args()
@@ -84,6 +87,9 @@ def traffic_from_counters():
 
 def main():
     args = parse()
+    if args.cpu_leg > 0:
+        cpu_leg(args.cpu_leg, args.cpu_rows, args.cpu_reps)
+        return
     if args.gpus != 1:
         sys.exit("bench.py measures one GPU (--gpus 1): this path runs on a single MI355X; "
                  "a run over several GPUs is not built")
@@ -386,12 +392,14 @@ def precision(uot, workloads, torch, dev, args):
     a = torch.from_numpy(prob.a).to(dev)
     b = torch.from_numpy(prob.b).to(dev)
     out = {"workload": f"precision: {prob.n}x{prob.m}, 16-D normal points, eps={prob.eps}, tau={prob.tau}, "
-                       f"{prob.max_iter} iterations, absorption at |log| > 30 checked every 10"}
+                       f"{prob.max_iter} iterations, absorption at |log| > 30 checked every 10 iterations "
+                       "(FP8: every 2)"}
+    ref = _load_precision_ref(prob)
     for name, dt, eb in (("f32", torch.float32, 4), ("bf16", torch.bfloat16, 2), ("fp8", torch.float8_e4m3fn, 1)):
         e0, e1 = _events(torch)
         e0.record()
         r = uot.sinkhorn(a, b, None, C=C, k_dtype=dt, eps=prob.eps, tau=prob.tau, max_iter=prob.max_iter,
-                         absorb_log_threshold=30.0, check_every=10, profile=True)
+                         absorb_log_threshold=30.0, check_every=2 if name == "fp8" else 10, profile=True)
         e1.record()
         torch.cuda.synchronize()
         info = r.info()
@@ -401,30 +409,114 @@ def precision(uot, workloads, torch, dev, args):
         out[name] = {"ms_per_solve": round(ms, 2), "iters_per_s": round(prob.max_iter / (ms * 1e-3), 1),
                      "pass_us": round(pass_us, 2), "pass_tb_s": round(prob.n * prob.m * eb / (pass_us * 1e-6) / 1e12, 3),
                      "absorptions": info["absorptions"], "flags": info["flags"]}
+        if ref is not None:
+            out[name]["err_vs_oracle"] = _precision_errors(r.f.cpu().numpy(), r.g.cpu().numpy(),
+                                                           float(r.loss.cpu()), ref, prob.eps)
+    if ref is None:
+        out["err_vs_oracle"] = f"missing {PRECISION_REF}"
     return out
 
 
-def cpu_baseline(prob):
-    """FP64 oracle on the host cores: kernel built once (untimed), then a
-    short run of T1 iterations and a run of T2 iterations sized to about
-    10 s; the rate is (T2 - T1) / (d2 - d1), which cancels per-call setup."""
+PRECISION_REF = os.path.join(ROOT, "tests", "golden", "precision_65536x8192_fp64.npz")
+
+
+def _load_precision_ref(prob):
+    """The FP64 oracle's result at the precision workload's full size, stored
+    by tests/golden/make_precision_reference.py."""
+    import numpy as np
+    if not os.path.exists(PRECISION_REF):
+        return None
+    z = np.load(PRECISION_REF)
+    if int(z["n"]) != prob.n or int(z["m"]) != prob.m or int(z["iters"]) != prob.max_iter:
+        return None
+    return {k: z[k] for k in z.files}
+
+
+def _precision_errors(f, g, loss, ref, eps):
+    """u, v errors from the potentials (entrywise max |u/u_ref - 1|, and
+    normwise ||U - U_ref|| / ||U_ref|| with U scaled by its largest entry)
+    and the relative loss error."""
+    import numpy as np
+    out = {}
+    for name, x, x0 in (("u", f, ref["f"]), ("v", g, ref["g"])):
+        d = np.expm1((x - x0) / eps)
+        w = np.exp((x0 - x0.max()) / eps)
+        out[name + "_entrywise"] = float(f"{np.max(np.abs(d)):.3e}")
+        out[name + "_normwise"] = float(f"{np.linalg.norm(d * w) / np.linalg.norm(w):.3e}")
+    L0 = float(ref["loss"])
+    out["loss"] = float(f"{abs(loss - L0) / abs(L0):.3e}")
+    return out
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_leg(threads: int, rows: int, reps: int) -> None:
+    """Child process of cpu_baseline: the FP64 oracle on the headline recipe
+    with ``rows`` source points and ``threads`` OpenMP threads bound to
+    cores; prints the per-run rates (iterations/s of that sample) as JSON."""
     import oracle
+    import workloads
+    prob = workloads.headline(n=rows)
     C = oracle.cost_points(prob.x, prob.y, prob.cost_kind, prob.normalize_max)
     K = oracle.kernel(C, prob.eps)
     del C
     T1 = 2
-    a0 = time.perf_counter()
-    oracle.sinkhorn(K, prob.a, prob.b, prob.eps, prob.tau, T1)
-    d1 = time.perf_counter() - a0
-    T2 = T1 + max(10, int(10.0 / max(d1 / T1, 1e-3)))
-    b0 = time.perf_counter()
-    oracle.sinkhorn(K, prob.a, prob.b, prob.eps, prob.tau, T2)
-    d2 = time.perf_counter() - b0
-    rate = (T2 - T1) / (d2 - d1)
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    rates = []
+    for _ in range(reps):
+        a0 = time.perf_counter()
+        oracle.sinkhorn(K, prob.a, prob.b, prob.eps, prob.tau, T1)
+        d1 = time.perf_counter() - a0
+        T2 = T1 + max(5, int(3.0 / max(d1 / T1, 1e-3)))
+        b0 = time.perf_counter()
+        oracle.sinkhorn(K, prob.a, prob.b, prob.eps, prob.tau, T2)
+        d2 = time.perf_counter() - b0
+        rates.append((T2 - T1) / (d2 - d1))
+    print(json.dumps({"rates": rates, "T2": T2}), flush=True)
+
+
+def cpu_baseline(prob):
+    """FP64 oracle on the host cores, in child processes (OpenMP threads
+    bound one per core, OMP_PROC_BIND=close, OMP_PLACES=cores): the headline
+    workload at full size on every core this process may run on (median of
+    3 runs), and on one core at 2048 x 16384 (the same recipe with 1/8 of
+    the rows; the rate is scaled to the full size).  Each run times T1 and T2
+    iterations of the plain loop, kernel built beforehand, and takes
+    (T2 - T1) / (time2 - time1), which cancels per-call setup."""
+    import statistics
+    import subprocess
+    avail = len(os.sched_getaffinity(0))
+    cores = min(avail, int(os.environ.get("OMP_NUM_THREADS", avail)))
+
+    def leg(threads, rows, reps):
+        env = dict(os.environ, OMP_NUM_THREADS=str(threads), OMP_PROC_BIND="close", OMP_PLACES="cores")
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-leg", str(threads), "--cpu-rows",
+                            str(rows), "--cpu-reps", str(reps)], env=env, capture_output=True, text=True,
+                           timeout=600)
+        if r.returncode != 0:
+            raise RuntimeError(f"cpu leg failed: {r.stderr[-2000:]}")
+        return json.loads(r.stdout.strip().splitlines()[-1])
+
+    t0 = time.perf_counter()
+    multi = leg(cores, prob.n, 3)
+    one = leg(1, 2048, 1)
+    wall = time.perf_counter() - t0
+    rate = statistics.median(multi["rates"])
+    rate1 = one["rates"][0] * 2048 / prob.n
     return {"value": round(rate, 3), "unit": "iters/s", "cores": cores, "kind": "oracle",
-            "sample": f"headline workload at full size ({prob.n}x{prob.m}, FP64 K), {T2}-iteration run minus "
-                      f"{T1}-iteration run (kernel build excluded); wall {d1 + d2:.1f} s"}
+            "runs": [round(x, 3) for x in multi["rates"]], "one_core_value": round(rate1, 4),
+            "cpu_model": _cpu_model(), "omp": "OMP_PROC_BIND=close OMP_PLACES=cores",
+            "sample": f"headline workload at full size ({prob.n}x{prob.m}, FP64 K): median of 3 runs, each a "
+                      f"{multi['T2']}-iteration run minus a 2-iteration run (kernel build excluded); one core: "
+                      f"2048 x {prob.m}, {one['T2']} minus 2 iterations, scaled by 2048/{prob.n}; wall {wall:.1f} s"}
 
 
 if __name__ == "__main__":

@@ -77,7 +77,7 @@ def _load():
         lib.orc_sinkhorn_absorbed.argtypes = [_dp, _dp, _dp, _i64, _i64, ctypes.c_double,
                                               ctypes.c_double, _i64, ctypes.c_double, _i64,
                                               ctypes.c_int, ctypes.c_double, _dp, _dp, _dp, _dp,
-                                              _dp, ctypes.POINTER(_i64), _dp]
+                                              _dp, ctypes.POINTER(_i64), _dp, _dp]
         lib.orc_sinkhorn_absorbed.restype = _i64
         lib.orc_grad_target_sqeuclid.argtypes = [_dp, _dp, _dp, _i64, _i64, _i64, _dp]
         lib.orc_grad_target_sqeuclid.restype = None
@@ -285,13 +285,15 @@ class AbsorbedResult:
     loss: float
     absorptions: int
     checks: np.ndarray     # compared maximum |log| at each check (0 elsewhere)
+    arms: np.ndarray       # level it was compared against (0 elsewhere)
 
 
 def sinkhorn_absorbed(C, a, b, eps: float, tau: float, max_iter: int, threshold: float,
                       check_every: int = 1, storage: Optional[str] = None,
                       store_scale: float = 1.0) -> AbsorbedResult:
     """Absorbed iteration with row- and column-normalised kernel, optionally
-    held in a narrow storage format (``None``, ``"f32"``, ``"bf16"`` or ``"e4m3"``)."""
+    held in a narrow storage format (``None``, ``"f32"``, ``"bf16"`` or
+    ``"e4m3"``); see orc_sinkhorn_absorbed for the absorption level."""
     C = _f64(C)
     a = _f64(a)
     b = _f64(b)
@@ -303,13 +305,14 @@ def sinkhorn_absorbed(C, a, b, eps: float, tau: float, max_iter: int, threshold:
     loss = ctypes.c_double(0.0)
     nabs = _i64(0)
     checks = np.zeros(max(int(max_iter), 1))
+    arms = np.zeros(max(int(max_iter), 1))
     kind = 0 if storage is None else _STORAGE_KINDS[storage]
     _load().orc_sinkhorn_absorbed(_p(C), _p(a), _p(b), n, m, float(eps), float(tau), int(max_iter),
                                   float(threshold), int(check_every), kind, float(store_scale),
                                   _p(f), _p(g), _p(r), _p(c), ctypes.byref(loss), ctypes.byref(nabs),
-                                  _p(checks))
+                                  _p(checks), _p(arms))
     return AbsorbedResult(f=f, g=g, r=r, c=c, loss=float(loss.value), absorptions=int(nabs.value),
-                          checks=checks[:max_iter])
+                          checks=checks[:max_iter], arms=arms[:max_iter])
 
 
 def fi_exponent(eps: float, tau: float) -> float:

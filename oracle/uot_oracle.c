@@ -598,23 +598,31 @@ ORC_EXPORT void orc_round_storage(const double* x, int64_t count, int kind, doub
  *     divided back by store_scale; 3: binary32), see orc_round_storage.
  * Start: u = v = 1, f = g = 0, then normalise.  After iteration t (t =
  * check_every, 2 check_every, ... and t < max_iter) the largest of
- * |log u_i|, |log v_j| (over positive entries) is compared with threshold;
- * above it, v is absorbed (g += eps log v, v = 1) and the kernel is
- * normalised and rebuilt (u does not need absorbing: the next half-step
- * recomputes it against the new f).
+ * |log u_i|, |log v_j| (over positive entries) is compared with a level,
+ * initially the threshold; above it, v is absorbed (g += eps log v, v = 1)
+ * and the kernel is normalised and rebuilt (u does not need absorbing: the
+ * next half-step recomputes it against the new f).  The normalisation puts
+ * part of the scalings back (what a kernel whose rows and columns all peak
+ * at 1 cannot carry); the largest |log| right after the rebuild (that
+ * residue) sets the next level: the threshold, or when the residue exceeds
+ * it the residue plus half the threshold, at most 60 (unless the threshold
+ * is larger), so a residue that absorption cannot remove does not trigger a
+ * rebuild at every check.
  * Outputs: f_tot, g_tot = f + eps log u, g + eps log v (-inf where the
  * scaling is 0); r = u * (Kt v), c = v * (Kt^T u) for the final scalings
  * (the plan's marginals, with the stored kernel); *loss the objective from
  * those (the identity form of orc_loss_identity on log scalings);
- * *absorptions the count; checks (optional, length max_iter) the compared
- * maximum at each check (0 elsewhere).  Returns iterations.
+ * *absorptions the count; checks and arms (optional, length max_iter) the
+ * compared maximum and the level at each check (0 elsewhere).  Returns
+ * iterations.
  */
 ORC_EXPORT int64_t orc_sinkhorn_absorbed(const double* C, const double* a, const double* b,
                                          int64_t n, int64_t m, double eps, double tau,
                                          int64_t max_iter, double threshold, int64_t check_every,
                                          int kind, double store_scale,
                                          double* f_tot, double* g_tot, double* r, double* c,
-                                         double* loss, int64_t* absorptions, double* checks) {
+                                         double* loss, int64_t* absorptions, double* checks,
+                                         double* arms) {
     double fi = orc_fi(eps, tau);
     double* Kt = (double*)malloc(sizeof(double) * (size_t)(n * m));
     double* f = (double*)malloc(sizeof(double) * (size_t)n);
@@ -626,7 +634,9 @@ ORC_EXPORT int64_t orc_sinkhorn_absorbed(const double* C, const double* a, const
     for (int64_t i = 0; i < n; ++i) { f[i] = 0.0; u[i] = 1.0; }
     for (int64_t j = 0; j < m; ++j) { g[j] = 0.0; v[j] = 1.0; }
     if (checks) for (int64_t t = 0; t < max_iter; ++t) checks[t] = 0.0;
+    if (arms) for (int64_t t = 0; t < max_iter; ++t) arms[t] = 0.0;
     int64_t nabs = 0;
+    double arm = threshold;      /* level a check compares against */
     for (int64_t t = 0; t <= max_iter; ++t) {
         int rebuild = (t == 0);
         if (t > 0 && threshold > 0.0 && t % check_every == 0 && t < max_iter) {
@@ -634,9 +644,10 @@ ORC_EXPORT int64_t orc_sinkhorn_absorbed(const double* C, const double* a, const
             for (int64_t i = 0; i < n; ++i) if (u[i] > 0.0 && fabs(log(u[i])) > mx) mx = fabs(log(u[i]));
             for (int64_t j = 0; j < m; ++j) if (v[j] > 0.0 && fabs(log(v[j])) > mx) mx = fabs(log(v[j]));
             if (checks) checks[t - 1] = mx;
-            if (mx > threshold) {
+            if (arms) arms[t - 1] = arm;
+            if (mx > arm) {
                 for (int64_t j = 0; j < m; ++j) if (v[j] > 0.0) { g[j] += eps * log(v[j]); v[j] = 1.0; }
-                rebuild = 1;
+                rebuild = 2;
                 ++nabs;
             }
         }
@@ -653,6 +664,17 @@ ORC_EXPORT int64_t orc_sinkhorn_absorbed(const double* C, const double* a, const
                 for (int64_t i = 0; i < n; ++i) if (C[i * m + j] - f[i] < mn) mn = C[i * m + j] - f[i];
                 if (v[j] > 0.0) v[j] = exp(log(v[j]) + (g[j] - mn) / eps);
                 g[j] = mn;
+            }
+            if (rebuild == 2) {
+                double res = 0.0;
+                for (int64_t i = 0; i < n; ++i) if (u[i] > 0.0 && fabs(log(u[i])) > res) res = fabs(log(u[i]));
+                for (int64_t j = 0; j < m; ++j) if (v[j] > 0.0 && fabs(log(v[j])) > res) res = fabs(log(v[j]));
+                if (!(res > threshold)) {
+                    arm = threshold;
+                } else {
+                    arm = res + 0.5 * threshold < 60.0 ? res + 0.5 * threshold : 60.0;
+                    if (arm < threshold) arm = threshold;
+                }
             }
             orc_kernel(C, n, m, eps, f, g, Kt);
             if (kind == 1 || kind == 3) {

@@ -57,40 +57,71 @@ int elem_size(int dt) {
     }
 }
 
-// Pinned host word used to read the stop flag (allocated once per process).
-std::once_flag g_pinned_once;
-uint32_t* g_pinned = nullptr;
-hipError_t g_pinned_err = hipSuccess;
+// Pinned host words through which the host reads the stop flag and the
+// absorption maxima.  Each call that reads them takes a slot of its own from
+// a pool (grown on demand, kept for the process) and returns it when it
+// ends, so concurrent calls on different streams or threads never share one.
+struct PinnedSlot {
+    uint32_t* p = nullptr;   // 64 bytes: flag word at 0, two doubles at byte 16
+    uint32_t* flag() const { return p; }
+    double* vals() const { return (double*)(p + 4); }
+};
+std::mutex g_pin_mu;
+std::vector<uint32_t*> g_pin_free;
 
-uint32_t* pinned_flag() {
-    std::call_once(g_pinned_once, [] {
-        g_pinned_err = hipHostMalloc((void**)&g_pinned, 64, hipHostMallocDefault);
-        if (g_pinned_err != hipSuccess) g_pinned = nullptr;
-    });
-    return g_pinned;
+hipError_t pinned_acquire(PinnedSlot& s) {
+    {
+        std::lock_guard<std::mutex> lk(g_pin_mu);
+        if (!g_pin_free.empty()) {
+            s.p = g_pin_free.back();
+            g_pin_free.pop_back();
+            return hipSuccess;
+        }
+    }
+    return hipHostMalloc((void**)&s.p, 64, hipHostMallocDefault);
 }
 
-// Two doubles of the same pinned allocation, for the absorption check.
-double* pinned_vals() {
-    uint32_t* p = pinned_flag();
-    return p ? (double*)(p + 4) : nullptr;
+void pinned_release(PinnedSlot& s) {
+    if (!s.p) return;
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    g_pin_free.push_back(s.p);
+    s.p = nullptr;
 }
 
-// Event pool for profiled runs (grown on demand, kept for the process).
+struct PinnedGuard {
+    PinnedSlot slot;
+    ~PinnedGuard() { pinned_release(slot); }
+};
+
+// Events of profiled runs: taken from a pool per call and returned at its end.
 std::mutex g_ev_mu;
-std::vector<hipEvent_t> g_events;
+std::vector<hipEvent_t> g_ev_free;
 
-hipError_t events(size_t count, std::vector<hipEvent_t>& out) {
-    std::lock_guard<std::mutex> lk(g_ev_mu);
-    while (g_events.size() < count) {
+hipError_t events_acquire(size_t count, std::vector<hipEvent_t>& out) {
+    out.clear();
+    {
+        std::lock_guard<std::mutex> lk(g_ev_mu);
+        while (out.size() < count && !g_ev_free.empty()) {
+            out.push_back(g_ev_free.back());
+            g_ev_free.pop_back();
+        }
+    }
+    while (out.size() < count) {
         hipEvent_t e;
         hipError_t err = hipEventCreate(&e);
         if (err != hipSuccess) return err;
-        g_events.push_back(e);
+        out.push_back(e);
     }
-    out.assign(g_events.begin(), g_events.begin() + count);
     return hipSuccess;
 }
+
+struct EventGuard {
+    std::vector<hipEvent_t> ev;
+    ~EventGuard() {
+        std::lock_guard<std::mutex> lk(g_ev_mu);
+        g_ev_free.insert(g_ev_free.end(), ev.begin(), ev.end());
+    }
+};
 
 // Scratch of the no-allocation entry point (uot_sinkhorn_noalloc): one copy
 // per GPU, held until the process ends, shared by every such call on that
@@ -255,6 +286,14 @@ uot_status make_plan(const uot_problem* p, const uot_options* o, Plan& P) {
     }
     if (target > p->n) target = p->n;
     P.rows_per_wg = (p->n + target - 1) / target;
+    // A strip's loads use 32-bit byte offsets from its first row, including
+    // the rows prefetched past its end.
+    {
+        const int64_t ldk_eff = p->K ? p->ldk : round_up(p->m, 64);
+        if ((P.rows_per_wg + 16) * ldk_eff * elem_size(p->k_dtype) >= (int64_t)1 << 31)
+            return fail(UOT_ERR_UNSUPPORTED, "a strip of %lld rows with ldk=%lld spans 2 GiB or more",
+                        (long long)P.rows_per_wg, (long long)ldk_eff);
+    }
     P.G = (int32_t)((p->n + P.rows_per_wg - 1) / P.rows_per_wg);
     if (P.persistent) {
         P.fin_cols = (int32_t)round_up((p->m + P.G - 1) / P.G, 4);
@@ -291,6 +330,16 @@ uot_status make_plan(const uot_problem* p, const uot_options* o, Plan& P) {
 
 double fi_of(double eps, double tau) { return isinf(tau) ? 1.0 : tau / (tau + eps); }
 
+// Level of the absorption check after a rebuild that left the residue `res`
+// (max |log u|, |log v|): the threshold, or res plus half the threshold when
+// the residue is beyond it, never above kAbsorbCeiling (unless the threshold
+// itself is).
+constexpr double kAbsorbCeiling = 60.0;
+double absorb_level(double res, double thr) {
+    if (!(res > thr)) return thr;
+    return std::max(thr, std::min(res + 0.5 * thr, kAbsorbCeiling));
+}
+
 // no_sync: never wait on the stream (the caller may not allow it): with
 // tol > 0 every iteration up to max_iter is enqueued and the launches after
 // the stop return at once; absorption, which decides on the host, is refused.
@@ -306,11 +355,9 @@ uot_status run_sinkhorn(const uot_problem* p, const uot_options* o, const uot_ou
     if (!aligned(ws, kAlign)) return fail(UOT_ERR_ALIGN, "workspace must be 256-byte aligned");
     if (no_sync && (P.stab || prof))
         return fail(UOT_ERR_UNSUPPORTED, "absorption and profiling wait on the stream");
-    uint32_t* flag_host = nullptr;
-    if (o->tol > 0.0 && !no_sync) {
-        flag_host = pinned_flag();
-        if (!flag_host) return hip_fail(g_pinned_err, "hipHostMalloc");
-    }
+    PinnedGuard pin;
+    if ((o->tol > 0.0 && !no_sync) || P.stab) UOT_HIP(pinned_acquire(pin.slot), "hipHostMalloc");
+    uint32_t* flag_host = (o->tol > 0.0 && !no_sync) ? pin.slot.flag() : nullptr;
 
     char* base = (char*)ws;
     Ctrl* ctrl = (Ctrl*)(base + P.off_ctrl);
@@ -354,6 +401,7 @@ uot_status run_sinkhorn(const uot_problem* p, const uot_options* o, const uot_ou
     const double fi = fi_of(p->eps, p->tau);
     UOT_HIP(launch_init(su, p->n, o->u0, sv, p->m, o->v0, cprev, ctrl, stream), "init");
     int32_t absorptions = 0;
+    double arm = o->absorb_log_threshold;   // level the absorption check compares against
     double* host_vals = nullptr;
     if (P.stab) {
         // g = 0 (zeroed through the init kernel's cprev path is not available: reuse it on g)
@@ -361,8 +409,7 @@ uot_status run_sinkhorn(const uot_problem* p, const uot_options* o, const uot_ou
         UOT_HIP(launch_rebuild(p->C, p->ldc, p->n, p->m, p->eps, fpot, gpot, su, sv, gmin_scratch, p->k_dtype,
                                (void*)K, ldk, store_scale, 1, stream),
                 "kernel rebuild");
-        host_vals = pinned_vals();
-        if (!host_vals) return hip_fail(g_pinned_err, "hipHostMalloc");
+        host_vals = pin.slot.vals();
     }
     // Checkpoint slot c holds v and K^T u after iteration c*k (slot 0: the start v).
     const int ck = o->checkpoint_every;
@@ -426,14 +473,15 @@ uot_status run_sinkhorn(const uot_problem* p, const uot_options* o, const uot_ou
     // exactly as without profiling.
     constexpr int kProfileStride = 8;
     enum { K_FUSED = 0, K_ROW = 1, K_COL = 2, K_FIN = 3 };
-    std::vector<hipEvent_t> ev;
+    EventGuard evg;
+    std::vector<hipEvent_t>& ev = evg.ev;
     std::vector<int> ev_kind;
     const int per_iter = fused ? 2 : 3;
     size_t evi = 0;
     if (prof) {
         memset(prof, 0, sizeof(*prof));
         size_t sampled = (size_t)(o->max_iter + kProfileStride - 1) / kProfileStride + 1;
-        UOT_HIP(events(2 * per_iter * sampled + 2, ev), "hipEventCreate");
+        UOT_HIP(events_acquire(2 * per_iter * sampled + 2, ev), "hipEventCreate");
         UOT_HIP(hipEventRecord(ev[evi++], stream), "hipEventRecord");
     }
     bool sample = false;
@@ -482,18 +530,29 @@ uot_status run_sinkhorn(const uot_problem* p, const uot_options* o, const uot_ou
         UOT_HIP(timed(K_FIN, [&] { return launch_finalize(F, stream); }), "column finalize");
         iters_run = t + 1;
         if (P.stab && (t + 1) % check_every == 0 && t + 1 < o->max_iter) {
-            // Absorb when a scaling's log leaves [-threshold, threshold]: v goes
-            // into g, then f and Kt are rebuilt from C (u keeps its total).
+            // Absorb when a scaling's log leaves [-threshold, threshold] (above
+            // the current level): v goes into g, then f and Kt are rebuilt from C
+            // (u keeps its total).
             UOT_HIP(launch_absorb_check(su, p->n, sv, p->m, absorb_vals, stream), "absorb check");
             UOT_HIP(hipMemcpyAsync(host_vals, absorb_vals, 2 * sizeof(double), hipMemcpyDeviceToHost, stream),
                     "absorb copy");
             UOT_HIP(hipStreamSynchronize(stream), "absorb sync");
-            if (host_vals[0] > o->absorb_log_threshold || host_vals[1] > o->absorb_log_threshold) {
+            if (std::max(host_vals[0], host_vals[1]) > arm) {
                 UOT_HIP(launch_absorb_apply(sv, gpot, p->m, p->eps, stream), "absorb");
                 UOT_HIP(launch_rebuild(p->C, p->ldc, p->n, p->m, p->eps, fpot, gpot, su, sv, gmin_scratch,
                                        p->k_dtype, (void*)K, ldk, store_scale, 0, stream),
                         "kernel rebuild");
                 ++absorptions;
+                // What the normalisation puts back (every row and column of Kt
+                // at maximum 1) cannot be absorbed: when that residue is beyond
+                // the threshold, the next absorption waits until the scalings
+                // grow by half a threshold more (at most to kAbsorbCeiling,
+                // inside the FP32 range of the passes' lane products).
+                UOT_HIP(launch_absorb_check(su, p->n, sv, p->m, absorb_vals, stream), "absorb check");
+                UOT_HIP(hipMemcpyAsync(host_vals, absorb_vals, 2 * sizeof(double), hipMemcpyDeviceToHost, stream),
+                        "absorb copy");
+                UOT_HIP(hipStreamSynchronize(stream), "absorb sync");
+                arm = absorb_level(std::max(host_vals[0], host_vals[1]), o->absorb_log_threshold);
             }
         }
         if (ck > 0 && (t + 1) % ck == 0 && t + 1 < o->max_iter) {

@@ -129,7 +129,7 @@ struct BatchSolve {
 #pragma unroll
             for (int c = 0; c < NCM; ++c)
                 buf[Q][r][c] = __builtin_bit_cast(
-                    Raw, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)voff[c], (int)soff, 2));
+                    Raw, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)(voff[c] + soff), 0, 2));
         }
     }
 

@@ -22,6 +22,8 @@
 // last row and the chunks of lanes beyond column m read as zeros without a
 // branch.  Per-row inputs (a, or u) are staged in LDS before the loop so
 // that no global load is waited on between prefetch and use.
+#include <mutex>
+
 #include "strip.h"
 
 namespace uot {
@@ -223,17 +225,33 @@ int pass_shape_count() { return kNumShapes; }
 PassShape pass_shape(int idx) { return kShapes[idx]; }
 
 // Launch one instantiation; raises its dynamic-LDS limit first when the
-// request exceeds the default 64 KiB (once per size increase).
+// request exceeds the default 64 KiB (once per device and size increase; the
+// attribute belongs to the device the call runs on).
 // With `resident` set, nothing is launched: *resident receives how many
 // workgroups of this instantiation fit on one CU with `lds` bytes of LDS.
 template <typename KT, typename AT, int WG, int NC, int D, bool VLDS, int MODE, int RB>
 static hipError_t launch_one(const PassLaunch& L, size_t lds, hipStream_t stream, int* resident) {
-    static size_t raised = 65536;
+    constexpr int kDevs = 64;
+    static std::mutex mu;
+    static size_t raised[kDevs];
     auto fn = pass_kernel<KT, AT, WG, NC, D, VLDS, MODE, RB>;
-    if (lds > raised) {
-        hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (lds > 65536) {
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
         if (e != hipSuccess) return e;
-        raised = lds;
+        bool need = true;
+        if (dev >= 0 && dev < kDevs) {
+            std::lock_guard<std::mutex> lk(mu);
+            need = lds > raised[dev];
+        }
+        if (need) {
+            e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+            if (dev >= 0 && dev < kDevs) {
+                std::lock_guard<std::mutex> lk(mu);
+                if (lds > raised[dev]) raised[dev] = lds;
+            }
+        }
     }
     if (resident) return hipOccupancyMaxActiveBlocksPerMultiprocessor(resident, (const void*)fn, WG, lds);
     hipLaunchKernelGGL(fn, dim3(L.grid), dim3(WG), lds, stream, L);

@@ -55,6 +55,9 @@ struct Strip {
         row_bytes = (uint32_t)(L.ldk * (int64_t)sizeof(KT));
         // Buffer resource over the strip: loads past its last row and the
         // chunks of lanes beyond column m (offset set to the strip size) read 0.
+        // The row offset is part of the lane offset, so the range check
+        // covers it; the host keeps (rows + 16) row_bytes below 2^31, so the
+        // sum never wraps.
         const uint32_t strip_bytes = (uint32_t)((int64_t)nrows * L.ldk * (int64_t)sizeof(KT));
         const KT* strip = (const KT*)L.K + r0 * L.ldk;
         rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)strip, (short)0, (int)strip_bytes, kBufferWord3);
@@ -76,7 +79,7 @@ struct Strip {
 #pragma unroll
         for (int c = 0; c < NC; ++c)
             buf[Q][c] = __builtin_bit_cast(
-                Raw, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)voff[c], (int)soff, kLoadAux));
+                Raw, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)(voff[c] + soff), 0, kLoadAux));
     }
 
     // Rows kb RB + r of batch kb into buffers Q RB + r.
@@ -88,7 +91,7 @@ struct Strip {
 #pragma unroll
             for (int c = 0; c < NC; ++c)
                 buf[Q * RB + r][c] = __builtin_bit_cast(
-                    Raw, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)voff[c], (int)soff, kLoadAux));
+                    Raw, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)(voff[c] + soff), 0, kLoadAux));
         }
     }
 
@@ -339,8 +342,9 @@ __device__ __forceinline__ void stage_rows(const PassLaunch& L, int64_t r0, int 
 // v (FP64) into LDS as AT.  Each lane issues its kStageV loads before the
 // first wait (a loop that waited on each load in turn would put that many L2
 // round trips in front of the workgroup's first row).  The loads go through a
-// buffer resource over v: one lane offset plus a per-load scalar offset, and
-// entries j >= m read as 0.  Requires 8 m < 2^31 (v fits in LDS here).
+// buffer resource over v (entries j >= m read as 0; the whole offset is the
+// lane's, so the range check covers it).  Requires 8 m < 2^31 (v fits in LDS
+// here).
 constexpr int kStageV = 16;
 
 template <int V, int NT, typename AT>
@@ -352,7 +356,7 @@ __device__ __forceinline__ void stage_v(const double* v, int64_t m, AT* vl) {
         double x[kStageV];
 #pragma unroll
         for (int q = 0; q < kStageV; ++q)
-            x[q] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(vr, j0 * 8, q * nt * 8, 0));
+            x[q] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(vr, (j0 + q * nt) * 8, 0, 0));
 #pragma unroll
         for (int q = 0; q < kStageV; ++q) {
             const int j = j0 + q * nt;

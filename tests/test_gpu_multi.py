@@ -131,19 +131,21 @@ def test_multi_argument_errors():
     assert e.value.status == 1
 
 
-def test_multi_full_size_sampled():
-    """8192 x 8192 cosine kernel, 256 pairs, 200 iterations, BF16 K: every
-    pair finite with flags 0; 4 sampled pairs against the oracle on the same
-    stored kernel (BF16 form bar)."""
+@pytest.mark.parametrize("kind,dtype,bar", [("bf16", torch.bfloat16, 2e-4), ("f32", torch.float32, 2e-6)])
+def test_multi_full_size_sampled(kind, dtype, bar):
+    """8192 x 8192 cosine kernel, 256 pairs, 200 iterations, BF16 and FP32
+    K (the launch shapes the benchmark times): every pair finite with flags
+    0; 4 sampled pairs against the oracle on the same stored kernel (each
+    form's bar)."""
     base, A, B = workloads.multi_rhs()
     A, B = A.T.copy(), B.T.copy()
-    say("  kernel on the host ...")
+    say(f"  {kind} kernel on the host ...")
     C = oracle.cost_points(base.x, base.y, base.cost_kind)
-    Kr, Kd = _stored(C, base.eps, "bf16", torch.bfloat16)
+    Kr, Kd = _stored(C, base.eps, kind, dtype)
     del C
     say("  solving 256 pairs ...")
     res = uot.sinkhorn_multi(Kd, to_dev(A), to_dev(B), m=base.m, eps=base.eps, tau=base.tau, max_iter=200)
     torch.cuda.synchronize()
     assert res.info()["flags"] == 0
     assert torch.isfinite(res.U).all() and torch.isfinite(res.V).all() and torch.isfinite(res.loss).all()
-    _compare(res, Kr, A, B, base.eps, base.tau, 200, [0, 77, 128, 255], 2e-4, "full size")
+    _compare(res, Kr, A, B, base.eps, base.tau, 200, [0, 77, 128, 255], bar, f"full size {kind}")

@@ -301,3 +301,50 @@ def test_persistent_headline_full_size():
         res, _ = gpu_solve(prob, k_dtype=torch.float32, persistent=True, tune=tune)
         assert res.info()["flags"] == 0
         compare(res, ref, 1e-6, 1e-6, f"persistent headline T=10 tune={tune}")
+
+
+def test_headline_full_size_tolerance_stop_against_oracle():
+    """The headline configuration's own stopping rule at full size: 16384^2
+    FP32 K, tol 1e-6 on the relative change of the column marginal, checked
+    every iteration; the oracle runs the same rule at full size.  Same
+    iteration count, and u, v, loss within 1e-6."""
+    prob = workloads.headline(max_iter=2000, tol=1e-6)
+    say("headline 16384^2, tol 1e-6: oracle on the host ...")
+    ref = _oracle(prob)
+    say(f"  oracle stopped after {ref.iters} iterations (err {ref.err:.3e}); GPU ...")
+    assert 10 < ref.iters < 2000
+    res, _ = gpu_solve(prob, k_dtype=torch.float32)
+    info = res.info()
+    say(f"  GPU stopped after {info['iters']} iterations (err {info['err']:.3e})")
+    assert info["iters"] == ref.iters and info["flags"] == 0
+    compare(res, ref, 1e-6, 1e-6, "headline tol stop")
+
+
+@pytest.mark.parametrize("dtype,m", [(torch.float32, 16381), (torch.float32, 8000), (torch.bfloat16, 8000),
+                                     (torch.float8_e4m3fn, 8000), (torch.float64, 3001)])
+def test_rows_past_the_last_row_read_zero(dtype, m):
+    """K given as the first n rows of a larger allocation whose further rows
+    are NaN: the last strip's prefetched rows (and a partial row batch) lie
+    past row n and must read as 0, so the result equals the one with K
+    alone, bit for bit.  Every read stays inside the allocation."""
+    n = 1001
+    prob = workloads.precision(n=n, m=m, max_iter=12)
+    prob.eps = 0.1            # every entry of exp(-C/eps) >= e^-10: no FP8 row flushes to 0
+    C = gpu_cost(prob)
+    K = uot.kernel_from_cost(C, prob.eps, dtype)
+    ldk = K.shape[1]
+    big = torch.empty((n + 64, ldk), dtype=dtype, device="cuda")
+    big[:n] = K
+    if dtype == torch.float8_e4m3fn:
+        big[n:].view(torch.uint8).fill_(0x7F)          # E4M3FN NaN
+    else:
+        big[n:] = float("nan")
+    a, b = to_dev(prob.a), to_dev(prob.b)
+    say(f"rows past the end: {dtype} n={n} m={m}")
+    r0 = uot.sinkhorn(a, b, K, m=m, eps=prob.eps, tau=prob.tau, max_iter=12)
+    r1 = uot.sinkhorn(a, b, big[:n], m=m, eps=prob.eps, tau=prob.tau, max_iter=12)
+    torch.cuda.synchronize()
+    assert r1.info()["flags"] == 0
+    for x, y in ((r0.u, r1.u), (r0.v, r1.v), (r0.r, r1.r), (r0.c, r1.c)):
+        assert torch.equal(x, y)
+    assert float(r0.loss) == float(r1.loss) and math.isfinite(float(r1.loss))

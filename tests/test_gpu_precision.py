@@ -17,6 +17,7 @@ Errors of u, v are computed from the potentials f = eps log u so that they
 stay meaningful where u itself overflows: entrywise |expm1((f - f_ref)/eps)|;
 normwise ||U - U_ref||_2 / ||U_ref||_2 with U = exp((f - max f_ref)/eps)."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -126,6 +127,12 @@ def _gpu_absorbed(prob, dtype, check_every=1, thr=30.0, C=None):
     return res
 
 
+def _decision_margin(res) -> float:
+    """Smallest |max |log| - level| over the oracle's absorption checks."""
+    at = res.arms > 0
+    return float(np.min(np.abs(res.checks[at] - res.arms[at]))) if np.any(at) else math.inf
+
+
 def _pot_errors(f, g, f0, g0, eps):
     """(entrywise max u, entrywise max v, normwise u, normwise v)."""
     du = np.expm1((f - f0) / eps)
@@ -150,8 +157,8 @@ def test_absorbed_iteration_against_oracle(dtype):
     C = oracle.cost_points(prob.x, prob.y, 0, True)
     kind, scale = STORE[dtype]
     same = oracle.sinkhorn_absorbed(C, prob.a, prob.b, prob.eps, prob.tau, prob.max_iter, 30.0, 1, kind, scale)
-    # the schedule is decided far enough from the threshold for FP32 sums
-    assert np.min(np.abs(same.checks - 30.0)) > 1e-3
+    # the schedule is decided far enough from the compared level for FP32 sums
+    assert _decision_margin(same) > 1e-3
     res = _gpu_absorbed(prob, dtype)
     info = res.info()
     f, g = res.f.cpu().numpy(), res.g.cpu().numpy()
@@ -185,15 +192,95 @@ def test_absorption_schedule_does_not_change_fp64_result():
     prob = workloads.precision(n=1024, m=512, max_iter=120)
     ref, _, _ = oracle.solve_problem(prob)
     f0, g0 = prob.eps * np.log(ref.u), prob.eps * np.log(ref.v)
+    C = oracle.cost_points(prob.x, prob.y, 0, True)
     counts = []
     for ce, thr in ((1, 30.0), (7, 30.0), (1, 5.0), (3, 1e9)):
         res = _gpu_absorbed(prob, torch.float64, check_every=ce, thr=thr)
         eu, ev, _, _ = _pot_errors(res.f.cpu().numpy(), res.g.cpu().numpy(), f0, g0, prob.eps)
         el = abs(float(res.loss.cpu()) - ref.loss) / abs(ref.loss)
         counts.append(res.info()["absorptions"])
-        say(f"  check_every={ce} thr={thr}: {eu:.2e} {ev:.2e} {el:.2e} abs={counts[-1]}")
+        same = oracle.sinkhorn_absorbed(C, prob.a, prob.b, prob.eps, prob.tau, prob.max_iter, thr, ce)
+        say(f"  check_every={ce} thr={thr}: {eu:.2e} {ev:.2e} {el:.2e} abs={counts[-1]} "
+            f"(oracle {same.absorptions}, margin {_decision_margin(same):.2e})")
         assert eu <= 1e-10 and ev <= 1e-10 and el <= 1e-10
-    assert counts[2] == 119 and counts[3] == 0 and 0 < counts[0] < 119
+        if _decision_margin(same) > 1e-6:
+            assert counts[-1] == same.absorptions
+    assert counts[3] == 0 and counts[0] >= 1 and counts[2] > counts[0]
+
+
+@pytest.mark.parametrize("m", [3000, 8192, 9000])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16, torch.float8_e4m3fn])
+def test_absorbed_rebuild_paths_same_storage(dtype, m):
+    """The normalised kernel build at the column counts of each rebuild
+    kernel: row and column minima in one read of C with 4 (m = 3000) or 8
+    (m = 8192, the precision workload's width) columns per lane, and
+    separate row and column minima (m = 9000); then 6 iterations of the
+    absorbed passes on it (no absorption yet: the level is out of reach, so
+    the stored kernel comes from C alone and matches the oracle's bit for
+    bit).  Against the oracle on the same storage at each form's parity bar."""
+    if dtype == torch.float64 and m > 8192:
+        pytest.skip("FP64 rows hold at most 8192 columns")
+    prob = workloads.precision(n=1000, m=m, max_iter=6)
+    C = oracle.cost_points(prob.x, prob.y, 0, True)
+    kind, scale = STORE[dtype]
+    same = oracle.sinkhorn_absorbed(C, prob.a, prob.b, prob.eps, prob.tau, prob.max_iter, 1e9, 1, kind, scale)
+    res = _gpu_absorbed(prob, dtype, check_every=1, thr=1e9)
+    info = res.info()
+    f, g = res.f.cpu().numpy(), res.g.cpu().numpy()
+    eu, ev, _, _ = _pot_errors(f, g, same.f, same.g, prob.eps)
+    el = abs(float(res.loss.cpu()) - same.loss) / abs(same.loss)
+    say(f"rebuild path {dtype} n=1000 m={m}: u {eu:.3e} v {ev:.3e} loss {el:.3e} (largest |log| "
+        f"{same.checks.max():.1f})")
+    assert info["iters"] == 6 and info["flags"] == 0 and info["absorptions"] == 0
+    bar = ABSORBED_PARITY[dtype]
+    assert eu <= bar and ev <= bar and el <= bar
+    np.testing.assert_allclose(res.r.cpu().numpy(), same.r, rtol=bar, atol=0)
+    np.testing.assert_allclose(res.c.cpu().numpy(), same.c, rtol=bar, atol=0)
+
+
+@pytest.mark.parametrize("m", [3000, 8192, 9000])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16, torch.float8_e4m3fn])
+def test_absorbed_iteration_with_rebuilds(dtype, m):
+    """200 iterations with absorption (level 30, checked every iteration)
+    at the three rebuild paths' column counts.  FP64 and FP32: against the
+    oracle on the same storage and schedule (same absorption count) and
+    against the plain FP64 iteration.  BF16, FP8: after an absorption the
+    potentials carry the GPU's FP32 rounding, so a few stored entries may
+    round to the neighbouring code and the same-storage comparison is only
+    as tight as one storage rounding; held instead to the storage bar against
+    the plain FP64 iteration (BF16: 2e-3 normwise on u, v and the loss; FP8:
+    finite, reported)."""
+    if dtype == torch.float64 and m > 8192:
+        pytest.skip("FP64 rows hold at most 8192 columns")
+    prob = workloads.precision(n=1000, m=m, max_iter=200)
+    C = oracle.cost_points(prob.x, prob.y, 0, True)
+    kind, scale = STORE[dtype]
+    same = oracle.sinkhorn_absorbed(C, prob.a, prob.b, prob.eps, prob.tau, prob.max_iter, 30.0, 1, kind, scale)
+    res = _gpu_absorbed(prob, dtype, check_every=1)
+    info = res.info()
+    f, g = res.f.cpu().numpy(), res.g.cpu().numpy()
+    assert info["iters"] == 200 and info["flags"] == 0 and info["absorptions"] >= 1
+    if _decision_margin(same) > 1e-3:
+        assert info["absorptions"] == same.absorptions
+    # the plain FP64 iteration (textbook stabilised form, its own absorption rule)
+    f0, g0, _ = oracle.sinkhorn_stabilized(C, prob.a, prob.b, prob.eps, prob.tau, prob.max_iter, 30.0)
+    r0, c0 = oracle.potential_marginals(C, f0, g0, prob.eps)
+    L0 = oracle.loss_potentials(f0, g0, r0, c0, prob.a, prob.b, prob.eps, prob.tau)
+    eu, ev, nu, nv = _pot_errors(f, g, f0, g0, prob.eps)
+    el = abs(float(res.loss.cpu()) - L0) / abs(L0)
+    say(f"absorbed {dtype} n=1000 m={m}: absorptions {info['absorptions']} (oracle {same.absorptions}); vs plain "
+        f"FP64: entrywise u {eu:.3e} v {ev:.3e}, normwise u {nu:.3e} v {nv:.3e}, loss {el:.3e}")
+    if dtype in (torch.float64, torch.float32):
+        bar = ABSORBED_PARITY[dtype]
+        su, sv, _, _ = _pot_errors(f, g, same.f, same.g, prob.eps)
+        sl = abs(float(res.loss.cpu()) - same.loss) / abs(same.loss)
+        assert su <= bar and sv <= bar and sl <= bar
+        tol = 1e-10 if dtype == torch.float64 else 2e-5
+        assert eu <= tol and ev <= tol and el <= tol
+    elif dtype == torch.bfloat16:
+        assert max(nu, nv, el) <= 2e-3
+    else:
+        assert np.all(np.isfinite(f)) and np.all(np.isfinite(g)) and math.isfinite(el)
 
 
 def test_absorption_needs_cost():
@@ -206,57 +293,48 @@ def test_absorption_needs_cost():
     assert e.value.status == 1
 
 
-def _cost_max(x, y, rows=4096):
-    mx = 0.0
-    for i in range(0, x.shape[0], rows):
-        mx = max(mx, float(oracle.cost_points(x[i:i + rows], y, 0, False).max()))
-    return mx
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "precision_65536x8192_fp64.npz")
+
+
+def precision_reference():
+    """FP64 oracle result of the precision workload at full size, written by
+    tests/golden/make_precision_reference.py (oracle only)."""
+    z = np.load(GOLDEN)
+    return {k: z[k] for k in z.files}
 
 
 def test_precision_full_size():
     """65536 x 8192, eps 1e-3, threshold 30, 2000 iterations, checks every
-    10.  The oracle is not run at this size; instead (a) the plan's
-    marginals returned with each stored kernel are checked, on sampled rows
-    and columns, against the exact FP64 kernel at the returned potentials:
-    every stored entry is within a relative u_fmt of the exact one (u_fmt =
-    2^-24, 2^-8 for FP32, BF16; entries below the format's normal range
-    excepted), so each marginal is too, up to FP32 arithmetic; (b) BF16 and
-    FP8 are compared with the FP32-K run on the same GPU."""
+    10, K stored in FP32, BF16 and FP8, against the FP64 oracle's result at
+    the same size (stabilised FP64 iteration, stored under tests/golden).
+    Bars: FP32 1e-6 on the loss and, on u and v entry by entry, the stored
+    kernel's own bound 2 fi/(1 - fi) 2^-24 = 1.2e-5 (one rounding of each
+    entry, amplified by the fixed point at fi = 0.990); BF16 2e-3 normwise
+    on u, v and on the loss (entrywise reported); FP8 reported.  FP8 checks
+    the scalings every 2 iterations (its truncated kernel moves them by up to
+    ~7 log units per iteration, and the passes' FP32 lane products hold
+    |log| < 88); it must not absorb far more often than FP32 (a rebuild that
+    the normalisation undoes is not repeated)."""
+    ref = precision_reference()
     prob = workloads.precision()
+    assert int(ref["n"]) == prob.n and int(ref["m"]) == prob.m and int(ref["iters"]) == prob.max_iter
     Cd = uot.cost_from_points(to_dev(prob.x), to_dev(prob.y), prob.cost_kind, prob.normalize_max)
-    say("  cost maximum on the host ...")
-    cmax = _cost_max(prob.x, prob.y)
-    rng = np.random.default_rng(5)
-    rows = np.sort(rng.choice(prob.n, 48, replace=False))
-    cols = np.sort(rng.choice(prob.m, 48, replace=False))
-    Crow = oracle.cost_points(prob.x[rows], prob.y, 0, False) / cmax          # 48 x m
-    Ccol = oracle.cost_points(prob.x, prob.y[cols], 0, False) / cmax          # n x 48
-    runs = {}
+    counts = {}
     for dtype in (torch.float32, torch.bfloat16, torch.float8_e4m3fn):
         say(f"  full size {dtype} ...")
-        r = _gpu_absorbed(prob, dtype, check_every=10, C=Cd)
+        r = _gpu_absorbed(prob, dtype, check_every=2 if dtype == torch.float8_e4m3fn else 10, C=Cd)
         info = r.info()
-        runs[dtype] = r
-        f, g = r.f.cpu().numpy(), r.g.cpu().numpy()
-        # exact marginals at the returned potentials
-        r_ex = np.exp((f[rows, None] + g[None, :] - Crow) / prob.eps).sum(axis=1)
-        c_ex = np.exp((f[:, None] + g[None, cols] - Ccol) / prob.eps).sum(axis=0)
-        er = _rel(r.r.cpu().numpy()[rows], r_ex)
-        ec = _rel(r.c.cpu().numpy()[cols], c_ex)
-        say(f"    loss {float(r.loss.cpu()):.10e} absorptions {info['absorptions']} flags {info['flags']}; "
-            f"marginals vs exact kernel: rows {er:.3e} cols {ec:.3e}")
+        counts[dtype] = info["absorptions"]
+        eu, ev, nu, nv = _pot_errors(r.f.cpu().numpy(), r.g.cpu().numpy(), ref["f"], ref["g"], prob.eps)
+        el = abs(float(r.loss.cpu()) - float(ref["loss"])) / abs(float(ref["loss"]))
+        say(f"    vs FP64 oracle: entrywise u {eu:.3e} v {ev:.3e}; normwise u {nu:.3e} v {nv:.3e}; "
+            f"loss {el:.3e}; absorptions {info['absorptions']} flags {info['flags']}")
         assert info["flags"] == 0 and info["iters"] == 2000 and info["absorptions"] >= 1
-        if dtype != torch.float8_e4m3fn:
-            bound = UNIT_ROUNDOFF[dtype] + 1e-5
-            assert er <= bound and ec <= bound
-    f0 = runs[torch.float32].f.cpu().numpy()
-    g0 = runs[torch.float32].g.cpu().numpy()
-    L0 = float(runs[torch.float32].loss.cpu())
-    for dtype in (torch.bfloat16, torch.float8_e4m3fn):
-        r = runs[dtype]
-        eu, ev, nu, nv = _pot_errors(r.f.cpu().numpy(), r.g.cpu().numpy(), f0, g0, prob.eps)
-        el = abs(float(r.loss.cpu()) - L0) / abs(L0)
-        say(f"  {dtype} vs FP32 K: entrywise u {eu:.3e} v {ev:.3e}; normwise u {nu:.3e} v {nv:.3e}; "
-            f"loss {el:.3e}")
-        if dtype == torch.bfloat16:
+        if dtype == torch.float32:
+            fi = prob.tau / (prob.tau + prob.eps)
+            assert max(eu, ev) <= 2 * fi / (1 - fi) * 2.0 ** -24 and el <= 1e-6
+        elif dtype == torch.bfloat16:
             assert max(nu, nv, el) <= 2e-3
+        else:
+            assert np.isfinite(eu) and np.isfinite(ev) and np.isfinite(el)
+    assert counts[torch.float8_e4m3fn] <= 5 * counts[torch.float32] + 5

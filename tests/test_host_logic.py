@@ -159,3 +159,20 @@ def test_multi_and_plan_argument_checks_happen_on_the_host():
     assert L.uot_plan(ctypes.byref(q), None, None, None, None, _addr(22), 10, _lib.UOT_F64, None) == _lib.UOT_ERR_ARG
     assert L.uot_plan(ctypes.byref(q), _addr(20), _addr(21), None, None, _addr(22), 5, _lib.UOT_F64,
                       None) == _lib.UOT_ERR_ARG
+
+
+def test_strip_offsets_must_stay_below_2_gib():
+    """A strip's loads use 32-bit byte offsets from its first row: a caller
+    leading dimension that makes a strip (plus its prefetched rows) span
+    2 GiB is refused on the host instead of wrapping."""
+    L = _lib.lib()
+    opt = _lib.Options()
+    opt.max_iter, opt.check_every, opt.fused = 5, 1, 1
+    p = _problem(300, 100)
+    assert L.uot_sinkhorn_workspace_size(ctypes.byref(p), ctypes.byref(opt)) > 0
+    p.ldk = 1 << 26                       # 256 MiB per FP32 row
+    assert L.uot_sinkhorn_workspace_size(ctypes.byref(p), ctypes.byref(opt)) == 0
+    out = _outputs(0)
+    st = L.uot_sinkhorn(ctypes.byref(p), ctypes.byref(opt), ctypes.byref(out), ctypes.c_void_p(FAKE), 1 << 30, None)
+    assert st == _lib.UOT_ERR_UNSUPPORTED
+    assert b"2 GiB" in L.uot_last_error()
