@@ -462,17 +462,20 @@ hipError_t launch_adj_finish(const AdjFinish& F, hipStream_t stream) {
 // is one dense FP64 product with inner dimension 2T + 2 (a contraction: it
 // runs on the matrix cores, v_mfma_f64_16x16x4f64) and the kernel applied in
 // its epilogue.  Workgroup: 4 waves in 2 x 2 over a 128 x 128 output tile,
-// each wave 64 x 64 as 4 x 4 blocks of 16 x 16.  Fragment of a block
-// (16 rows x 4 slots): lane l holds Lf[s0 + l/16][i0 + l%16], read straight
-// from memory (four 128-byte runs per wave); the next 4 slots are in flight
-// while the 16 products of the current ones issue.  The inner dimension is
-// padded to a multiple of 4 with zero factors.  Output block: lane l holds
-// rows i0 + l/16 + 4 q, q < 4, of column j0 + l%16 (the FP64 form
+// each wave 64 x 64 as 4 x 4 blocks of 16 x 16.  The factors of 16 slots
+// (16 KiB of Lf and of Rf, each slot's 128 entries one contiguous 1 KiB run)
+// are staged through LDS, double buffered: the next slab's loads are in
+// flight while the 64 products of the current one issue, and one barrier
+// separates slabs.  Fragment of a block (16 rows x 4 slots): lane l holds
+// Lf[s0 + l/16][i0 + l%16].  Slots are padded to a multiple of 16 and rows to
+// multiples of 128 with zero factors (kGradcSlotPad, kGradcRowPad).  Output block: lane l
+// holds rows i0 + l/16 + 4 q, q < 4, of column j0 + l%16 (the FP64 form
 // interleaves its four result rows, unlike the FP32 16 x 16 forms).
 // ---------------------------------------------------------------------------
 typedef double f64x4_t __attribute__((ext_vector_type(4)));
 constexpr int GC_WG = 256;
-constexpr int GC_TILE = 128;
+constexpr int GC_TILE = kGradcRowPad;
+constexpr int GC_KS = kGradcSlotPad;    // slots per LDS slab
 
 int gradc_row_tiles(int64_t n) { return (int)((n + GC_TILE - 1) / GC_TILE); }
 
@@ -484,7 +487,7 @@ __global__ void fill_f64_kernel(double* p, int64_t count, double value) {
 hipError_t launch_fill_f64(double* p, int64_t count, double value, hipStream_t stream) {
     if (count <= 0) return hipSuccess;
     int64_t blocks = (count + 255) / 256;
-    if (blocks > 1024) blocks = 1024;
+    if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(fill_f64_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, p, count, value);
     return hipGetLastError();
 }
@@ -493,11 +496,14 @@ template <typename KT, int DIM>
 __global__ __launch_bounds__(GC_WG, 2) void gradc_kernel(GradCLaunch L) {
     constexpr int ND = 1 + DIM;
     __shared__ double red[2][ND][64];
+    __shared__ __align__(16) double As[2][GC_KS][GC_TILE];
+    __shared__ __align__(16) double Bs[2][GC_KS][GC_TILE];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int wi = wave >> 1, wj = wave & 1;
     const int64_t n = L.n, m = L.m;
+    const int64_t ldl = L.ldl, ldr = L.ldr;     // padded row lengths of Lf, Rf
     const int64_t tiles_j = (m + GC_TILE - 1) / GC_TILE;
     const int64_t tiles = tiles_j * ((n + GC_TILE - 1) / GC_TILE);
     // Workgroups go to the 8 XCDs in turn: give each XCD a contiguous run of
@@ -505,59 +511,63 @@ __global__ __launch_bounds__(GC_WG, 2) void gradc_kernel(GradCLaunch L) {
     int64_t b = blockIdx.x;
     if (tiles % 8 == 0) b = (b % 8) * (tiles / 8) + b / 8;
     const int64_t ti = b / tiles_j, tj = b % tiles_j;
-    const int64_t i0 = ti * GC_TILE + wi * 64;
-    const int64_t j0 = tj * GC_TILE + wj * 64;
+    const int64_t it0 = ti * GC_TILE, jt0 = tj * GC_TILE;
+    const int64_t i0 = it0 + wi * 64;
+    const int64_t j0 = jt0 + wj * 64;
     const int r16 = lane & 15, g4 = lane >> 4;
 
-    // Fragment addresses (rows and columns past the end read the last one;
-    // their results are never stored).
-    const double* pa[4];
-    const double* pb[4];
+    // Slab loads: thread t moves 8 consecutive factors (four 16-byte loads)
+    // of slot t/16 for Lf and for Rf.
+    const int ls = tid >> 4, lc = (tid & 15) * 8;
+    const double* ga = L.Lf + (int64_t)ls * ldl + it0 + lc;
+    const double* gb = L.Rf + (int64_t)ls * ldr + jt0 + lc;
+    f64x2 ra[4], rb[4];
+    auto fetch = [&](int64_t slab) {
+        const double* pa = ga + slab * GC_KS * ldl;
+        const double* pb = gb + slab * GC_KS * ldr;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        int64_t i = i0 + 16 * q + r16;
-        int64_t j = j0 + 16 * q + r16;
-        pa[q] = L.Lf + (int64_t)g4 * n + (i < n ? i : n - 1);
-        pb[q] = L.Rf + (int64_t)g4 * m + (j < m ? j : m - 1);
-    }
+        for (int q = 0; q < 4; ++q) {
+            ra[q] = *(const f64x2*)(pa + 2 * q);
+            rb[q] = *(const f64x2*)(pb + 2 * q);
+        }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            *(f64x2*)&As[buf][ls][lc + 2 * q] = ra[q];
+            *(f64x2*)&Bs[buf][ls][lc + 2 * q] = rb[q];
+        }
+    };
+
     f64x4_t acc[4][4];
 #pragma unroll
     for (int p = 0; p < 4; ++p)
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[p][q] = (f64x4_t){0.0, 0.0, 0.0, 0.0};
 
-    const int64_t steps = L.nterms / 4;     // nterms is padded to a multiple of 4
-    const int64_t sa = 4 * n, sb = 4 * m;
-    double a0[4], b0[4], a1[4], b1[4];
+    const int64_t slabs = L.nterms / GC_KS;     // nterms is padded to a multiple of GC_KS
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    for (int64_t sl = 0; sl < slabs; ++sl) {
+        const int buf = (int)(sl & 1);
+        if (sl + 1 < slabs) fetch(sl + 1);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        a0[q] = pa[q][0];
-        b0[q] = pb[q][0];
-    }
-    for (int64_t st = 0; st < steps; st += 2) {
-        const bool more1 = st + 1 < steps;
-        const bool more2 = st + 2 < steps;
-        const int64_t o1 = more1 ? (st + 1) : st;
+        for (int kk = 0; kk < GC_KS / 4; ++kk) {
+            double a[4], bv[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            a1[q] = pa[q][o1 * sa];
-            b1[q] = pb[q][o1 * sb];
+            for (int q = 0; q < 4; ++q) {
+                a[q] = As[buf][4 * kk + g4][wi * 64 + 16 * q + r16];
+                bv[q] = Bs[buf][4 * kk + g4][wj * 64 + 16 * q + r16];
+            }
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[p], bv[q], acc[p][q], 0, 0, 0);
         }
-#pragma unroll
-        for (int p = 0; p < 4; ++p)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[p], b0[q], acc[p][q], 0, 0, 0);
-        if (!more1) break;
-        const int64_t o2 = more2 ? (st + 2) : st + 1;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            a0[q] = pa[q][o2 * sa];
-            b0[q] = pb[q][o2 * sb];
-        }
-#pragma unroll
-        for (int p = 0; p < 4; ++p)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[p], b1[q], acc[p][q], 0, 0, 0);
+        if (sl + 1 < slabs) stash(buf ^ 1);
+        __syncthreads();
     }
 
     // Epilogue: G = scale K (.) acc; column sums of G and G x_i for the target gradient.
@@ -634,7 +644,9 @@ static hipError_t gradc_launch_t(const GradCLaunch& L, hipStream_t stream) {
 }
 
 hipError_t launch_gradc(const GradCLaunch& L, hipStream_t stream) {
-    if (L.nterms % 4 != 0 || L.nterms < 4) return hipErrorInvalidValue;
+    if (L.nterms % GC_KS != 0 || L.nterms < GC_KS || L.ldl % GC_TILE != 0 || L.ldr % GC_TILE != 0 ||
+        L.ldl < L.n || L.ldr < L.m)
+        return hipErrorInvalidValue;
     if (L.k_dtype == UOT_F32) return gradc_launch_t<float>(L, stream);
     if (L.k_dtype == UOT_F64) return gradc_launch_t<double>(L, stream);
     return hipErrorInvalidValue;

@@ -658,7 +658,8 @@ struct BwdPlan {
     int32_t dim;
     int k, nseg;
     bool cost_grad;           // store the factors of Kbar for dL/dC or dL/dy
-    int64_t nterms;           // 2T + 2, padded to a multiple of 4
+    int64_t nterms;           // 2T + 2, padded to a multiple of kGradcSlotPad
+    int64_t ldl, ldr;         // n and m padded to kGradcRowPad (factor row lengths)
     int32_t row_tiles;        // row tiles of the cost-gradient product
     size_t off_fwd, off_part, off_str, off_utr, off_wtr, off_vtr, off_useed, off_abar, off_gsum, off_gy,
         off_bbar, off_cbar, off_wfin, off_avec, off_lf, off_rf, off_ysum, total;
@@ -708,12 +709,14 @@ uot_status make_bwd_plan(const uot_problem* p, const uot_options* o, int64_t dim
     B.off_wfin = off; off = align_up(off + d8 * m, kAlign);
     B.off_avec = off; off = align_up(off + d8 * m, kAlign);
     B.cost_grad = cost_grad;
-    B.nterms = round_up(2 * (int64_t)o->max_iter + 2, 4);
+    B.nterms = round_up(2 * (int64_t)o->max_iter + 2, kGradcSlotPad);
+    B.ldl = round_up(n, kGradcRowPad);
+    B.ldr = round_up(m, kGradcRowPad);
     B.row_tiles = gradc_row_tiles(n);
     B.off_lf = B.off_rf = B.off_ysum = off;
     if (cost_grad) {
-        B.off_lf = off; off = align_up(off + d8 * (size_t)B.nterms * n, kAlign);
-        B.off_rf = off; off = align_up(off + d8 * (size_t)B.nterms * m, kAlign);
+        B.off_lf = off; off = align_up(off + d8 * (size_t)B.nterms * B.ldl, kAlign);
+        B.off_rf = off; off = align_up(off + d8 * (size_t)B.nterms * B.ldr, kAlign);
         B.off_ysum = off; off = align_up(off + d8 * (size_t)B.row_tiles * (1 + (dim > 0 ? dim : 0)) * m, kAlign);
     }
     B.total = off;
@@ -759,10 +762,11 @@ uot_status run_backward(const uot_problem* p, const uot_options* o, const double
     double* avec = (double*)(base + B.off_avec);
     double* Lf = cost_grad ? (double*)(base + B.off_lf) : nullptr;
     double* Rf = cost_grad ? (double*)(base + B.off_rf) : nullptr;
-    const int64_t used_terms = 2 * (int64_t)o->max_iter + 2;
-    if (cost_grad && B.nterms > used_terms) {
-        UOT_HIP(launch_fill_f64(Lf + used_terms * n, (B.nterms - used_terms) * n, 0.0, stream), "factor padding");
-        UOT_HIP(launch_fill_f64(Rf + used_terms * m, (B.nterms - used_terms) * m, 0.0, stream), "factor padding");
+    const int64_t ldl = B.ldl, ldr = B.ldr;
+    if (cost_grad) {
+        // padding slots and the rows past n (columns past m) hold zero factors
+        UOT_HIP(launch_fill_f64(Lf, B.nterms * ldl, 0.0, stream), "factor padding");
+        UOT_HIP(launch_fill_f64(Rf, B.nterms * ldr, 0.0, stream), "factor padding");
     }
     const void* K = p->K;
     int64_t ldk = p->ldk;
@@ -868,8 +872,8 @@ uot_status run_backward(const uot_problem* p, const uot_options* o, const double
         if (cost_grad) {
             // slot 0: (rbar u_T) v_T^T, slot 1: u_T (cbar v_T)^T
             S.st_q = Lf;
-            S.st_u = Lf + n;
-            S.st_a = Rf + m;
+            S.st_u = Lf + ldl;
+            S.st_a = Rf + ldr;
             S.st_b = Rf;
         }
         UOT_HIP(launch_adj(p->k_dtype, B.nc, ADJ_SEED, (int)dim, S, stream), "adjoint seed pass");
@@ -911,10 +915,10 @@ uot_status run_backward(const uot_problem* p, const uot_options* o, const double
             S.add_seed = (t == T) ? 1 : 0;
             if (cost_grad) {
                 // slot 2t: u_t wbar_t^T, slot 2t + 1: sbar_t v_{t-1}^T
-                S.st_u = Lf + (int64_t)(2 * t) * n;
-                S.st_q = Lf + (int64_t)(2 * t + 1) * n;
-                S.st_a = Rf + (int64_t)(2 * t) * m;
-                S.st_b = Rf + (int64_t)(2 * t + 1) * m;
+                S.st_u = Lf + (int64_t)(2 * t) * ldl;
+                S.st_q = Lf + (int64_t)(2 * t + 1) * ldl;
+                S.st_a = Rf + (int64_t)(2 * t) * ldr;
+                S.st_b = Rf + (int64_t)(2 * t + 1) * ldr;
             }
             UOT_HIP(launch_adj(p->k_dtype, B.nc, ADJ_STEP, (int)dim, S, stream), "adjoint step pass");
             if (t > 1) {
@@ -955,6 +959,8 @@ uot_status run_backward(const uot_problem* p, const uot_options* o, const double
         G.nterms = B.nterms;
         G.Lf = Lf;
         G.Rf = Rf;
+        G.ldl = ldl;
+        G.ldr = ldr;
         G.grad_loss = grad_loss;
         G.inv_eps = 1.0 / p->eps;
         G.G = grad_C;

@@ -396,14 +396,17 @@ hipError_t launch_adj_finish(const AdjFinish& F, hipStream_t stream);
 // a dense FP64 product on the matrix cores with the kernel applied in its
 // epilogue; optionally the per-row-tile column sums of G and G x_i that give
 // the target-point gradient.
+constexpr int kGradcSlotPad = 16;    // factor slots padded to a multiple of this (zero factors)
+constexpr int kGradcRowPad = 128;    // factor rows padded to a multiple of this (zero entries)
 struct GradCLaunch {
     const void* K;            // stored kernel (FP32 or FP64), k_scale 1
     int32_t k_dtype;
     int64_t ldk;
     int64_t n, m;
-    int64_t nterms;           // rank of Kbar (2T + 2)
-    const double* Lf;         // nterms x n
-    const double* Rf;         // nterms x m
+    int64_t nterms;           // rank of Kbar (2T + 2), padded to kGradcSlotPad
+    const double* Lf;         // nterms x ldl (ldl = n padded to kGradcRowPad)
+    const double* Rf;         // nterms x ldr
+    int64_t ldl, ldr;
     const double* grad_loss;  // device scalar
     double inv_eps;
     double* G;                // n x ldg, or NULL
