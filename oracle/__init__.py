@@ -79,6 +79,9 @@ def _load():
                                               ctypes.c_int, ctypes.c_double, _dp, _dp, _dp, _dp,
                                               _dp, ctypes.POINTER(_i64), _dp, _dp]
         lib.orc_sinkhorn_absorbed.restype = _i64
+        lib.orc_envelope_gradients.argtypes = [_dp, _dp, _dp, _dp, _dp, _i64, _i64, ctypes.c_double, _dp, _dp,
+                                               _dp]
+        lib.orc_envelope_gradients.restype = None
         lib.orc_grad_target_sqeuclid.argtypes = [_dp, _dp, _dp, _i64, _i64, _i64, _dp]
         lib.orc_grad_target_sqeuclid.restype = None
         lib.orc_potential_marginals.argtypes = [_dp, _dp, _dp, _i64, _i64, ctypes.c_double, _dp, _dp]
@@ -224,6 +227,19 @@ def adjoint(K, a, b, eps: float, tau: float, res: Result, want_G: bool = True):
                         _p(tr["v"]), _p(tr["s"]), _p(tr["u"]), _p(tr["w"]),
                         _p(ga), _p(gb), _p(G))
     return ga, gb, G
+
+
+def envelope_gradients(K, u, v, a, b, tau: float, want_P: bool = True):
+    """Implicit (envelope) gradients at the scalings (u, v): returns
+    (grad_a, grad_b, P) with dL/dC = P = diag(u) K diag(v) (None unless
+    want_P), dL/da = tau (1 - r/a), dL/db = tau (1 - c/b)."""
+    K, u, v, a, b = map(_f64, (K, u, v, a, b))
+    n, m = K.shape
+    ga = np.empty(n)
+    gb = np.empty(m)
+    P = np.empty((n, m)) if want_P else None
+    _load().orc_envelope_gradients(_p(K), _p(u), _p(v), _p(a), _p(b), n, m, float(tau), _p(ga), _p(gb), _p(P))
+    return ga, gb, P
 
 
 def grad_points_sqeuclid(G, x, y) -> np.ndarray:

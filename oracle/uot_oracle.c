@@ -481,6 +481,36 @@ ORC_EXPORT void orc_grad_target_sqeuclid(const double* G, const double* x, const
 }
 
 /* ------------------------------------------------------------------ */
+/* Envelope (implicit) gradients                                        */
+/* ------------------------------------------------------------------ */
+/* At the minimiser P* of the primal objective (entropic UOT, Section 2.1's
+ * scaling loop run to its fixed point) the derivative of the optimal value
+ * with respect to a parameter is the objective's partial derivative at
+ * fixed P = P* (the P-derivative vanishes there):
+ *   dL/dC_ij = P_ij,   dL/da_i = tau (1 - r_i/a_i),   dL/db_j = tau (1 - c_j/b_j)
+ * (the KL terms' derivatives in their second argument; 0 when tau = inf).
+ * Evaluated here at given scalings: P_ij = u_i K_ij v_j, r = P 1, c = P^T 1,
+ * so it equals the gradient of the returned objective only as far as (u, v)
+ * is a fixed point.  a_i, b_j > 0 required.  P may be NULL. */
+ORC_EXPORT void orc_envelope_gradients(const double* K, const double* u, const double* v, const double* a,
+                                       const double* b, int64_t n, int64_t m, double tau, double* grad_a,
+                                       double* grad_b, double* P) {
+    double* s = (double*)malloc(sizeof(double) * (size_t)n);
+    double* w = (double*)malloc(sizeof(double) * (size_t)m);
+    orc_Kv(K, v, n, m, s);
+    orc_KTu(K, u, n, m, w);
+    for (int64_t i = 0; i < n; ++i) grad_a[i] = isinf(tau) ? 0.0 : tau * (1.0 - u[i] * s[i] / a[i]);
+    for (int64_t j = 0; j < m; ++j) grad_b[j] = isinf(tau) ? 0.0 : tau * (1.0 - v[j] * w[j] / b[j]);
+    if (P) {
+        #pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = 0; j < m; ++j) P[i * m + j] = u[i] * K[i * m + j] * v[j];
+    }
+    free(s);
+    free(w);
+}
+
+/* ------------------------------------------------------------------ */
 /* Marginals and objective from potentials                              */
 /* ------------------------------------------------------------------ */
 

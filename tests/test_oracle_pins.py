@@ -307,6 +307,56 @@ def test_adjoint_envelope_at_convergence():
     np.testing.assert_allclose(gb, prob.tau * (1 - res.c / prob.b), rtol=0, atol=1e-9)
 
 
+def test_envelope_gradients_equal_unrolled_adjoint_at_convergence():
+    """The oracle's implicit gradients against its unrolled reverse mode
+    (pinned by finite differences) once the iterates have converged
+    (fi^(2T) ~ 1e-35 here), on a rectangular problem with both histograms
+    unnormalised; and the point gradients built from them."""
+    prob = workloads.random_small(13, 8, seed=41, eps=0.25, tau=0.7)
+    C, K = _problem_arrays(prob)
+    res = oracle.sinkhorn(K, prob.a, prob.b, prob.eps, prob.tau, 300, trace=True)
+    ga, gb, G = oracle.adjoint(K, prob.a, prob.b, prob.eps, prob.tau, res)
+    ea, eb, P = oracle.envelope_gradients(K, res.u, res.v, prob.a, prob.b, prob.tau)
+    np.testing.assert_allclose(P, G, rtol=1e-9, atol=1e-15)
+    np.testing.assert_allclose(ea, ga, rtol=0, atol=1e-10)
+    np.testing.assert_allclose(eb, gb, rtol=0, atol=1e-10)
+    # before convergence they differ: the envelope is not the unrolled gradient
+    res5 = oracle.sinkhorn(K, prob.a, prob.b, prob.eps, prob.tau, 2, trace=True)
+    ga5, _, G5 = oracle.adjoint(K, prob.a, prob.b, prob.eps, prob.tau, res5)
+    ea5, _, P5 = oracle.envelope_gradients(K, res5.u, res5.v, prob.a, prob.b, prob.tau)
+    assert np.max(np.abs(P5 - G5)) > 1e-6 and np.max(np.abs(ea5 - ga5)) > 1e-6
+
+
+def test_envelope_gradients_match_finite_differences_of_the_optimum():
+    """Central differences of the converged objective in a, b and the cost
+    (h = 1e-6 relative), against the envelope gradients."""
+    prob = workloads.random_small(6, 5, seed=43, eps=0.4, tau=0.9)
+    C, K = _problem_arrays(prob)
+    T = 400
+
+    def loss(a, b, C):
+        return oracle.sinkhorn(oracle.kernel(C, prob.eps), a, b, prob.eps, prob.tau, T).loss
+
+    res = oracle.sinkhorn(K, prob.a, prob.b, prob.eps, prob.tau, T)
+    ea, eb, P = oracle.envelope_gradients(K, res.u, res.v, prob.a, prob.b, prob.tau)
+    h = 1e-6
+    for i in (0, 3, 5):
+        da = np.zeros(6)
+        da[i] = h * prob.a[i]
+        fd = (loss(prob.a + da, prob.b, C) - loss(prob.a - da, prob.b, C)) / (2 * da[i])
+        assert fd == pytest.approx(ea[i], rel=1e-6, abs=1e-9)
+    for j in (1, 4):
+        db = np.zeros(5)
+        db[j] = h * prob.b[j]
+        fd = (loss(prob.a, prob.b + db, C) - loss(prob.a, prob.b - db, C)) / (2 * db[j])
+        assert fd == pytest.approx(eb[j], rel=1e-6, abs=1e-9)
+    for (i, j) in ((0, 0), (2, 3), (5, 4)):
+        dC = np.zeros_like(C)
+        dC[i, j] = h
+        fd = (loss(prob.a, prob.b, C + dC) - loss(prob.a, prob.b, C - dC)) / (2 * h)
+        assert fd == pytest.approx(P[i, j], rel=1e-5, abs=1e-11)
+
+
 # ---------------------------------------------------------------- P10: absorption
 def test_stabilized_equals_plain():
     prob = workloads.random_small(14, 10, seed=23, eps=0.02, tau=0.3)
