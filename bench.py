@@ -255,6 +255,21 @@ def fwd_bwd(uot, workloads, torch, dev, args):
         c_ms += e1.elapsed_time(e2)
         del gr
     c_ms /= reps
+    # implicit (envelope) gradients at the final scalings: no checkpoints
+    r = uot.sinkhorn(a, b, uot.kernel_from_cost(uot.cost_from_points(x, y), prob.eps, torch.float32), eps=prob.eps,
+                     tau=prob.tau, max_iter=prob.max_iter)
+    i_ms = 0.0
+    for _ in range(reps + 1):
+        e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(2))
+        e1.record()
+        gi = uot.sinkhorn_implicit_backward(r, g, x=x, y=y, want_C=False, want_y=True)
+        e2.record()
+        torch.cuda.synchronize()
+        i_ms = e1.elapsed_time(e2) if i_ms == 0.0 else min(i_ms, e1.elapsed_time(e2))
+    gu = uot.sinkhorn_backward(fwd(), g, x=x, y=y)
+    torch.cuda.synchronize()
+    imp_err = {k: float(f"{(torch.linalg.norm(getattr(gi, k) - getattr(gu, k)) / torch.linalg.norm(getattr(gu, k))).item():.3e}")
+               for k in ("grad_a", "grad_b", "grad_x")}
     kb = prob.n * prob.m * 4
     # forward: T passes; reverse: T recompute + T adjoint passes + 1 column + 1 seed pass
     passes = prob.max_iter * 3 + 3
@@ -262,6 +277,7 @@ def fwd_bwd(uot, workloads, torch, dev, args):
                         f"{prob.checkpoint_every}, gradients for x, a, b",
             "fwd_ms": round(f_ms, 3), "bwd_ms": round(b_ms, 3), "fwd_bwd_ms": round(f_ms + b_ms, 3),
             "bwd_with_cost_grad_ms": round(c_ms, 3),
+            "implicit_bwd_ms": round(i_ms, 3), "implicit_vs_unrolled_normwise": imp_err,
             "cost_grad_tflop_s": round(2.0 * prob.n * prob.m * (2 * prob.max_iter + 2) / ((c_ms - b_ms) * 1e-3) / 1e12, 2)
             if c_ms > b_ms else None,
             "k_passes": passes, "k_bytes_tb_s": round(passes * kb / ((f_ms + b_ms) * 1e-3) / 1e12, 3)}

@@ -324,6 +324,42 @@ uot_status uot_sinkhorn_backward(const uot_problem* prob, const uot_options* opt
                                  void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * Implicit (envelope) gradient of the objective at the scalings (u, v) of a
+ * converged uot_sinkhorn call: at the minimiser P of the objective its
+ * derivative in a parameter is the partial derivative at fixed P, so
+ *   dL/dC = P = diag(u) K diag(v),  dL/da = tau (1 - r/a),  dL/db = tau (1 - c/b),
+ *   dL/dx_i = 2 sum_j P_ij (x_i - y_j),  dL/dy_j = 2 sum_i P_ij (y_j - x_i)
+ * (r = P 1, c = P^T 1; the KL terms vanish for tau = inf).  This equals the
+ * gradient of the unrolled loop only as far as (u, v) has converged (the
+ * difference shrinks like fi^(2T)); it costs one marginal pass over K (r and
+ * c), plus one per point coordinate when x or y gradients are requested
+ * (K (v y_d) by rows and K^T (u x_d) by columns in the same pass), plus the
+ * dense write of dL/dC if requested -- instead of the 3T passes of the
+ * unrolled reverse sweep.  No checkpoints are needed.
+ *
+ *   prob, opt   the forward's problem (K of any dtype, or C to rebuild it)
+ *               and options (accum, tune; the loop options are ignored)
+ *   u, v        the forward's scalings (device, n and m; finite: not the
+ *               totals of an absorbed solve)
+ *   grad_loss   device scalar g; outputs are g times dL/d(input)
+ *   grad_a, grad_b        device n, m or NULL
+ *   grad_C      device n x ldgc FP64 or NULL (columns [m, ldgc) untouched)
+ *   x, y, dim   points of an un-normalised squared-Euclidean cost (dim 1..16)
+ *   grad_x, grad_y        device n x dim, m x dim or NULL
+ * Requirements: a, b > 0 where gradients are requested.
+ * Errors: UOT_ERR_ARG, UOT_ERR_DTYPE, UOT_ERR_ALIGN, UOT_ERR_WORKSPACE,
+ * UOT_ERR_UNSUPPORTED, UOT_ERR_HIP.  Workspace:
+ * uot_sinkhorn_implicit_backward_workspace_size bytes.
+ */
+size_t uot_sinkhorn_implicit_backward_workspace_size(const uot_problem* prob, const uot_options* opt, int64_t dim);
+uot_status uot_sinkhorn_implicit_backward(const uot_problem* prob, const uot_options* opt,
+                                          const double* u, const double* v, const double* grad_loss,
+                                          double* grad_a, double* grad_b, double* grad_C, int64_t ldgc,
+                                          const double* x, const double* y, int64_t dim,
+                                          double* grad_x, double* grad_y,
+                                          void* ws, size_t ws_bytes, void* stream);
+
+/*
  * Decode `count` stored kernel entries (a multiple of 16 bytes' worth) to
  * FP32 exactly as the streaming passes read them, times k_scale.  For
  * inspecting a stored K (e.g. checking the FP8 decoding).

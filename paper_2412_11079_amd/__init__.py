@@ -17,7 +17,7 @@ from . import _lib
 from ._lib import (UOT_ACC_F32, UOT_ACC_F64, UOT_BF16, UOT_COST_COSINE, UOT_COST_SQEUCLID, UOT_F32, UOT_F64,
                    UOT_FLAG_NONFINITE, UOT_FLAG_NOT_CONVERGED, UOT_FLAG_ZERO_SUM, UOT_FP8_E4M3, UOTError)
 
-__all__ = ["sinkhorn", "sinkhorn_backward", "Gradients", "UOTLoss", "UOTCostLoss", "uot_loss", "uot_loss_cost", "cost_from_points", "kernel_from_cost",
+__all__ = ["sinkhorn", "sinkhorn_backward", "sinkhorn_implicit_backward", "Gradients", "UOTLoss", "UOTCostLoss", "uot_loss", "uot_loss_cost", "cost_from_points", "kernel_from_cost",
            "kernel_to_f32", "sinkhorn_batched", "BatchedSolver", "BatchedResult", "plan", "sinkhorn_multi",
            "SinkhornResult", "UOTError", "lib_path",
            "UOT_F64", "UOT_F32", "UOT_BF16", "UOT_FP8_E4M3", "UOT_COST_SQEUCLID", "UOT_COST_COSINE"]
@@ -364,6 +364,50 @@ def sinkhorn_backward(res: SinkhornResult, grad_loss: torch.Tensor, *, x: Option
     return out
 
 
+def sinkhorn_implicit_backward(res: SinkhornResult, grad_loss: torch.Tensor, *, x: Optional[torch.Tensor] = None,
+                               y: Optional[torch.Tensor] = None, want_a: bool = True, want_b: bool = True,
+                               want_x: bool = True, want_C: bool = False, want_y: bool = False) -> Gradients:
+    """Implicit (envelope) gradients at the scalings of a converged
+    ``sinkhorn`` call (include/uot.h, uot_sinkhorn_implicit_backward): no
+    checkpoints, one marginal pass over K plus one per point coordinate."""
+    prob, opt = res._problem, res._options
+    device = res.u.device
+    n, m = res.u.shape[0], res.v.shape[0]
+    if opt.absorb_log_threshold > 0.0:
+        raise ValueError("the implicit gradient needs the scalings of a solve without absorption")
+    g = grad_loss.reshape(()).to(dtype=torch.float64, device=device).contiguous()
+    dim = 0
+    if y is not None:
+        if y.dtype != torch.float64 or y.dim() != 2 or y.shape[0] != m:
+            raise ValueError("y must be an (m, d) float64 tensor")
+        y = y.contiguous()
+        dim = y.shape[1]
+    if x is not None:
+        if y is None or x.dtype != torch.float64 or x.shape != (n, dim):
+            raise ValueError("x must be an (n, d) float64 tensor matching y")
+        x = x.contiguous()
+    if (want_y or (want_x and x is not None)) and (x is None or y is None):
+        raise ValueError("point gradients need x and y")
+    L = _lib.lib()
+    need = L.uot_sinkhorn_implicit_backward_workspace_size(ctypes.byref(prob), ctypes.byref(opt), dim)
+    if need == 0:
+        _lib.check(L.uot_sinkhorn_implicit_backward(ctypes.byref(prob), ctypes.byref(opt), None, None, None, None,
+                                                    None, None, 0, None, None, dim, None, None, None, 0, None))
+    ws = _workspace(need, device)
+    out = Gradients()
+    out.grad_a = torch.empty(n, dtype=torch.float64, device=device) if want_a else None
+    out.grad_b = torch.empty(m, dtype=torch.float64, device=device) if want_b else None
+    out.grad_x = torch.empty((n, dim), dtype=torch.float64, device=device) if (x is not None and want_x) else None
+    out.grad_y = torch.empty((m, dim), dtype=torch.float64, device=device) if (x is not None and want_y) else None
+    out.grad_C = torch.empty((n, m), dtype=torch.float64, device=device) if want_C else None
+    _lib.check(L.uot_sinkhorn_implicit_backward(ctypes.byref(prob), ctypes.byref(opt), _ptr(res.u), _ptr(res.v),
+                                                _ptr(g), _ptr(out.grad_a), _ptr(out.grad_b), _ptr(out.grad_C), m,
+                                                _ptr(x), _ptr(y), dim, _ptr(out.grad_x), _ptr(out.grad_y),
+                                                _ptr(ws), ws.numel(), _stream(device)))
+    out._keep = (ws, g, x, y, res)
+    return out
+
+
 class UOTLoss(torch.autograd.Function):
     """UOT objective of the unrolled loop on points, with gradients w.r.t. the
     source points x, the target points y and the histograms a and b.
@@ -375,15 +419,16 @@ class UOTLoss(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, x, y, a, b, eps: float, tau: float, max_iter: int, checkpoint_every: int = 50,
-                k_dtype: torch.dtype = torch.float32):
+                k_dtype: torch.dtype = torch.float32, implicit: bool = False):
         x64 = x.detach().to(torch.float64).contiguous()
         y64 = y.detach().to(torch.float64).contiguous()
         C = cost_from_points(x64, y64, UOT_COST_SQEUCLID, False)
         K = kernel_from_cost(C, eps, k_dtype)
         del C
         res = sinkhorn(a.detach().to(torch.float64).contiguous(), b.detach().to(torch.float64).contiguous(), K,
-                       eps=eps, tau=tau, max_iter=max_iter, checkpoint_every=checkpoint_every)
+                       eps=eps, tau=tau, max_iter=max_iter, checkpoint_every=0 if implicit else checkpoint_every)
         ctx.res = res
+        ctx.implicit = implicit
         ctx.save_for_backward(x64, y64)
         ctx.dtypes = (x.dtype, y.dtype, a.dtype, b.dtype)
         return res.loss.clone().to(x.dtype)
@@ -393,13 +438,13 @@ class UOTLoss(torch.autograd.Function):
         x64, y64 = ctx.saved_tensors
         need_x, need_y, need_a, need_b = ctx.needs_input_grad[:4]
         pts = need_x or need_y
-        gr = sinkhorn_backward(ctx.res, grad.detach().to(torch.float64), x=x64 if pts else None,
-                               y=y64 if pts else None, want_a=need_a, want_b=need_b, want_x=need_x,
-                               want_y=need_y)
+        fn = sinkhorn_implicit_backward if ctx.implicit else sinkhorn_backward
+        gr = fn(ctx.res, grad.detach().to(torch.float64), x=x64 if pts else None, y=y64 if pts else None,
+                want_a=need_a, want_b=need_b, want_x=need_x, want_y=need_y)
         xd, yd, ad, bd = ctx.dtypes
         cast = lambda t, d: t.to(d) if t is not None else None  # noqa: E731
         return (cast(gr.grad_x, xd), cast(gr.grad_y, yd), cast(gr.grad_a, ad), cast(gr.grad_b, bd),
-                None, None, None, None, None)
+                None, None, None, None, None, None)
 
 
 class UOTCostLoss(torch.autograd.Function):
@@ -428,9 +473,11 @@ class UOTCostLoss(torch.autograd.Function):
 
 
 def uot_loss(x, y, a, b, eps: float, tau: float, max_iter: int, checkpoint_every: int = 50,
-             k_dtype: torch.dtype = torch.float32) -> torch.Tensor:
-    """Differentiable UOT objective of two point clouds (see UOTLoss)."""
-    return UOTLoss.apply(x, y, a, b, eps, tau, max_iter, checkpoint_every, k_dtype)
+             k_dtype: torch.dtype = torch.float32, implicit: bool = False) -> torch.Tensor:
+    """Differentiable UOT objective of two point clouds (see UOTLoss);
+    ``implicit`` uses the envelope gradient at the final scalings (exact at
+    convergence, no checkpoints) instead of the unrolled reverse sweep."""
+    return UOTLoss.apply(x, y, a, b, eps, tau, max_iter, checkpoint_every, k_dtype, implicit)
 
 
 def uot_loss_cost(C, a, b, eps: float, tau: float, max_iter: int, checkpoint_every: int = 50,

@@ -72,6 +72,10 @@ SIGNATURES = {
     "uot_sinkhorn_backward_workspace_size": ([ctypes.POINTER(Problem), ctypes.POINTER(Options), _i64, _i32], _sz),
     "uot_sinkhorn_backward": ([ctypes.POINTER(Problem), ctypes.POINTER(Options), _vp, _vp, _vp, _vp, _vp, _vp,
                                _vp, _i64, _vp, _vp, _i64, _vp, _vp, _vp, _sz, _vp], _i32),
+    "uot_sinkhorn_implicit_backward_workspace_size": ([ctypes.POINTER(Problem), ctypes.POINTER(Options), _i64],
+                                                      _sz),
+    "uot_sinkhorn_implicit_backward": ([ctypes.POINTER(Problem), ctypes.POINTER(Options), _vp, _vp, _vp, _vp, _vp,
+                                        _vp, _i64, _vp, _vp, _i64, _vp, _vp, _vp, _sz, _vp], _i32),
     "uot_sinkhorn_batched_workspace_size": ([_i32], _sz),
     "uot_sinkhorn_batched": ([ctypes.POINTER(Problem), _i32, ctypes.POINTER(Options), ctypes.POINTER(Outputs), _vp,
                               _sz, _vp], _i32),

@@ -673,4 +673,56 @@ hipError_t launch_grady_finish(const double* ysum, int32_t tiles, const double* 
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Implicit (envelope) gradients from the marginal passes:
+//   s = K v, w = K^T u (one marginal pass),  sy_d = K (v y_d), wx_d = K^T (u x_d)
+//   (one marginal pass per point coordinate d), then
+//   grad_a = g tau (1 - u s / a), grad_b = g tau (1 - v w / b),
+//   grad_x_id = 2 g (x_id u_i s_i - u_i sy_d,i),  grad_y_jd = 2 g (y_jd v_j w_j - v_j wx_d,j).
+// ---------------------------------------------------------------------------
+__global__ void env_weight_kernel(const double* u, const double* x, int64_t n, const double* v, const double* y,
+                                  int64_t m, int32_t dim, int32_t d, double* ud, double* vd) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t i = t; i < n; i += stride) ud[i] = u[i] * x[i * dim + d];
+    for (int64_t j = t; j < m; j += stride) vd[j] = v[j] * y[j * dim + d];
+}
+
+hipError_t launch_env_weight(const double* u, const double* x, int64_t n, const double* v, const double* y, int64_t m,
+                             int32_t dim, int32_t d, double* ud, double* vd, hipStream_t stream) {
+    const int64_t mx = n > m ? n : m;
+    int blocks = (int)((mx + 255) / 256);
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(env_weight_kernel, dim3(blocks), dim3(256), 0, stream, u, x, n, v, y, m, dim, d, ud, vd);
+    return hipGetLastError();
+}
+
+__global__ void env_finish_kernel(EnvFinish F) {
+    const double g = *F.grad_loss;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t i = t; i < F.n; i += stride) {
+        const double r = F.u[i] * F.s[i];
+        if (F.grad_a) F.grad_a[i] = F.tau_inf ? 0.0 : g * F.tau * (1.0 - r / F.a[i]);
+        if (F.grad_x)
+            for (int d = 0; d < F.dim; ++d)
+                F.grad_x[i * F.dim + d] = 2.0 * g * (F.x[i * F.dim + d] * r - F.u[i] * F.sy[(int64_t)d * F.n + i]);
+    }
+    for (int64_t j = t; j < F.m; j += stride) {
+        const double c = F.v[j] * F.w[j];
+        if (F.grad_b) F.grad_b[j] = F.tau_inf ? 0.0 : g * F.tau * (1.0 - c / F.b[j]);
+        if (F.grad_y)
+            for (int d = 0; d < F.dim; ++d)
+                F.grad_y[j * F.dim + d] = 2.0 * g * (F.y[j * F.dim + d] * c - F.v[j] * F.wx[(int64_t)d * F.m + j]);
+    }
+}
+
+hipError_t launch_env_finish(const EnvFinish& F, hipStream_t stream) {
+    const int64_t mx = F.n > F.m ? F.n : F.m;
+    int blocks = (int)((mx + 255) / 256);
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(env_finish_kernel, dim3(blocks), dim3(256), 0, stream, F);
+    return hipGetLastError();
+}
+
 }  // namespace uot

@@ -977,6 +977,163 @@ uot_status run_backward(const uot_problem* p, const uot_options* o, const double
 
 
 // ---------------------------------------------------------------------------
+// Implicit (envelope) backward: marginal passes only
+// ---------------------------------------------------------------------------
+struct ImpPlan {
+    Plan F;                   // forward plan (the marginal passes)
+    size_t off_sy, off_wx, off_ud, off_vd, total;
+};
+
+uot_status make_imp_plan(const uot_problem* p, const uot_options* o, int64_t dim, ImpPlan& B) {
+    if (!o) return fail(UOT_ERR_ARG, "options must not be NULL");
+    uot_options fo = *o;
+    fo.fused = 1;
+    fo.persistent = 0;
+    fo.tol = 0.0;
+    fo.absorb_log_threshold = 0.0;
+    fo.checkpoint_every = 0;
+    fo.u0 = fo.v0 = nullptr;
+    fo.max_iter = 1;
+    uot_status st = make_plan(p, &fo, B.F);
+    if (st != UOT_OK) return st;
+    if (dim < 0 || dim > 16) return fail(UOT_ERR_UNSUPPORTED, "point dimension %lld (0 to 16)", (long long)dim);
+    const size_t d8 = sizeof(double);
+    size_t off = B.F.total;
+    B.off_sy = off; off = align_up(off + d8 * (size_t)(dim > 0 ? dim : 1) * p->n, kAlign);
+    B.off_wx = off; off = align_up(off + d8 * (size_t)(dim > 0 ? dim : 1) * p->m, kAlign);
+    B.off_ud = off; off = align_up(off + d8 * (size_t)p->n, kAlign);
+    B.off_vd = off; off = align_up(off + d8 * (size_t)p->m, kAlign);
+    B.total = off;
+    return UOT_OK;
+}
+
+uot_status run_implicit_backward(const uot_problem* p, const uot_options* o, const double* u, const double* v,
+                                 const double* grad_loss, double* grad_a, double* grad_b, double* grad_C,
+                                 int64_t ldgc, const double* x, const double* y, int64_t dim, double* grad_x,
+                                 double* grad_y, void* ws, size_t ws_bytes, hipStream_t stream) {
+    ImpPlan B;
+    uot_status st = make_imp_plan(p, o, dim, B);
+    if (st != UOT_OK) return st;
+    if (!u || !v || !grad_loss) return fail(UOT_ERR_ARG, "u, v and grad_loss are required");
+    if (!aligned(u, 8) || !aligned(v, 8)) return fail(UOT_ERR_ALIGN, "u and v must be 8-byte aligned");
+    if ((grad_x || grad_y) && (dim < 1 || !x || !y)) return fail(UOT_ERR_ARG, "point gradients need x, y and dim >= 1");
+    if (grad_C && ldgc < p->m) return fail(UOT_ERR_ARG, "ldgc (%lld) < m (%lld)", (long long)ldgc, (long long)p->m);
+    if ((grad_C && !aligned(grad_C, 8)) || (grad_x && !aligned(grad_x, 8)) || (grad_y && !aligned(grad_y, 8)))
+        return fail(UOT_ERR_ALIGN, "gradient outputs must be 8-byte aligned");
+    if (ws_bytes < B.total || !ws) return fail(UOT_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", B.total, ws_bytes);
+    if (!aligned(ws, kAlign)) return fail(UOT_ERR_ALIGN, "workspace must be 256-byte aligned");
+    const Plan& P = B.F;
+    const int64_t n = p->n, m = p->m;
+    char* base = (char*)ws;
+    Ctrl* ctrl = (Ctrl*)(base + P.off_ctrl);
+    double* sbuf = (double*)(base + P.off_s);
+    double* wbuf = (double*)(base + P.off_w);
+    double* bp = (double*)(base + P.off_bp);
+    void* part = base + P.off_part;
+    double* sy = (double*)(base + B.off_sy);
+    double* wx = (double*)(base + B.off_wx);
+    double* ud = (double*)(base + B.off_ud);
+    double* vd = (double*)(base + B.off_vd);
+    const void* K = p->K;
+    int64_t ldk = p->ldk;
+    const double store_scale = (p->k_dtype == UOT_FP8_E4M3) ? 448.0 : 1.0;
+    double k_scale = (p->K && p->k_scale > 0.0) ? p->k_scale : 1.0;
+    if (P.build_k) {
+        K = base + P.off_k;
+        ldk = P.ldk_ws;
+        k_scale = 1.0 / store_scale;
+        UOT_HIP(launch_kernel_build(p->C, p->ldc, n, m, p->eps, nullptr, nullptr, p->k_dtype, (void*)K, ldk,
+                                    store_scale, stream),
+                "kernel build");
+    }
+    UOT_HIP(launch_init(nullptr, 0, nullptr, nullptr, 0, nullptr, nullptr, ctrl, stream), "init");
+
+    PassLaunch L;
+    memset(&L, 0, sizeof(L));
+    L.K = K;
+    L.ldk = ldk;
+    L.n = n;
+    L.m = m;
+    L.rows_per_wg = P.rows_per_wg;
+    L.grid = P.G;
+    L.a = p->a;
+    L.partials = part;
+    L.ldp = P.ldp;
+    L.fi = fi_of(p->eps, p->tau);
+    L.fi_is_one = (L.fi == 1.0);
+    L.inv_eps = 1.0 / p->eps;
+    L.ctrl = ctrl;
+    L.check_done = 0;
+    L.ldv_bytes = P.ldv_bytes;
+    L.k_scale = k_scale;
+    L.fin_blocks = P.fin_blocks;
+    L.blockpart = bp;
+    FinLaunch F;
+    memset(&F, 0, sizeof(F));
+    F.partials = part;
+    F.ldp = P.ldp;
+    F.G = P.G;
+    F.m = m;
+    F.b = p->b;
+    F.k_scale = k_scale;
+    F.fi = L.fi;
+    F.fi_is_one = L.fi_is_one;
+    F.inv_eps = L.inv_eps;
+    F.ctrl = ctrl;
+    F.blockpart = bp;
+    F.acc64 = P.acc64;
+    F.marginal_only = 1;
+    F.c_out = nullptr;
+
+    // one marginal pass: s = K v (rows), w = K^T u (columns)
+    auto marginals = [&](const double* uu, const double* vv, double* s_out, double* w_out) -> hipError_t {
+        PassLaunch LM = L;
+        LM.u = (double*)uu;
+        LM.v = vv;
+        LM.s_out = s_out;
+        hipError_t e = launch_pass(P.k_dtype, P.acc64, MODE_MARG, P.shape, LM, stream);
+        if (e != hipSuccess) return e;
+        FinLaunch FM = F;
+        FM.v = (double*)vv;   // read only (c_out is NULL)
+        FM.w_out = w_out;
+        return launch_finalize(FM, stream);
+    };
+    UOT_HIP(marginals(u, v, sbuf, wbuf), "marginal pass");
+    const bool points = grad_x || grad_y;
+    for (int d = 0; points && d < dim; ++d) {
+        UOT_HIP(launch_env_weight(u, x, n, v, y, m, (int32_t)dim, d, ud, vd, stream), "point weights");
+        UOT_HIP(marginals(ud, vd, sy + (int64_t)d * n, wx + (int64_t)d * m), "marginal pass");
+    }
+    EnvFinish E;
+    memset(&E, 0, sizeof(E));
+    E.grad_loss = grad_loss;
+    E.u = u;
+    E.v = v;
+    E.a = p->a;
+    E.b = p->b;
+    E.s = sbuf;
+    E.w = wbuf;
+    E.sy = sy;
+    E.wx = wx;
+    E.x = x;
+    E.y = y;
+    E.grad_a = grad_a;
+    E.grad_b = grad_b;
+    E.grad_x = grad_x;
+    E.grad_y = grad_y;
+    E.n = n;
+    E.m = m;
+    E.dim = points ? (int32_t)dim : 0;
+    E.tau_inf = isinf(p->tau) ? 1 : 0;
+    E.tau = p->tau;
+    UOT_HIP(launch_env_finish(E, stream), "envelope gradients");
+    if (grad_C)
+        UOT_HIP(launch_plan_from_k(K, p->k_dtype, ldk, n, m, k_scale, u, v, grad_C, UOT_F64, ldgc, stream, grad_loss),
+                "cost gradient");
+    return UOT_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Batched problems
 // ---------------------------------------------------------------------------
 
@@ -1665,6 +1822,20 @@ uot_status uot_sinkhorn_backward(const uot_problem* prob, const uot_options* opt
                                  double* grad_x, double* grad_y, void* ws, size_t ws_bytes, void* stream) {
     return run_backward(prob, opt, u, v, ckpt, grad_loss, grad_a, grad_b, grad_C, ldgc, x, y, dim, grad_x, grad_y,
                         ws, ws_bytes, (hipStream_t)stream);
+}
+
+size_t uot_sinkhorn_implicit_backward_workspace_size(const uot_problem* prob, const uot_options* opt, int64_t dim) {
+    ImpPlan B;
+    if (make_imp_plan(prob, opt, dim, B) != UOT_OK) return 0;
+    return B.total;
+}
+
+uot_status uot_sinkhorn_implicit_backward(const uot_problem* prob, const uot_options* opt, const double* u,
+                                          const double* v, const double* grad_loss, double* grad_a, double* grad_b,
+                                          double* grad_C, int64_t ldgc, const double* x, const double* y, int64_t dim,
+                                          double* grad_x, double* grad_y, void* ws, size_t ws_bytes, void* stream) {
+    return run_implicit_backward(prob, opt, u, v, grad_loss, grad_a, grad_b, grad_C, ldgc, x, y, dim, grad_x, grad_y,
+                                 ws, ws_bytes, (hipStream_t)stream);
 }
 
 size_t uot_batched_desc_bytes(int32_t count) { return count < 0 ? 0 : batch_desc_bytes(count) + sizeof(uot_batched_meta); }

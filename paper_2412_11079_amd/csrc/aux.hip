@@ -767,12 +767,13 @@ template <typename KT, typename PT>
 __global__ __launch_bounds__(256) void plan_from_k_kernel(const KT* __restrict__ K, int64_t ldk, int64_t n,
                                                           int64_t m, double k_scale, const double* __restrict__ u,
                                                           const double* __restrict__ v, PT* __restrict__ P,
-                                                          int64_t ldp) {
+                                                          int64_t ldp, const double* __restrict__ dscale) {
     using Raw = typename KVec<KT>::raw;
     constexpr int V = KVec<KT>::N;
     const int64_t chunks = (m + V - 1) / V;
+    const double sc = dscale ? k_scale * *dscale : k_scale;
     for (int64_t i = blockIdx.y; i < n; i += gridDim.y) {
-        const double ui = u[i] * k_scale;
+        const double ui = u[i] * sc;
         const Raw* row = (const Raw*)(K + i * ldk);
         for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < chunks; q += (int64_t)gridDim.x * 256) {
             double x[V];
@@ -801,14 +802,15 @@ __global__ __launch_bounds__(256) void plan_from_cost_kernel(const double* __res
 
 template <typename PT>
 static hipError_t launch_plan_k_typed(const void* K, int k_dtype, int64_t ldk, int64_t n, int64_t m, double k_scale,
-                                      const double* u, const double* v, PT* P, int64_t ldp, hipStream_t stream) {
+                                      const double* u, const double* v, PT* P, int64_t ldp, const double* dscale,
+                                      hipStream_t stream) {
     const int64_t chunks_max = (m + 1) / 2;
     dim3 grid((unsigned)std::min<int64_t>((chunks_max + 255) / 256, 64), (unsigned)std::min<int64_t>(n, 4096));
     switch (k_dtype) {
-        case UOT_F64: hipLaunchKernelGGL((plan_from_k_kernel<double, PT>), grid, dim3(256), 0, stream, (const double*)K, ldk, n, m, k_scale, u, v, P, ldp); break;
-        case UOT_F32: hipLaunchKernelGGL((plan_from_k_kernel<float, PT>), grid, dim3(256), 0, stream, (const float*)K, ldk, n, m, k_scale, u, v, P, ldp); break;
-        case UOT_BF16: hipLaunchKernelGGL((plan_from_k_kernel<bf16_t, PT>), grid, dim3(256), 0, stream, (const bf16_t*)K, ldk, n, m, k_scale, u, v, P, ldp); break;
-        case UOT_FP8_E4M3: hipLaunchKernelGGL((plan_from_k_kernel<fp8_t, PT>), grid, dim3(256), 0, stream, (const fp8_t*)K, ldk, n, m, k_scale, u, v, P, ldp); break;
+        case UOT_F64: hipLaunchKernelGGL((plan_from_k_kernel<double, PT>), grid, dim3(256), 0, stream, (const double*)K, ldk, n, m, k_scale, u, v, P, ldp, dscale); break;
+        case UOT_F32: hipLaunchKernelGGL((plan_from_k_kernel<float, PT>), grid, dim3(256), 0, stream, (const float*)K, ldk, n, m, k_scale, u, v, P, ldp, dscale); break;
+        case UOT_BF16: hipLaunchKernelGGL((plan_from_k_kernel<bf16_t, PT>), grid, dim3(256), 0, stream, (const bf16_t*)K, ldk, n, m, k_scale, u, v, P, ldp, dscale); break;
+        case UOT_FP8_E4M3: hipLaunchKernelGGL((plan_from_k_kernel<fp8_t, PT>), grid, dim3(256), 0, stream, (const fp8_t*)K, ldk, n, m, k_scale, u, v, P, ldp, dscale); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -816,11 +818,11 @@ static hipError_t launch_plan_k_typed(const void* K, int k_dtype, int64_t ldk, i
 
 hipError_t launch_plan_from_k(const void* K, int k_dtype, int64_t ldk, int64_t n, int64_t m, double k_scale,
                               const double* u, const double* v, void* P, int plan_dtype, int64_t ldp,
-                              hipStream_t stream) {
+                              hipStream_t stream, const double* dscale) {
     if (plan_dtype == UOT_F64)
-        return launch_plan_k_typed<double>(K, k_dtype, ldk, n, m, k_scale, u, v, (double*)P, ldp, stream);
+        return launch_plan_k_typed<double>(K, k_dtype, ldk, n, m, k_scale, u, v, (double*)P, ldp, dscale, stream);
     if (plan_dtype == UOT_F32)
-        return launch_plan_k_typed<float>(K, k_dtype, ldk, n, m, k_scale, u, v, (float*)P, ldp, stream);
+        return launch_plan_k_typed<float>(K, k_dtype, ldk, n, m, k_scale, u, v, (float*)P, ldp, dscale, stream);
     return hipErrorInvalidValue;
 }
 

@@ -418,6 +418,22 @@ struct GradCLaunch {
 int gradc_row_tiles(int64_t n);
 hipError_t launch_fill_f64(double* p, int64_t count, double value, hipStream_t stream);
 hipError_t launch_gradc(const GradCLaunch& L, hipStream_t stream);
+// Implicit (envelope) gradients from marginal passes (adj.hip).
+hipError_t launch_env_weight(const double* u, const double* x, int64_t n, const double* v, const double* y, int64_t m,
+                             int32_t dim, int32_t d, double* ud, double* vd, hipStream_t stream);
+struct EnvFinish {
+    const double* grad_loss;
+    const double* u; const double* v; const double* a; const double* b;
+    const double* s; const double* w;          // K v, K^T u
+    const double* sy; const double* wx;        // dim x n: K (v y_d); dim x m: K^T (u x_d)
+    const double* x; const double* y;
+    double* grad_a; double* grad_b; double* grad_x; double* grad_y;
+    int64_t n, m;
+    int32_t dim;
+    int32_t tau_inf;
+    double tau;
+};
+hipError_t launch_env_finish(const EnvFinish& F, hipStream_t stream);
 // grad_y[j][d] = 2 (y_jd sum_i G_ij - sum_i G_ij x_id), the sums taken over row tiles in order.
 hipError_t launch_grady_finish(const double* ysum, int32_t tiles, const double* y, int64_t m, int32_t dim,
                                double* grad_y, hipStream_t stream);

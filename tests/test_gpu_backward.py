@@ -214,3 +214,97 @@ def test_backward_full_size_against_oracle():
         e = _norm_err(g, r)
         say(f"  grad_{name}: {e:.3e}")
         assert e <= 1e-5, name
+
+
+# ------------------------------------------------------------------ implicit (envelope) gradients
+def _gpu_implicit(prob, T, k_dtype, scale=1.0, C=None):
+    x, y = to_dev(prob.x), to_dev(prob.y)
+    if C is None:
+        C = uot.cost_from_points(x, y, prob.cost_kind, prob.normalize_max)
+    K = uot.kernel_from_cost(C, prob.eps, k_dtype)
+    res = uot.sinkhorn(to_dev(prob.a), to_dev(prob.b), K, m=prob.m, eps=prob.eps, tau=prob.tau, max_iter=T)
+    g = torch.full((), scale, dtype=torch.float64, device="cuda")
+    gr = uot.sinkhorn_implicit_backward(res, g, x=x, y=y, want_C=True, want_y=True)
+    torch.cuda.synchronize()
+    return res, {k: getattr(gr, "grad_" + k).cpu().numpy() for k in ("a", "b", "x", "y", "C")}
+
+
+def _oracle_implicit(prob, T, storage=None, scale=1.0):
+    C = oracle.cost_points(prob.x, prob.y, prob.cost_kind, prob.normalize_max)
+    K = oracle.kernel(C, prob.eps)
+    if storage is not None:
+        K = oracle.round_storage(K * (448.0 if storage == "e4m3" else 1.0), storage) / (448.0 if storage == "e4m3"
+                                                                                       else 1.0)
+    res = oracle.sinkhorn(K, prob.a, prob.b, prob.eps, prob.tau, T)
+    ga, gb, P = oracle.envelope_gradients(K, res.u, res.v, prob.a, prob.b, prob.tau)
+    return {"a": scale * ga, "b": scale * gb, "C": scale * P,
+            "x": scale * oracle.grad_points_sqeuclid(P, prob.x, prob.y),
+            "y": scale * oracle.grad_target_sqeuclid(P, prob.x, prob.y)}
+
+
+@pytest.mark.parametrize("n,m,T,k_dtype,storage,tol", [
+    (300, 257, 20, torch.float64, None, 1e-10),
+    (129, 700, 9, torch.float64, None, 1e-10),
+    (1000, 1500, 40, torch.float32, None, 1e-6),
+    (777, 4093, 25, torch.float32, None, 1e-6),
+    (700, 1111, 30, torch.bfloat16, "bf16", 1e-6),
+    (700, 1111, 30, torch.float8_e4m3fn, "e4m3", 1e-6)])
+def test_implicit_gradients_match_oracle_envelope(n, m, T, k_dtype, storage, tol):
+    """The envelope gradients at the scalings after T iterations (converged
+    or not), against the oracle's envelope gradients at its own scalings of
+    the same T iterations on the same stored kernel; grad_loss = 0.8."""
+    prob = workloads.grad(n=n, m=m, max_iter=T)
+    say(f"implicit gradients {k_dtype} n={n} m={m} T={T}")
+    ref = _oracle_implicit(prob, T, storage, 0.8)
+    _, got = _gpu_implicit(prob, T, k_dtype, 0.8)
+    for name in ("a", "b", "x", "y", "C"):
+        e = _norm_err(got[name], ref[name])
+        say(f"  grad_{name}: {e:.3e}")
+        assert e <= tol, name
+
+
+def test_implicit_equals_unrolled_at_convergence():
+    """Once the iterates have converged (eps = 0.1, tau = 1, 600 iterations:
+    fi^1200 ~ 1e-25), the envelope gradients equal the unrolled reverse
+    sweep's on the GPU, FP64 K."""
+    prob = workloads.grad(n=600, m=520, max_iter=600)
+    prob.eps = 0.1
+    _, imp = _gpu_implicit(prob, 600, torch.float64)
+    _, ga, gb, gx, G, gy = _gpu_grads(prob, 600, 100, torch.float64, full=True)
+    for name, g in (("a", ga), ("b", gb), ("x", gx), ("C", G), ("y", gy)):
+        e = _norm_err(imp[name], g)
+        say(f"  implicit vs unrolled grad_{name}: {e:.3e}")
+        assert e <= 1e-10, name
+
+
+def test_implicit_autograd_and_errors():
+    prob = workloads.grad(n=300, m=260, max_iter=40)
+    x = to_dev(prob.x).requires_grad_(True)
+    y = to_dev(prob.y).requires_grad_(True)
+    a = to_dev(prob.a).requires_grad_(True)
+    b = to_dev(prob.b)
+    L = uot.uot_loss(x, y, a, b, prob.eps, prob.tau, 40, k_dtype=torch.float64, implicit=True)
+    (1.5 * L).backward()
+    _, got = _gpu_implicit(prob, 40, torch.float64, 1.5)
+    np.testing.assert_allclose(x.grad.cpu().numpy(), got["x"], rtol=1e-13, atol=0)
+    np.testing.assert_allclose(y.grad.cpu().numpy(), got["y"], rtol=1e-13, atol=0)
+    np.testing.assert_allclose(a.grad.cpu().numpy(), got["a"], rtol=1e-13, atol=0)
+    res, _ = _gpu_implicit(prob, 5, torch.float64)
+    g = torch.ones((), dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):
+        uot.sinkhorn_implicit_backward(res, g, want_y=True)          # point gradients need x and y
+
+
+def test_implicit_full_size_against_unrolled_oracle():
+    """Differentiation workload at full size (8192^2 FP32, 500 iterations):
+    the envelope gradients against the oracle's unrolled adjoint, within the
+    gradient bar (the iterates are converged to fi^1000 ~ 2.5e-9)."""
+    prob = workloads.grad()
+    say("full-size implicit: oracle unrolled adjoint on the host ...")
+    ref, ga0, gb0, gx0, G0, gy0 = _oracle_grads(prob, prob.max_iter, full=True)
+    say("  GPU ...")
+    _, got = _gpu_implicit(prob, prob.max_iter, torch.float32)
+    for name, r in (("a", ga0), ("b", gb0), ("x", gx0), ("C", G0), ("y", gy0)):
+        e = _norm_err(got[name], r)
+        say(f"  grad_{name}: {e:.3e}")
+        assert e <= 1e-5, name
