@@ -79,6 +79,9 @@ def _load():
                                               ctypes.c_int, ctypes.c_double, _dp, _dp, _dp, _dp,
                                               _dp, ctypes.POINTER(_i64), _dp, _dp]
         lib.orc_sinkhorn_absorbed.restype = _i64
+        lib.orc_matrix_rescale.argtypes = [_dp, _dp, _dp, _i64, _i64, ctypes.c_double, ctypes.c_double, _i64, _dp,
+                                           _dp]
+        lib.orc_matrix_rescale.restype = None
         lib.orc_envelope_gradients.argtypes = [_dp, _dp, _dp, _dp, _dp, _i64, _i64, ctypes.c_double, _dp, _dp,
                                                _dp]
         lib.orc_envelope_gradients.restype = None
@@ -227,6 +230,19 @@ def adjoint(K, a, b, eps: float, tau: float, res: Result, want_G: bool = True):
                         _p(tr["v"]), _p(tr["s"]), _p(tr["u"]), _p(tr["w"]),
                         _p(ga), _p(gb), _p(G))
     return ga, gb, G
+
+
+def matrix_rescale(A, a, b, eps: float, tau: float, T: int):
+    """The paper's literal in-place rescaling of a copy of A (column factors
+    first, then each row, T iterations); returns (A_T, r, c)."""
+    A = np.array(A, dtype=np.float64, copy=True, order="C")
+    a = _f64(a)
+    b = _f64(b)
+    n, m = A.shape
+    r = np.empty(n)
+    c = np.empty(m)
+    _load().orc_matrix_rescale(_p(A), _p(a), _p(b), n, m, float(eps), float(tau), int(T), _p(r), _p(c))
+    return A, r, c
 
 
 def envelope_gradients(K, u, v, a, b, tau: float, want_P: bool = True):

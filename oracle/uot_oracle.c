@@ -481,6 +481,63 @@ ORC_EXPORT void orc_grad_target_sqeuclid(const double* G, const double* x, const
 }
 
 /* ------------------------------------------------------------------ */
+/* The paper's literal in-place matrix rescaling                        */
+/* ------------------------------------------------------------------ */
+/* Section 2.1's rescaling applied to the matrix itself, in the order of the
+ * interleaved single-pass algorithm of Section 4.1 (Algorithm 1: column
+ * factors first, then each row).  Before the first iteration the column
+ * factors are computed from A's column sums; each iteration then, for every
+ * row i: multiplies the row by the column factors, sums it, forms the row
+ * factor (RPD_i / sum)^fi, multiplies the row by it and adds the row into
+ * the next column sums; at its end the column factors become
+ * (CPD_j / column sum_j)^fi.  A (n x m, row-major) is rescaled in place for
+ * T iterations; r and c (optional) receive its row and column sums after
+ * the last one.  RPD = a, CPD = b; a zero target gives a zero factor.
+ * Plain loops, every sum in ascending index order. */
+ORC_EXPORT void orc_matrix_rescale(double* A, const double* a, const double* b, int64_t n, int64_t m,
+                                   double eps, double tau, int64_t T, double* r, double* c) {
+    const double fi = orc_fi(eps, tau);
+    double* fcol = (double*)malloc(sizeof(double) * (size_t)m);
+    double* next = (double*)malloc(sizeof(double) * (size_t)m);
+    for (int64_t j = 0; j < m; ++j) fcol[j] = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < m; ++j) fcol[j] += A[i * m + j];
+    for (int64_t t = 0; t < T; ++t) {
+        for (int64_t j = 0; j < m; ++j) {
+            fcol[j] = orc_factor(b[j], fcol[j], fi);
+            next[j] = 0.0;
+        }
+        for (int64_t i = 0; i < n; ++i) {
+            double* row = A + i * m;
+            double sum = 0.0;
+            for (int64_t j = 0; j < m; ++j) {
+                row[j] *= fcol[j];
+                sum += row[j];
+            }
+            const double frow = orc_factor(a[i], sum, fi);
+            for (int64_t j = 0; j < m; ++j) {
+                row[j] *= frow;
+                next[j] += row[j];
+            }
+        }
+        for (int64_t j = 0; j < m; ++j) fcol[j] = next[j];
+    }
+    if (r)
+        for (int64_t i = 0; i < n; ++i) {
+            double sum = 0.0;
+            for (int64_t j = 0; j < m; ++j) sum += A[i * m + j];
+            r[i] = sum;
+        }
+    if (c) {
+        for (int64_t j = 0; j < m; ++j) c[j] = 0.0;
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = 0; j < m; ++j) c[j] += A[i * m + j];
+    }
+    free(fcol);
+    free(next);
+}
+
+/* ------------------------------------------------------------------ */
 /* Envelope (implicit) gradients                                        */
 /* ------------------------------------------------------------------ */
 /* At the minimiser P* of the primal objective (entropic UOT, Section 2.1's

@@ -307,6 +307,62 @@ def test_adjoint_envelope_at_convergence():
     np.testing.assert_allclose(gb, prob.tau * (1 - res.c / prob.b), rtol=0, atol=1e-9)
 
 
+def test_matrix_rescale_balanced_equals_vector_form():
+    """fi = 1 (tau = inf): the literal in-place rescaling after T iterations
+    is diag(alpha) K diag(beta) with alpha, beta the vector-form scalings
+    taken columns first, i.e. the oracle's rows-first iteration on K^T with
+    the histograms swapped."""
+    prob = workloads.random_small(11, 7, seed=51, eps=0.2, tau=math.inf)
+    C, K = _problem_arrays(prob)
+    for T in (1, 2, 9):
+        A, r, c = oracle.matrix_rescale(K, prob.a, prob.b, prob.eps, prob.tau, T)
+        res = oracle.sinkhorn(K.T.copy(), prob.b, prob.a, prob.eps, prob.tau, T)
+        P = (res.u[:, None] * K.T * res.v[None, :]).T
+        np.testing.assert_allclose(A, P, rtol=1e-12, atol=0)
+        np.testing.assert_allclose(r, A.sum(axis=1), rtol=1e-13)
+        np.testing.assert_allclose(c, A.sum(axis=0), rtol=1e-13)
+        np.testing.assert_allclose(r, prob.a, rtol=1e-12)         # rows are rescaled last
+
+
+def test_matrix_rescale_separable_closed_form():
+    """A rank-1 start A = k1 k2^T stays rank-1 under the literal rescaling,
+    with the O(n + m) recurrence (columns, then rows)
+      k2 <- k2^(1-fi) b^fi S1^(-fi),  S1 = sum k1,
+      k1 <- k1^(1-fi) a^fi S2^(-fi),  S2 = sum k2,
+    checked at every T against the O(nm) in-place rescaling, fi < 1."""
+    rng = np.random.default_rng(52)
+    n, m = 9, 14
+    k1 = np.exp(-rng.random(n))
+    k2 = np.exp(-rng.random(m))
+    a = 0.5 + rng.random(n)
+    b = 0.5 + rng.random(m)
+    eps, tau = 0.05, 0.7
+    fi = tau / (tau + eps)
+    for T in (1, 3, 10):
+        A, _, _ = oracle.matrix_rescale(np.outer(k1, k2), a, b, eps, tau, T)
+        l1, l2 = np.log(k1), np.log(k2)
+        for _ in range(T):
+            l2 = (1 - fi) * l2 + fi * np.log(b) - fi * np.log(np.exp(l1).sum())
+            l1 = (1 - fi) * l1 + fi * np.log(a) - fi * np.log(np.exp(l2).sum())
+        np.testing.assert_allclose(A, np.exp(l1[:, None] + l2[None, :]), rtol=1e-12)
+
+
+def test_matrix_rescale_one_by_one_limit_is_cost_independent():
+    """1 x 1: log A after a column and a row step is (1-fi)^2 log A + (1-fi)
+    fi log b + fi log a; the fixed point ((1-fi) log b + log a)/(2 - fi) does
+    not depend on the cost, unlike the vector form's optimum."""
+    eps, tau, a, b, C = 0.05, 1.0, 0.7, 1.3, 0.4
+    fi = tau / (tau + eps)
+    K = np.array([[math.exp(-C / eps)]])
+    x = math.log(K[0, 0])
+    for T in range(1, 6):
+        x = (1 - fi) * ((1 - fi) * x + fi * math.log(b)) + fi * math.log(a)
+        A, _, _ = oracle.matrix_rescale(K, [a], [b], eps, tau, T)
+        assert math.log(A[0, 0]) == pytest.approx(x, abs=1e-13)
+    A, _, _ = oracle.matrix_rescale(K, [a], [b], eps, tau, 400)
+    assert math.log(A[0, 0]) == pytest.approx(((1 - fi) * math.log(b) + math.log(a)) / (2 - fi), abs=1e-12)
+
+
 def test_envelope_gradients_equal_unrolled_adjoint_at_convergence():
     """The oracle's implicit gradients against its unrolled reverse mode
     (pinned by finite differences) once the iterates have converged
