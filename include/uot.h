@@ -240,6 +240,36 @@ uot_status uot_sinkhorn(const uot_problem* prob, const uot_options* opt,
                         const uot_outputs* out, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * The paper's literal form (Section 2.1, in the single-pass order of
+ * Section 4.1's Algorithm 1): the matrix given as prob->K (FP32 or FP64,
+ * n x ldk) is rescaled IN PLACE.  Before the first iteration the column
+ * factors beta_j = (b_j / column sum_j)^fi are formed; each iteration then
+ * multiplies every row by beta, forms the row factor alpha_i =
+ * (a_i / row sum_i)^fi, multiplies the row by it (one read and one write of
+ * the matrix, fused), and forms the next beta from the new column sums.
+ * For fi = 1 (tau = inf) this is the vector-form iteration taken columns
+ * first; for fi < 1 it is a different iteration (its limit does not depend
+ * on the cost), provided to measure the in-place form beside the vector
+ * form (twice the bytes per iteration).
+ *   prob: n, m, a, b (targets), K (the matrix, modified), ldk, eps, tau;
+ *     k_scale 0 or 1; C ignored.
+ *   opt: max_iter, tol / check_every (relative L1 change of beta * column
+ *     sums, as uot_sinkhorn), tune (one-row launch shapes 1-8); absorption,
+ *     checkpoints, warm start, cooperative loop and FP64 accumulation of an
+ *     FP32 matrix must be off.
+ *   out: u (n) receives the last row factors, v (m) the column factors the
+ *     next iteration would apply, r (n, optional) the row sums and c (m,
+ *     optional) the column sums of the rescaled matrix, info (optional);
+ *     loss, ckpt, f, g are ignored.
+ * Columns [m, round up of m to 16 bytes) of each row are written as 0.
+ * Errors: UOT_ERR_ARG, UOT_ERR_DTYPE, UOT_ERR_ALIGN, UOT_ERR_WORKSPACE,
+ * UOT_ERR_UNSUPPORTED, UOT_ERR_HIP.
+ */
+size_t uot_matrix_rescale_workspace_size(const uot_problem* prob, const uot_options* opt);
+uot_status uot_matrix_rescale(const uot_problem* prob, const uot_options* opt, const uot_outputs* out,
+                              void* ws, size_t ws_bytes, void* stream);
+
+/*
  * For callers that cannot allocate (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): uot_sinkhorn without a
  * workspace argument.  Its scratch is a device array of the library,

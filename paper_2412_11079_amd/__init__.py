@@ -18,7 +18,7 @@ from ._lib import (UOT_ACC_F32, UOT_ACC_F64, UOT_BF16, UOT_COST_COSINE, UOT_COST
                    UOT_FLAG_NONFINITE, UOT_FLAG_NOT_CONVERGED, UOT_FLAG_ZERO_SUM, UOT_FP8_E4M3, UOTError)
 
 __all__ = ["sinkhorn", "sinkhorn_backward", "sinkhorn_implicit_backward", "Gradients", "UOTLoss", "UOTCostLoss", "uot_loss", "uot_loss_cost", "cost_from_points", "kernel_from_cost",
-           "kernel_to_f32", "sinkhorn_batched", "BatchedSolver", "BatchedResult", "plan", "sinkhorn_multi",
+           "kernel_to_f32", "matrix_rescale_", "MatrixResult", "sinkhorn_batched", "BatchedSolver", "BatchedResult", "plan", "sinkhorn_multi",
            "SinkhornResult", "UOTError", "lib_path",
            "UOT_F64", "UOT_F32", "UOT_BF16", "UOT_FP8_E4M3", "UOT_COST_SQEUCLID", "UOT_COST_COSINE"]
 
@@ -225,6 +225,55 @@ def sinkhorn(a: torch.Tensor, b: torch.Tensor, K: Optional[torch.Tensor] = None,
     res._problem = prob
     res._options = opt
     res.ckpt = ckpt
+    return res
+
+
+@dataclass
+class MatrixResult:
+    alpha: torch.Tensor       # (n,) last row factors
+    beta: torch.Tensor        # (m,) column factors of the next iteration
+    r: torch.Tensor           # (n,) row sums of the rescaled matrix
+    c: torch.Tensor           # (m,) column sums
+    info_raw: torch.Tensor
+
+    def info(self) -> dict:
+        s = _lib.Info.from_buffer_copy(bytes(self.info_raw.cpu().numpy().tobytes()))
+        return {"iters": s.iters, "err": s.err, "flags": s.flags}
+
+
+def matrix_rescale_(A: torch.Tensor, a: torch.Tensor, b: torch.Tensor, *, m: Optional[int] = None, eps: float,
+                    tau: float, max_iter: int, tol: float = 0.0, check_every: int = 1, tune: int = 0) -> MatrixResult:
+    """The paper's literal in-place rescaling of ``A`` (include/uot.h,
+    uot_matrix_rescale): ``A`` (n, ldk) FP32 or FP64 is modified in place."""
+    if A.dtype not in (torch.float32, torch.float64):
+        raise ValueError("A must be float32 or float64")
+    device = A.device
+    n = a.shape[0]
+    m = b.shape[0] if m is None else int(m)
+    a = _vec64(a, "a", n, device)
+    b = _vec64(b, "b", m, device)
+    prob = _problem(a, b, A, None, m, eps, tau, device)
+    opt = _lib.Options()
+    opt.max_iter = int(max_iter)
+    opt.check_every = int(check_every)
+    opt.tol = float(tol)
+    opt.fused = 1
+    opt.tune = int(tune)
+    L = _lib.lib()
+    need = L.uot_matrix_rescale_workspace_size(ctypes.byref(prob), ctypes.byref(opt))
+    if need == 0:
+        _lib.check(L.uot_matrix_rescale(ctypes.byref(prob), ctypes.byref(opt), None, None, 0, None))
+    ws = _workspace(need, device)
+    res = MatrixResult(alpha=torch.empty(n, dtype=torch.float64, device=device),
+                       beta=torch.empty(m, dtype=torch.float64, device=device),
+                       r=torch.empty(n, dtype=torch.float64, device=device),
+                       c=torch.empty(m, dtype=torch.float64, device=device),
+                       info_raw=torch.zeros(ctypes.sizeof(_lib.Info), dtype=torch.uint8, device=device))
+    out = _lib.Outputs(res.alpha.data_ptr(), res.beta.data_ptr(), res.r.data_ptr(), res.c.data_ptr(), None,
+                       res.info_raw.data_ptr(), None, None, None)
+    _lib.check(L.uot_matrix_rescale(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(out), _ptr(ws), ws.numel(),
+                                    _stream(device)))
+    res._keep = (ws, a, b)
     return res
 
 

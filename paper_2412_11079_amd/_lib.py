@@ -64,6 +64,9 @@ SIGNATURES = {
     "uot_sinkhorn_workspace_size": ([ctypes.POINTER(Problem), ctypes.POINTER(Options)], _sz),
     "uot_sinkhorn": ([ctypes.POINTER(Problem), ctypes.POINTER(Options), ctypes.POINTER(Outputs), _vp, _sz, _vp],
                      _i32),
+    "uot_matrix_rescale_workspace_size": ([ctypes.POINTER(Problem), ctypes.POINTER(Options)], _sz),
+    "uot_matrix_rescale": ([ctypes.POINTER(Problem), ctypes.POINTER(Options), ctypes.POINTER(Outputs), _vp, _sz,
+                            _vp], _i32),
     "uot_sinkhorn_noalloc": ([ctypes.POINTER(Problem), ctypes.POINTER(Options), ctypes.POINTER(Outputs), _vp],
                              _i32),
     "uot_sinkhorn_profiled": ([ctypes.POINTER(Problem), ctypes.POINTER(Options), ctypes.POINTER(Outputs), _vp,

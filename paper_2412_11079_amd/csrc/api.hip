@@ -232,7 +232,7 @@ int64_t max_lds_bytes() {
     return v;
 }
 
-uot_status make_plan(const uot_problem* p, const uot_options* o, Plan& P) {
+uot_status make_plan(const uot_problem* p, const uot_options* o, Plan& P, bool one_row = false) {
     uot_status st = check_problem(p, o);
     if (st != UOT_OK) return st;
     P.k_dtype = p->k_dtype;
@@ -247,7 +247,7 @@ uot_status make_plan(const uot_problem* p, const uot_options* o, Plan& P) {
             return fail(UOT_ERR_UNSUPPORTED, "shape %d covers %lld columns, m=%lld", P.shape,
                         (long long)s.wg * s.nc * P.vec, (long long)p->m);
     } else {
-        P.shape = default_shape(nv, o->persistent != 0, P.k_dtype, P.acc64);
+        P.shape = default_shape(nv, o->persistent != 0 || one_row, P.k_dtype, P.acc64);
         if (P.shape < 0)
             return fail(UOT_ERR_UNSUPPORTED, "m=%lld exceeds the row length one workgroup holds (%d columns)",
                         (long long)p->m, 4096 * P.vec);
@@ -975,6 +975,134 @@ uot_status run_backward(const uot_problem* p, const uot_options* o, const double
     return UOT_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// The paper's literal in-place matrix rescaling
+// ---------------------------------------------------------------------------
+uot_status make_matrix_plan(const uot_problem* p, const uot_options* o, Plan& P) {
+    if (!p || !o) return fail(UOT_ERR_ARG, "problem and options must not be NULL");
+    if (!p->K) return fail(UOT_ERR_ARG, "the in-place form rescales the matrix given as K");
+    if (p->k_dtype != UOT_F32 && p->k_dtype != UOT_F64)
+        return fail(UOT_ERR_DTYPE, "the in-place form rescales an FP32 or FP64 matrix");
+    if (o->absorb_log_threshold != 0.0 || o->checkpoint_every != 0 || o->persistent || o->u0 || o->v0 || !o->fused ||
+        (p->k_dtype == UOT_F32 && o->accum == UOT_ACC_F64))
+        return fail(UOT_ERR_UNSUPPORTED,
+                    "the in-place form runs the fused per-iteration pass with the storage type's own arithmetic: "
+                    "no absorption, checkpoints, warm start, cooperative loop or FP64 accumulation of FP32");
+    if (o->tune > 8) return fail(UOT_ERR_UNSUPPORTED, "the in-place form runs the one-row launch shapes (tune 1-8)");
+    if (p->k_scale != 0.0 && p->k_scale != 1.0) return fail(UOT_ERR_ARG, "the in-place form takes k_scale 1");
+    return make_plan(p, o, P, true);
+}
+
+uot_status run_matrix(const uot_problem* p, const uot_options* o, const uot_outputs* out, void* ws, size_t ws_bytes,
+                      hipStream_t stream) {
+    Plan P;
+    uot_status st = make_matrix_plan(p, o, P);
+    if (st != UOT_OK) return st;
+    if (!out || !out->u || !out->v) return fail(UOT_ERR_ARG, "outputs u and v are required");
+    if (!aligned(out->u, 8) || !aligned(out->v, 8)) return fail(UOT_ERR_ALIGN, "u and v must be 8-byte aligned");
+    if (ws_bytes < P.total || !ws) return fail(UOT_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", P.total, ws_bytes);
+    if (!aligned(ws, kAlign)) return fail(UOT_ERR_ALIGN, "workspace must be 256-byte aligned");
+    PinnedGuard pin;
+    if (o->tol > 0.0) UOT_HIP(pinned_acquire(pin.slot), "hipHostMalloc");
+    uint32_t* flag_host = o->tol > 0.0 ? pin.slot.flag() : nullptr;
+    char* base = (char*)ws;
+    Ctrl* ctrl = (Ctrl*)(base + P.off_ctrl);
+    double* cprev = (double*)(base + P.off_cprev);
+    double* wbuf = (double*)(base + P.off_w);
+    double* bp = (double*)(base + P.off_bp);
+    void* part = base + P.off_part;
+    double* alpha = out->u;      // row factors of the last iteration (1 before the first)
+    double* beta = out->v;       // column factors the next iteration applies
+    // u = 1 (it weights the first column sums), beta = 1 (so the first factors are (b / colsum)^fi)
+    UOT_HIP(launch_init(alpha, p->n, nullptr, beta, p->m, nullptr, cprev, ctrl, stream), "init");
+    const double fi = fi_of(p->eps, p->tau);
+
+    PassLaunch L;
+    memset(&L, 0, sizeof(L));
+    L.K = p->K;
+    L.ldk = p->ldk;
+    L.n = p->n;
+    L.m = p->m;
+    L.rows_per_wg = P.rows_per_wg;
+    L.grid = P.G;
+    L.v = beta;
+    L.a = p->a;
+    L.u = alpha;
+    L.s_out = out->r;
+    L.partials = part;
+    L.ldp = P.ldp;
+    L.fi = fi;
+    L.fi_is_one = (fi == 1.0);
+    L.inv_eps = 1.0 / p->eps;
+    L.ctrl = ctrl;
+    L.check_done = 1;
+    L.ldv_bytes = P.ldv_bytes;
+    L.k_scale = 1.0;
+    L.tol = o->tol;
+    L.fin_blocks = P.fin_blocks;
+    L.blockpart = bp;
+    FinLaunch F;
+    memset(&F, 0, sizeof(F));
+    F.partials = part;
+    F.ldp = P.ldp;
+    F.G = P.G;
+    F.m = p->m;
+    F.b = p->b;
+    F.v = beta;
+    F.w_out = wbuf;
+    F.cprev = cprev;
+    F.k_scale = 1.0;
+    F.fi = fi;
+    F.fi_is_one = (fi == 1.0);
+    F.inv_eps = 1.0 / p->eps;
+    F.ctrl = ctrl;
+    F.blockpart = bp;
+    F.acc64 = P.acc64;
+
+    // Before the first iteration: column sums of A (rows weighted by u = 1),
+    // then the first column factors.
+    {
+        PassLaunch LC = L;
+        LC.check_done = 0;
+        UOT_HIP(launch_pass(P.k_dtype, P.acc64, MODE_COL, P.shape, LC, stream), "column sums");
+        UOT_HIP(launch_finalize(F, stream), "column factors");
+    }
+    const int check_every = o->check_every > 0 ? o->check_every : 1;
+    int64_t iters_run = 0;
+    for (int t = 0; t < o->max_iter; ++t) {
+        PassLaunch L1 = L;
+        L1.iter = t + 1;
+        L1.test_stop = 1;
+        UOT_HIP(launch_pass_matrix(P.k_dtype, P.shape, L1, stream), "in-place pass");
+        UOT_HIP(launch_finalize(F, stream), "column factors");
+        iters_run = t + 1;
+        if (flag_host && (t + 1) % check_every == 0 && t + 1 < o->max_iter) {
+            UOT_HIP(hipMemcpyAsync(flag_host, &ctrl->done, sizeof(uint32_t), hipMemcpyDeviceToHost, stream),
+                    "flag copy");
+            UOT_HIP(hipStreamSynchronize(stream), "flag sync");
+            if (*(volatile uint32_t*)flag_host) break;
+        }
+    }
+    if (out->c && o->max_iter > 0)
+        UOT_HIP(hipMemcpyAsync(out->c, wbuf, sizeof(double) * p->m, hipMemcpyDeviceToDevice, stream), "column sums");
+    if (out->info) {
+        ObjLaunch O;
+        memset(&O, 0, sizeof(O));
+        O.n = p->n;
+        O.m = p->m;
+        O.eps = p->eps;
+        O.info = out->info;
+        O.ctrl = ctrl;
+        O.tol = o->tol;
+        O.iters_run = iters_run;
+        O.blockpart = bp;
+        O.fin_blocks = P.fin_blocks;
+        O.info_only = 1;
+        UOT_HIP(launch_objective(O, stream), "report");
+    }
+    return UOT_OK;
+}
 
 // ---------------------------------------------------------------------------
 // Implicit (envelope) backward: marginal passes only
@@ -1822,6 +1950,17 @@ uot_status uot_sinkhorn_backward(const uot_problem* prob, const uot_options* opt
                                  double* grad_x, double* grad_y, void* ws, size_t ws_bytes, void* stream) {
     return run_backward(prob, opt, u, v, ckpt, grad_loss, grad_a, grad_b, grad_C, ldgc, x, y, dim, grad_x, grad_y,
                         ws, ws_bytes, (hipStream_t)stream);
+}
+
+size_t uot_matrix_rescale_workspace_size(const uot_problem* prob, const uot_options* opt) {
+    Plan P;
+    if (make_matrix_plan(prob, opt, P) != UOT_OK) return 0;
+    return P.total;
+}
+
+uot_status uot_matrix_rescale(const uot_problem* prob, const uot_options* opt, const uot_outputs* out, void* ws,
+                              size_t ws_bytes, void* stream) {
+    return run_matrix(prob, opt, out, ws, ws_bytes, (hipStream_t)stream);
 }
 
 size_t uot_sinkhorn_implicit_backward_workspace_size(const uot_problem* prob, const uot_options* opt, int64_t dim) {

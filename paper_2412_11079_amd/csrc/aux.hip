@@ -175,7 +175,7 @@ __global__ __launch_bounds__(1024) void objective_kernel(ObjLaunch O) {
     // With potentials, the total scalings are u e^{f/eps}, v e^{g/eps} and
     // log(total) = log u + f/eps; r = u * (Kt v), c = v * (Kt^T u) as before.
     const double inv_eps = 1.0 / O.eps;
-    for (int64_t i = tid; i < O.n; i += 1024) {
+    for (int64_t i = tid; i < (O.info_only ? 0 : O.n); i += 1024) {
         double r = O.u[i] * O.s[i];
         if (O.r_out) O.r_out[i] = r;
         double lu = (O.u[i] > 0.0) ? log(O.u[i]) + (O.fpot ? O.fpot[i] * inv_eps : 0.0) : -INFINITY;
@@ -185,7 +185,7 @@ __global__ __launch_bounds__(1024) void objective_kernel(ObjLaunch O) {
         mass += r;
         kr += kl_term(r, O.a[i]);
     }
-    for (int64_t j = tid; j < O.m; j += 1024) {
+    for (int64_t j = tid; j < (O.info_only ? 0 : O.m); j += 1024) {
         double c = O.v[j] * O.w[j];
         if (O.c_out) O.c_out[j] = c;
         double lv = (O.v[j] > 0.0) ? log(O.v[j]) + (O.gpot ? O.gpot[j] * inv_eps : 0.0) : -INFINITY;
@@ -222,7 +222,7 @@ __global__ __launch_bounds__(1024) void objective_kernel(ObjLaunch O) {
             O.info->absorptions = O.absorptions;
             uint32_t fl = O.ctrl->flags;
             if (O.tol > 0.0 && !stopped && !(O.iters_run > 0 && stop_err <= O.tol)) fl |= UOT_FLAG_NOT_CONVERGED;
-            if (!isfinite(L)) fl |= UOT_FLAG_NONFINITE;
+            if (!O.info_only && !isfinite(L)) fl |= UOT_FLAG_NONFINITE;
             O.info->flags = fl;
         }
     }

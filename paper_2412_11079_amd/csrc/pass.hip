@@ -292,6 +292,22 @@ static hipError_t launch_typed(int mode, int shape_idx, const PassLaunch& L, siz
     }
 }
 
+// The in-place matrix form: one-row shapes (0-7), storage type = lane type.
+template <typename KT>
+static hipError_t launch_matrix_typed(int shape_idx, const PassLaunch& L, size_t lds, hipStream_t stream) {
+    switch (shape_idx) {
+        case 0: return launch_one<KT, KT, 256, 1, 4, false, MODE_MATRIX, 1>(L, lds, stream, nullptr);
+        case 1: return launch_one<KT, KT, 512, 1, 4, false, MODE_MATRIX, 1>(L, lds, stream, nullptr);
+        case 2: return launch_one<KT, KT, 1024, 1, 4, false, MODE_MATRIX, 1>(L, lds, stream, nullptr);
+        case 3: return launch_one<KT, KT, 1024, 2, 3, false, MODE_MATRIX, 1>(L, lds, stream, nullptr);
+        case 4: return launch_one<KT, KT, 512, 4, 3, false, MODE_MATRIX, 1>(L, lds, stream, nullptr);
+        case 5: return launch_one<KT, KT, 512, 8, 2, true, MODE_MATRIX, 1>(L, lds, stream, nullptr);
+        case 6: return launch_one<KT, KT, 1024, 4, 2, true, MODE_MATRIX, 1>(L, lds, stream, nullptr);
+        case 7: return launch_one<KT, KT, 512, 8, 3, true, MODE_MATRIX, 1>(L, lds, stream, nullptr);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 size_t pass_lds_bytes(int shape_idx, int mode, int acc64, const PassLaunch& L) {
     PassShape s = kShapes[shape_idx];
     size_t b = sizeof(double) * 2 * (size_t)L.rows_per_wg;
@@ -316,6 +332,13 @@ hipError_t launch_pass(int k_dtype, int acc64, int mode, int shape_idx, const Pa
                        hipStream_t stream) {
     return dispatch_pass(k_dtype, acc64, mode, shape_idx, L, pass_lds_bytes(shape_idx, mode, acc64, L), stream,
                          nullptr);
+}
+
+hipError_t launch_pass_matrix(int k_dtype, int shape_idx, const PassLaunch& L, hipStream_t stream) {
+    const size_t lds = pass_lds_bytes(shape_idx, MODE_MATRIX, k_dtype == UOT_F64, L);
+    if (k_dtype == UOT_F64) return launch_matrix_typed<double>(shape_idx, L, lds, stream);
+    if (k_dtype == UOT_F32) return launch_matrix_typed<float>(shape_idx, L, lds, stream);
+    return hipErrorInvalidValue;
 }
 
 int pass_resident_per_cu(int k_dtype, int acc64, int mode, int shape_idx, size_t lds) {

@@ -179,10 +179,36 @@ struct Strip {
                 }
             }
             ur = (AT)uval;
+            if constexpr (MODE == MODE_MATRIX) {
+                if (tid == 0 && L.s_out) L.s_out[r0 + k] = uval * tot;
+            }
         } else {
             ur = (AT)row_in[k];
         }
-        if constexpr (kAcc) {
+        if constexpr (MODE == MODE_MATRIX) {
+            // The rescaled row x_ij beta_j alpha_i is written back in place and
+            // accumulated (its column sums give the next column factors).
+            static_assert(sizeof(KT) == sizeof(AT), "the in-place form keeps the storage type");
+            const uint32_t soff = (uint32_t)k * row_bytes;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                AT x[V];
+                Unpack<KT, AT>::run(buf[Q][c], x);
+                Raw z;
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    AT beta;
+                    if constexpr (VLDS) beta = (col[c] < m) ? vl[col[c] + e] : (AT)0;
+                    else beta = vv[c * V + e];
+                    if (ragged && col[c] + e >= m) x[e] = (AT)0;
+                    const AT y = (x[e] * beta) * ur;
+                    z[e] = y;
+                    acc[c * V + e] += y;
+                }
+                __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, z), rsrc, (int)(voff[c] + soff), 0,
+                                                       0);
+            }
+        } else if constexpr (kAcc) {
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 AT x[V];
@@ -199,6 +225,7 @@ struct Strip {
     template <int Q>
     __device__ __forceinline__ void process_batch(const PassLaunch& L, int kb, const AT* vl, const double* row_in,
                                                   const double* row_sh, double (*red)[NW * RB], int& slot) {
+        static_assert(MODE != MODE_MATRIX, "the in-place form runs the one-row shapes");
         const int tid = threadIdx.x;
         const int lane = tid & 63;
         const int wave = tid >> 6;
@@ -330,7 +357,7 @@ template <typename S, int MODE, bool VLDS, typename AT>
 __device__ __forceinline__ void stage_rows(const PassLaunch& L, int64_t r0, int nrows, double* row_in,
                                            double* row_sh) {
     for (int k = threadIdx.x; k < nrows; k += blockDim.x) {
-        if constexpr (MODE == MODE_FUSED || MODE == MODE_ROW) {
+        if constexpr (MODE == MODE_FUSED || MODE == MODE_ROW || MODE == MODE_MATRIX) {
             row_in[k] = L.a[r0 + k];
             row_sh[k] = L.fpot ? -(1.0 - L.fi) * L.fpot[r0 + k] * L.inv_eps : 0.0;
         } else {

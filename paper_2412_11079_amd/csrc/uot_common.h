@@ -236,7 +236,10 @@ __device__ __forceinline__ double stop_error(const double* bp, int nblocks, int 
 // ---------------------------------------------------------------------------
 // Pass kernels (pass.hip).
 // ---------------------------------------------------------------------------
-enum PassMode { MODE_FUSED = 0, MODE_ROW = 1, MODE_COL = 2, MODE_MARG = 3 };
+// MODE_MATRIX: the paper's literal in-place form -- the fused pass with v
+// holding the column factors, writing each row back multiplied by the column
+// factors and its row factor, and accumulating the rescaled entries.
+enum PassMode { MODE_FUSED = 0, MODE_ROW = 1, MODE_COL = 2, MODE_MARG = 3, MODE_MATRIX = 4 };
 
 struct PassLaunch {
     const void* K;
@@ -247,7 +250,7 @@ struct PassLaunch {
     const double* v;           // m
     const double* a;           // n
     double* u;                 // n
-    double* s_out;             // n (MODE_MARG)
+    double* s_out;             // n (MODE_MARG: K v; MODE_MATRIX: row sums of the rescaled rows, if set)
     void* partials;            // grid x ldp, FP32 or FP64
     int64_t ldp;
     double fi;
@@ -287,6 +290,8 @@ int pass_resident_per_cu(int k_dtype, int acc64, int mode, int shape_idx, size_t
 
 // Launch one streaming pass; returns hipSuccess or an error.  k_dtype and
 // acc64 select the instantiation; shape_idx indexes pass_shape().
+// The in-place matrix form (MODE_MATRIX) on a one-row shape; FP32 or FP64 storage.
+hipError_t launch_pass_matrix(int k_dtype, int shape_idx, const PassLaunch& L, hipStream_t stream);
 hipError_t launch_pass(int k_dtype, int acc64, int mode, int shape_idx, const PassLaunch& L,
                        hipStream_t stream);
 
@@ -468,6 +473,7 @@ struct ObjLaunch {
     double* u_tot;            // optional total u (may overflow to inf)
     double* v_tot;            // optional total v
     int32_t absorptions;      // absorptions performed (counted on the host)
+    int32_t info_only;        // write info only (no marginals or objective)
 };
 hipError_t launch_objective(const ObjLaunch& O, hipStream_t stream);
 
