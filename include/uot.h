@@ -270,6 +270,42 @@ uot_status uot_matrix_rescale(const uot_problem* prob, const uot_options* opt, c
                               void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * Kernel-free solve for a squared-Euclidean cost of points (Section 2.1's
+ * iteration in vector form, as uot_sinkhorn with opt->fused = 1): the
+ * Gibbs kernel K_ij = exp(-cost_scale ||x_i - y_j||^2 / eps) is recomputed
+ * inside every pass instead of being read from memory, so no n x m array
+ * exists and the per-iteration memory traffic is O(n + m) (the O(nm)
+ * traffic Sections 1 and 3 name as the bottleneck is gone; the pass is
+ * bounded by the vector ALU instead).  Each entry is formed from
+ * t = -cost_scale log2(e) ||x_i - y_j||^2 / eps, evaluated in FP64 as
+ * alpha_i + beta_j + x'_i . y_j, as 2^t = 2^rint(t) 2^(t - rint(t)), the
+ * fractional power by the hardware exp2 on its FP32 rounding (relative
+ * error about 1e-7 per entry, the size of an FP32 storage rounding of K);
+ * the products with v and u and the column partials are FP32 per lane,
+ * every reduction across lanes and workgroups FP64, as for an FP32 K.
+ *   prob: n, m, a, b, eps, tau (K, C, ldk, ldc, k_dtype, k_scale ignored)
+ *   x, y, dim   source points (n x dim) and target points (m x dim), FP64
+ *               row-major, contiguous, dim 2 or 3
+ *   cost_scale  > 0; the cost is cost_scale ||x_i - y_j||^2 (pass
+ *               1 / max_ij ||x_i - y_j||^2 to match a max-normalised cost)
+ *   opt: max_iter, tol, check_every, u0, v0 as uot_sinkhorn; fused = 1,
+ *     accum = UOT_ACC_F32, and no absorption, checkpoints or cooperative
+ *     loop (else UOT_ERR_UNSUPPORTED)
+ *   out: as uot_sinkhorn (u, v required; r, c, loss, info, f, g optional;
+ *     ckpt ignored)
+ * Rows of at most 8192 columns (m <= 8192, else UOT_ERR_UNSUPPORTED): a
+ * workgroup keeps the target points of a whole row on chip.
+ * Errors: UOT_ERR_ARG, UOT_ERR_ALIGN, UOT_ERR_WORKSPACE, UOT_ERR_UNSUPPORTED,
+ * UOT_ERR_HIP.  Workspace: uot_sinkhorn_points_workspace_size bytes (0 on
+ * invalid arguments).
+ */
+size_t uot_sinkhorn_points_workspace_size(const uot_problem* prob, int64_t dim, double cost_scale,
+                                          const uot_options* opt);
+uot_status uot_sinkhorn_points(const uot_problem* prob, const double* x, const double* y, int64_t dim,
+                               double cost_scale, const uot_options* opt, const uot_outputs* out,
+                               void* ws, size_t ws_bytes, void* stream);
+
+/*
  * For callers that cannot allocate (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): uot_sinkhorn without a
  * workspace argument.  Its scratch is a device array of the library,

@@ -228,6 +228,53 @@ def sinkhorn(a: torch.Tensor, b: torch.Tensor, K: Optional[torch.Tensor] = None,
     return res
 
 
+def sinkhorn_points(x: torch.Tensor, y: torch.Tensor, a: torch.Tensor, b: torch.Tensor, *, eps: float, tau: float,
+                    max_iter: int, cost_scale: float = 1.0, tol: float = 0.0, check_every: int = 1,
+                    u0: Optional[torch.Tensor] = None, v0: Optional[torch.Tensor] = None) -> SinkhornResult:
+    """Kernel-free solve for the cost ``cost_scale * ||x_i - y_j||^2`` of 2-D
+    or 3-D points (include/uot.h, uot_sinkhorn_points): K is recomputed in
+    every pass, never stored."""
+    device = a.device
+    n, m = a.shape[0], b.shape[0]
+    if x.dim() != 2 or y.dim() != 2 or x.shape[0] != n or y.shape[0] != m or x.shape[1] != y.shape[1]:
+        raise ValueError("x must be (n, d) and y (m, d) with the lengths of a and b")
+    dim = x.shape[1]
+    x = x.to(device=device, dtype=torch.float64).contiguous()
+    y = y.to(device=device, dtype=torch.float64).contiguous()
+    a = _vec64(a, "a", n, device)
+    b = _vec64(b, "b", m, device)
+    prob = _problem(a, b, None, None, m, eps, tau, device)
+    opt = _lib.Options()
+    opt.max_iter = int(max_iter)
+    opt.check_every = int(check_every)
+    opt.tol = float(tol)
+    opt.fused = 1
+    opt.accum = UOT_ACC_F32
+    opt.u0 = None if u0 is None else _vec64(u0, "u0", n, device).data_ptr()
+    opt.v0 = None if v0 is None else _vec64(v0, "v0", m, device).data_ptr()
+    L = _lib.lib()
+    need = L.uot_sinkhorn_points_workspace_size(ctypes.byref(prob), dim, float(cost_scale), ctypes.byref(opt))
+    if need == 0:
+        _lib.check(L.uot_sinkhorn_points(ctypes.byref(prob), _ptr(x), _ptr(y), dim, float(cost_scale),
+                                         ctypes.byref(opt), None, None, 0, None))
+    ws = _workspace(need, device)
+    u = torch.empty(n, dtype=torch.float64, device=device)
+    v = torch.empty(m, dtype=torch.float64, device=device)
+    r = torch.empty(n, dtype=torch.float64, device=device)
+    c = torch.empty(m, dtype=torch.float64, device=device)
+    loss = torch.empty((), dtype=torch.float64, device=device)
+    info = torch.zeros(ctypes.sizeof(_lib.Info), dtype=torch.uint8, device=device)
+    fpot = torch.empty(n, dtype=torch.float64, device=device)
+    gpot = torch.empty(m, dtype=torch.float64, device=device)
+    out = _lib.Outputs(u.data_ptr(), v.data_ptr(), r.data_ptr(), c.data_ptr(), loss.data_ptr(), info.data_ptr(),
+                       None, fpot.data_ptr(), gpot.data_ptr())
+    _lib.check(L.uot_sinkhorn_points(ctypes.byref(prob), _ptr(x), _ptr(y), dim, float(cost_scale),
+                                     ctypes.byref(opt), ctypes.byref(out), _ptr(ws), ws.numel(), _stream(device)))
+    res = SinkhornResult(u=u, v=v, r=r, c=c, loss=loss, info_raw=info, f=fpot, g=gpot)
+    res._keepalive = (ws, x, y, a, b)
+    return res
+
+
 @dataclass
 class MatrixResult:
     alpha: torch.Tensor       # (n,) last row factors

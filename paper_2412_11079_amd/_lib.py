@@ -67,6 +67,9 @@ SIGNATURES = {
     "uot_matrix_rescale_workspace_size": ([ctypes.POINTER(Problem), ctypes.POINTER(Options)], _sz),
     "uot_matrix_rescale": ([ctypes.POINTER(Problem), ctypes.POINTER(Options), ctypes.POINTER(Outputs), _vp, _sz,
                             _vp], _i32),
+    "uot_sinkhorn_points_workspace_size": ([ctypes.POINTER(Problem), _i64, _dbl, ctypes.POINTER(Options)], _sz),
+    "uot_sinkhorn_points": ([ctypes.POINTER(Problem), _vp, _vp, _i64, _dbl, ctypes.POINTER(Options),
+                             ctypes.POINTER(Outputs), _vp, _sz, _vp], _i32),
     "uot_sinkhorn_noalloc": ([ctypes.POINTER(Problem), ctypes.POINTER(Options), ctypes.POINTER(Outputs), _vp],
                              _i32),
     "uot_sinkhorn_profiled": ([ctypes.POINTER(Problem), ctypes.POINTER(Options), ctypes.POINTER(Outputs), _vp,

@@ -12,6 +12,7 @@
 
 #include "batch.h"
 #include "multi.h"
+#include "online.h"
 #include "plan.h"
 #include "uot_common.h"
 
@@ -230,6 +231,14 @@ int64_t max_lds_bytes() {
     if (hipGetDevice(&dev) != hipSuccess) return 65536;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 65536;
     return v;
+}
+
+// Compute units of the current device (256 when it cannot be queried).
+int64_t cu_count() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return 256;
+    return cus;
 }
 
 uot_status make_plan(const uot_problem* p, const uot_options* o, Plan& P, bool one_row = false) {
@@ -1105,6 +1114,188 @@ uot_status run_matrix(const uot_problem* p, const uot_options* o, const uot_outp
 }
 
 // ---------------------------------------------------------------------------
+// Kernel-free solve from points (the Gibbs kernel recomputed in every pass)
+// ---------------------------------------------------------------------------
+struct PtsPlan {
+    int32_t G;
+    int64_t rows_per_wg, ldp;
+    int32_t fin_blocks;
+    size_t off_ctrl, off_cprev, off_w, off_s, off_bp, off_part, off_rows, off_beta, off_loga, total;
+};
+
+uot_status make_points_plan(const uot_problem* p, int64_t dim, double cost_scale, const uot_options* o,
+                            PtsPlan& P) {
+    if (!p || !o) return fail(UOT_ERR_ARG, "problem and options must not be NULL");
+    if (p->n < 1 || p->m < 1) return fail(UOT_ERR_ARG, "empty problem (n=%lld, m=%lld)", (long long)p->n, (long long)p->m);
+    if (!p->a || !p->b) return fail(UOT_ERR_ARG, "a and b must not be NULL");
+    if (!aligned(p->a, 8) || !aligned(p->b, 8)) return fail(UOT_ERR_ALIGN, "a and b must be 8-byte aligned");
+    if (!(p->eps > 0.0) || !isfinite(p->eps)) return fail(UOT_ERR_ARG, "eps must be finite and > 0");
+    if (!(p->tau > 0.0)) return fail(UOT_ERR_ARG, "tau must be > 0 (or +inf)");
+    if (!(cost_scale > 0.0) || !isfinite(cost_scale)) return fail(UOT_ERR_ARG, "cost_scale must be finite and > 0");
+    if (dim != 2 && dim != 3) return fail(UOT_ERR_UNSUPPORTED, "point dimension %lld (2 or 3)", (long long)dim);
+    if (p->m > online_max_m())
+        return fail(UOT_ERR_UNSUPPORTED, "the kernel-free pass holds rows of up to %lld columns (m=%lld)",
+                    (long long)online_max_m(), (long long)p->m);
+    if (o->max_iter < 0) return fail(UOT_ERR_ARG, "max_iter must be >= 0");
+    if (o->absorb_log_threshold != 0.0 || o->checkpoint_every != 0 || o->persistent || !o->fused ||
+        o->accum != UOT_ACC_F32)
+        return fail(UOT_ERR_UNSUPPORTED,
+                    "the kernel-free solve runs the fused per-iteration pass with FP32 lane arithmetic: no "
+                    "absorption, checkpoints, cooperative loop or FP64 accumulation");
+    if (o->u0 && !aligned(o->u0, 8)) return fail(UOT_ERR_ALIGN, "u0 must be 8-byte aligned");
+    if (o->v0 && !aligned(o->v0, 8)) return fail(UOT_ERR_ALIGN, "v0 must be 8-byte aligned");
+    // As many workgroups as the compute units hold at once (the pass is
+    // ALU-bound: one wave of strips, no tail).
+    const int per_cu = std::max(1, online_wgs_per_cu((int)dim, p->m));
+    const int64_t target = std::min<int64_t>((int64_t)per_cu * cu_count(), p->n);
+    P.rows_per_wg = (p->n + target - 1) / target;
+    P.G = (int32_t)((p->n + P.rows_per_wg - 1) / P.rows_per_wg);
+    P.ldp = round_up(p->m, 64);
+    P.fin_blocks = finalize_blocks(p->m);
+    size_t off = 0;
+    P.off_ctrl = off; off = align_up(off + sizeof(Ctrl), kAlign);
+    P.off_cprev = off; off = align_up(off + sizeof(double) * p->m, kAlign);
+    P.off_w = off; off = align_up(off + sizeof(double) * p->m, kAlign);
+    P.off_s = off; off = align_up(off + sizeof(double) * p->n, kAlign);
+    P.off_bp = off; off = align_up(off + sizeof(double) * 2 * (size_t)P.fin_blocks, kAlign);
+    P.off_part = off; off = align_up(off + sizeof(float) * (size_t)P.G * P.ldp, kAlign);
+    P.off_rows = off; off = align_up(off + sizeof(double) * 4 * (size_t)p->n, kAlign);
+    P.off_beta = off; off = align_up(off + sizeof(double) * (size_t)p->m, kAlign);
+    P.off_loga = off; off = align_up(off + sizeof(double) * (size_t)p->n, kAlign);
+    P.total = off;
+    return UOT_OK;
+}
+
+uot_status run_points(const uot_problem* p, const double* x, const double* y, int64_t dim, double cost_scale,
+                      const uot_options* o, const uot_outputs* out, void* ws, size_t ws_bytes, hipStream_t stream) {
+    PtsPlan P;
+    uot_status st = make_points_plan(p, dim, cost_scale, o, P);
+    if (st != UOT_OK) return st;
+    if (!x || !y) return fail(UOT_ERR_ARG, "x and y must not be NULL");
+    if (!aligned(x, 8) || !aligned(y, 8)) return fail(UOT_ERR_ALIGN, "x and y must be 8-byte aligned");
+    if (!out || !out->u || !out->v) return fail(UOT_ERR_ARG, "outputs u and v are required");
+    if (!aligned(out->u, 8) || !aligned(out->v, 8)) return fail(UOT_ERR_ALIGN, "u and v must be 8-byte aligned");
+    if (ws_bytes < P.total || !ws) return fail(UOT_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", P.total, ws_bytes);
+    if (!aligned(ws, kAlign)) return fail(UOT_ERR_ALIGN, "workspace must be 256-byte aligned");
+    PinnedGuard pin;
+    if (o->tol > 0.0) UOT_HIP(pinned_acquire(pin.slot), "hipHostMalloc");
+    uint32_t* flag_host = o->tol > 0.0 ? pin.slot.flag() : nullptr;
+    char* base = (char*)ws;
+    Ctrl* ctrl = (Ctrl*)(base + P.off_ctrl);
+    double* cprev = (double*)(base + P.off_cprev);
+    double* wbuf = (double*)(base + P.off_w);
+    double* sbuf = (double*)(base + P.off_s);
+    double* bp = (double*)(base + P.off_bp);
+    void* part = base + P.off_part;
+    const double fi = fi_of(p->eps, p->tau);
+    double* rows = (double*)(base + P.off_rows);
+    double* beta = (double*)(base + P.off_beta);
+    double* loga = (double*)(base + P.off_loga);
+    const double c2 = cost_scale * 1.4426950408889634 / p->eps;      // log2(e) / eps
+    UOT_HIP(launch_init(out->u, p->n, o->u0, out->v, p->m, o->v0, cprev, ctrl, stream), "init");
+    UOT_HIP(launch_online_setup(x, y, p->a, p->n, p->m, (int)dim, c2, rows, beta, loga, stream), "point terms");
+
+    OnlineLaunch OL;
+    memset(&OL, 0, sizeof(OL));
+    PassLaunch& L = OL.P;
+    L.n = p->n;
+    L.m = p->m;
+    L.rows_per_wg = P.rows_per_wg;
+    L.grid = P.G;
+    L.v = out->v;
+    L.a = p->a;
+    L.u = out->u;
+    L.partials = part;
+    L.ldp = P.ldp;
+    L.fi = fi;
+    L.fi_is_one = (fi == 1.0);
+    L.inv_eps = 1.0 / p->eps;
+    L.ctrl = ctrl;
+    L.check_done = 1;
+    L.tol = o->tol;
+    L.fin_blocks = P.fin_blocks;
+    L.blockpart = bp;
+    L.k_scale = 1.0;
+    OL.y = y;
+    OL.rows = rows;
+    OL.beta = beta;
+    OL.loga = loga;
+    OL.dim = (int32_t)dim;
+
+    FinLaunch F;
+    memset(&F, 0, sizeof(F));
+    F.partials = part;
+    F.ldp = P.ldp;
+    F.G = P.G;
+    F.m = p->m;
+    F.b = p->b;
+    F.v = out->v;
+    F.w_out = wbuf;
+    F.cprev = cprev;
+    F.k_scale = 1.0;
+    F.fi = fi;
+    F.fi_is_one = (fi == 1.0);
+    F.inv_eps = 1.0 / p->eps;
+    F.ctrl = ctrl;
+    F.blockpart = bp;
+    F.acc64 = 0;
+
+    const int check_every = o->check_every > 0 ? o->check_every : 1;
+    int64_t iters_run = 0;
+    for (int t = 0; t < o->max_iter; ++t) {
+        OnlineLaunch O1 = OL;
+        O1.P.iter = t + 1;
+        O1.P.test_stop = 1;
+        UOT_HIP(launch_online(MODE_FUSED, O1, stream), "kernel-free pass");
+        UOT_HIP(launch_finalize(F, stream), "column finalize");
+        iters_run = t + 1;
+        if (flag_host && (t + 1) % check_every == 0 && t + 1 < o->max_iter) {
+            UOT_HIP(hipMemcpyAsync(flag_host, &ctrl->done, sizeof(uint32_t), hipMemcpyDeviceToHost, stream),
+                    "flag copy");
+            UOT_HIP(hipStreamSynchronize(stream), "flag sync");
+            if (*(volatile uint32_t*)flag_host) break;
+        }
+    }
+    // Marginals of the final scalings, then the objective.
+    {
+        OnlineLaunch OM = OL;
+        OM.P.check_done = 0;
+        OM.P.s_out = sbuf;
+        UOT_HIP(launch_online(MODE_MARG, OM, stream), "kernel-free marginal pass");
+        FinLaunch FM = F;
+        FM.marginal_only = 1;
+        FM.c_out = nullptr;
+        UOT_HIP(launch_finalize(FM, stream), "marginal finalize");
+    }
+    ObjLaunch O;
+    memset(&O, 0, sizeof(O));
+    O.u = out->u;
+    O.v = out->v;
+    O.s = sbuf;
+    O.w = wbuf;
+    O.a = p->a;
+    O.b = p->b;
+    O.n = p->n;
+    O.m = p->m;
+    O.eps = p->eps;
+    O.tau = p->tau;
+    O.tau_inf = isinf(p->tau) ? 1 : 0;
+    O.r_out = out->r;
+    O.c_out = out->c;
+    O.loss = out->loss;
+    O.info = out->info;
+    O.ctrl = ctrl;
+    O.tol = o->tol;
+    O.iters_run = iters_run;
+    O.f_out = out->f;
+    O.g_out = out->g;
+    O.blockpart = bp;
+    O.fin_blocks = P.fin_blocks;
+    UOT_HIP(launch_objective(O, stream), "objective");
+    return UOT_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Implicit (envelope) backward: marginal passes only
 // ---------------------------------------------------------------------------
 struct ImpPlan {
@@ -1950,6 +2141,19 @@ uot_status uot_sinkhorn_backward(const uot_problem* prob, const uot_options* opt
                                  double* grad_x, double* grad_y, void* ws, size_t ws_bytes, void* stream) {
     return run_backward(prob, opt, u, v, ckpt, grad_loss, grad_a, grad_b, grad_C, ldgc, x, y, dim, grad_x, grad_y,
                         ws, ws_bytes, (hipStream_t)stream);
+}
+
+size_t uot_sinkhorn_points_workspace_size(const uot_problem* prob, int64_t dim, double cost_scale,
+                                          const uot_options* opt) {
+    PtsPlan P;
+    if (make_points_plan(prob, dim, cost_scale, opt, P) != UOT_OK) return 0;
+    return P.total;
+}
+
+uot_status uot_sinkhorn_points(const uot_problem* prob, const double* x, const double* y, int64_t dim,
+                               double cost_scale, const uot_options* opt, const uot_outputs* out, void* ws,
+                               size_t ws_bytes, void* stream) {
+    return run_points(prob, x, y, dim, cost_scale, opt, out, ws, ws_bytes, (hipStream_t)stream);
 }
 
 size_t uot_matrix_rescale_workspace_size(const uot_problem* prob, const uot_options* opt) {

@@ -1,0 +1,30 @@
+// Internal declarations of the kernel-free pass (online.hip).
+#pragma once
+
+#include "uot_common.h"
+
+namespace uot {
+
+struct OnlineLaunch {
+    PassLaunch P;             // strip, scalings, partials, stopping test (K, ldk unused)
+    const double* y;          // m x dim target points
+    const double* rows;       // n x 4: x'_i (2 c x_i, zero-padded to 3) and alpha_i = -c |x_i|^2
+    const double* beta;       // m: beta_j = -c |y_j|^2
+    const double* loga;       // n: log a_i (0 where a_i = 0)
+    int32_t dim;              // 2 or 3
+};
+
+// Rows of at most online_max_m() columns.
+int64_t online_max_m();
+constexpr int kOnlineWG = 512;   // lanes per workgroup of the kernel-free pass
+// Workgroups of the pass for rows of m columns that one compute unit holds.
+int online_wgs_per_cu(int dim, int64_t m);
+// Row and column terms of the exponent (rows, beta above) from the points
+// and log a,
+// c = cost_scale log2(e) / eps; once per solve.
+hipError_t launch_online_setup(const double* x, const double* y, const double* a, int64_t n, int64_t m, int dim,
+                               double c, double* rows, double* beta, double* loga, hipStream_t stream);
+// One pass; mode MODE_FUSED or MODE_MARG.
+hipError_t launch_online(int mode, const OnlineLaunch& O, hipStream_t stream);
+
+}  // namespace uot

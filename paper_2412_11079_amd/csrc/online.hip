@@ -1,0 +1,242 @@
+// Kernel-free ("online") fused pass for a squared-Euclidean cost of 2-D or
+// 3-D points: the iteration of Section 2.1 (vector form, rows first) with
+// the Gibbs kernel recomputed in registers instead of streamed from HBM.
+// The O(nm) memory traffic the paper identifies as the barrier (Sections 1
+// and 3) disappears; what remains is arithmetic, so the pass is bounded by
+// the vector ALU (VALU), not by HBM.
+//
+// Entry (i, j), in log2 units with exact FP64 arithmetic:
+//   t_ij = -C_ij log2(e) / eps = alpha_i + beta_j + sum_d x'_id y_jd,
+//   alpha_i = -|x_i|^2 c,  beta_j = -|y_j|^2 c,  x'_i = 2 c x_i,  c = cost_scale log2(e) / eps,
+// then K_ij = 2^t_ij = 2^k 2^f with k = rint(t_ij) and f = t_ij - k in
+// [-1/2, 1/2] (exact in FP64): 2^f by the hardware exp2 on the FP32
+// rounding of f (relative error ~1e-7, the size of an FP32 storage
+// rounding of K), 2^k by ldexp.  An FP32 argument would not do: t reaches
+// hundreds, and its rounding alone would move K by ~1e-5.
+//
+// Workgroup: 512 lanes owning a strip of rows; lane l holds the columns
+// j = l + 512 c (c < CPL, m <= 512 CPL) in registers: coordinates and beta
+// in FP64, v and the column partials in FP32.  Rows are taken R at a time
+// (column-outer, row-inner, so each column's data serves R independent
+// exponent chains): the R rows' K values are formed and dotted with v, the
+// R row totals are reduced over the wave (FP64) and met in one LDS exchange
+// and barrier (fixed order), lanes 0..R-1 of every wave form the R scalings
+// u_i = (a_i / total_i)^fi at once, and a lane broadcast hands them to
+// every lane, which accumulates the R rows into its column partials.  The
+// column finalize sums the partials as for a stored K.  Row terms (x'_i,
+// alpha_i) are wave-uniform and read by scalar loads.
+#include "online.h"
+#include "scalemath.h"
+#include "strip.h"
+
+namespace uot {
+
+__global__ void online_setup_kernel(const double* __restrict__ x, const double* __restrict__ y,
+                                    const double* __restrict__ a, int64_t n, int64_t m, int dim, double c,
+                                    double* __restrict__ rows, double* __restrict__ beta,
+                                    double* __restrict__ loga) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) {
+        const double ai = a[t];
+        loga[t] = ai > 0.0 ? log(ai) : 0.0;
+        double xd[3] = {0.0, 0.0, 0.0}, nx = 0.0;
+        for (int d = 0; d < dim; ++d) {
+            xd[d] = x[t * dim + d];
+            nx = fma(xd[d], xd[d], nx);
+        }
+        for (int d = 0; d < 3; ++d) rows[4 * t + d] = 2.0 * c * xd[d];
+        rows[4 * t + 3] = -c * nx;
+    } else if (t - n < m) {
+        const int64_t j = t - n;
+        double ny = 0.0;
+        for (int d = 0; d < dim; ++d) ny = fma(y[j * dim + d], y[j * dim + d], ny);
+        beta[j] = -c * ny;
+    }
+}
+
+// BL: beta and v of the lane's columns sit in LDS (read once per group of R
+// rows) instead of registers, for 16 columns per lane.
+template <int DIM, int CPL, int R, int MODE, bool BL>
+__global__ __launch_bounds__(kOnlineWG) void online_kernel(OnlineLaunch O, const double* __restrict__ rows,
+                                                           const double* __restrict__ beta) {
+    static_assert(MODE == MODE_FUSED || MODE == MODE_MARG, "online fused or marginal pass");
+    static_assert(R >= 1 && R <= 64, "rows per group");
+    constexpr int WG = kOnlineWG;
+    constexpr int NW = WG / 64;
+    const PassLaunch& L = O.P;
+    __shared__ double red[2][R][NW];
+    __shared__ uint32_t exit_sh;
+    extern __shared__ __align__(16) double on_lds[];    // BL: beta (WG CPL), then v (WG CPL, FP32)
+
+    if (pass_exit(L, &exit_sh)) return;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * L.rows_per_wg;
+    int64_t r1 = r0 + L.rows_per_wg;
+    if (r1 > L.n) r1 = L.n;
+    const int nrows = (int)(r1 - r0);
+    const int64_t m = L.m;
+
+    // The lane's columns (columns past m: a copy of the last one, v = 0).
+    double yc[CPL][DIM], bc[BL ? 1 : CPL];
+    float vc[BL ? 1 : CPL], acc[CPL];
+    double* bl = on_lds;
+    float* vl = (float*)(on_lds + (BL ? WG * CPL : 0));
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+        const int64_t j = (int64_t)c * WG + tid;
+        const int64_t jj = j < m ? j : m - 1;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) yc[c][d] = O.y[jj * DIM + d];
+        if constexpr (BL) {
+            bl[c * WG + tid] = beta[jj];
+            vl[c * WG + tid] = j < m ? (float)L.v[j] : 0.0f;
+        } else {
+            bc[c] = beta[jj];
+            vc[c] = j < m ? (float)L.v[j] : 0.0f;
+        }
+        acc[c] = 0.0f;
+    }
+
+    int slot = 0;
+    for (int k = 0; k < nrows; k += R) {
+        const int nr = nrows - k < R ? nrows - k : R;
+        // Row terms of the group (rows past the strip repeat its last row;
+        // their scaling is 0, so they add nothing).
+        double xr[R][DIM], al[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t i = r0 + k + (r < nr ? r : nr - 1);
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) xr[r][d] = rows[4 * i + d];
+            al[r] = rows[4 * i + 3];
+        }
+        float kv[R][CPL], s[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) s[r] = 0.0f;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            // Each lane reads only the LDS words it wrote: no barrier needed.
+            const double bcc = BL ? bl[c * WG + tid] : bc[BL ? 0 : c];
+            const float vcc = BL ? vl[c * WG + tid] : vc[BL ? 0 : c];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                double t = al[r] + bcc;
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) t = fma(xr[r][d], yc[c][d], t);
+                const double kf = __builtin_rint(t);
+                const float f = (float)(t - kf);
+                const float e = __builtin_ldexpf(__builtin_amdgcn_exp2f(f), (int)fmax(kf, -1000.0));
+                kv[r][c] = e;
+                s[r] = fmaf(e, vcc, s[r]);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double d = wave_sum_f64((double)s[r]);
+            if (lane == 0) red[slot][r][wave] = d;
+        }
+        __syncthreads();
+        // Lane r (< nr) of every wave: row total in a fixed order, then u.
+        double uu = 0.0;
+        if (lane < nr) {
+            double tot = 0.0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) tot += red[slot][lane][w];
+            const int64_t i = r0 + k + lane;
+            if constexpr (MODE == MODE_MARG) {
+                uu = L.u[i];
+                if (wave == 0) L.s_out[i] = tot;
+            } else {
+                const double ai = L.a[i];
+                uu = ai == 0.0 ? 0.0 : L.fi_is_one ? ai / tot : sm::scaling_pow(O.loga[i], tot, L.fi);
+                if (wave == 0) {
+                    L.u[i] = uu;
+                    if (ai > 0.0 && !(tot > 0.0)) atomicOr(&L.ctrl->flags, UOT_FLAG_ZERO_SUM);
+                    if (!isfinite(uu)) atomicOr(&L.ctrl->flags, UOT_FLAG_NONFINITE);
+                }
+            }
+        }
+        slot ^= 1;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const float fr = (float)readlane_f64(uu, r);
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) acc[c] = fmaf(kv[r][c], fr, acc[c]);
+        }
+    }
+    float* P = (float*)L.partials + (int64_t)blockIdx.x * L.ldp;
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+        const int64_t j = (int64_t)c * WG + tid;
+        if (j < m) __builtin_nontemporal_store(acc[c], &P[j]);
+    }
+}
+
+hipError_t launch_online_setup(const double* x, const double* y, const double* a, int64_t n, int64_t m, int dim,
+                               double c, double* rows, double* beta, double* loga, hipStream_t stream) {
+    const int64_t total = n + m;
+    const int64_t blocks = (total + 255) / 256;
+    hipLaunchKernelGGL(online_setup_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, x, y, a, n, m, dim, c,
+                       rows, beta, loga);
+    return hipGetLastError();
+}
+
+// Columns per lane (CPL) and rows per group (R) for rows of m columns: the
+// R CPL K values of a group stay in registers until its scalings are known.
+#define UOT_ONLINE_SHAPES(DIM, X)                   \
+    if (m <= 512) X(DIM, 1, 8, false);              \
+    else if (m <= 1024) X(DIM, 2, 8, false);        \
+    else if (m <= 2048) X(DIM, 4, 8, false);        \
+    else if (m <= 4096) X(DIM, 8, 8, false);        \
+    else X(DIM, 16, (DIM == 3 ? 3 : 4), true)
+
+// Dynamic LDS of the pass for rows of m columns.
+static size_t online_lds(int64_t m) { return m > 4096 ? (size_t)kOnlineWG * 16 * (8 + 4) : 0; }
+
+int64_t online_max_m() { return 16 * kOnlineWG; }
+
+int online_wgs_per_cu(int dim, int64_t m) {
+    int nb = 0;
+    hipError_t e = hipSuccess;
+#define UOT_OCC(DIM, CPL, R, BL)                                                                           \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, online_kernel<DIM, CPL, R, MODE_FUSED, BL>, kOnlineWG, \
+                                                     online_lds(m))
+    if (dim == 2) {
+        UOT_ONLINE_SHAPES(2, UOT_OCC);
+    } else {
+        UOT_ONLINE_SHAPES(3, UOT_OCC);
+    }
+#undef UOT_OCC
+    return e == hipSuccess ? nb : 0;
+}
+
+hipError_t launch_online(int mode, const OnlineLaunch& O, hipStream_t stream) {
+    const int64_t m = O.P.m;
+    if ((O.dim != 2 && O.dim != 3) || m > online_max_m() || (mode != MODE_FUSED && mode != MODE_MARG))
+        return hipErrorInvalidValue;
+    const size_t lds = online_lds(m);
+#define UOT_LAUNCH(DIM, CPL, R, BL)                                                                             \
+    do {                                                                                                        \
+        auto kf = online_kernel<DIM, CPL, R, MODE_FUSED, BL>;                                                   \
+        auto km = online_kernel<DIM, CPL, R, MODE_MARG, BL>;                                                    \
+        auto kk = mode == MODE_FUSED ? kf : km;                                                                 \
+        if (lds > 65536) {                                                                                      \
+            hipError_t ea = hipFuncSetAttribute((const void*)kk, hipFuncAttributeMaxDynamicSharedMemorySize,   \
+                                                (int)lds);                                                      \
+            if (ea != hipSuccess) return ea;                                                                    \
+        }                                                                                                       \
+        hipLaunchKernelGGL(kk, dim3(O.P.grid), dim3(kOnlineWG), lds, stream, O, O.rows, O.beta);               \
+    } while (0)
+    if (O.dim == 2) {
+        UOT_ONLINE_SHAPES(2, UOT_LAUNCH);
+    } else {
+        UOT_ONLINE_SHAPES(3, UOT_LAUNCH);
+    }
+#undef UOT_LAUNCH
+    return hipGetLastError();
+}
+
+}  // namespace uot

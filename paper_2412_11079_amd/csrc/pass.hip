@@ -35,11 +35,10 @@ template <typename KT, typename AT, int WG, int NC, int D, bool VLDS, int MODE, 
 __global__ __launch_bounds__(WG) void pass_kernel(PassLaunch L) {
     using S = Strip<KT, AT, WG, NC, D, VLDS, MODE, RB>;
     __shared__ double red[2][S::NW * RB];
-    __shared__ double err_sh;
+    __shared__ uint32_t exit_sh;
     extern __shared__ __align__(16) unsigned char dyn_lds[];
 
-    if (L.check_done && ld_volatile_u32(&L.ctrl->done)) return;
-    if (L.test_stop && stop_test(L, L.iter, &err_sh)) return;
+    if (pass_exit(L, &exit_sh)) return;
 
     const int64_t r0 = (int64_t)blockIdx.x * L.rows_per_wg;
     int64_t r1 = r0 + L.rows_per_wg;

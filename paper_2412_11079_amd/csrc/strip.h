@@ -394,6 +394,35 @@ __device__ __forceinline__ void stage_v(const double* v, int64_t m, AT* vl) {
 
 // Stopping test of the previous iteration (see PassLaunch): identical in
 // every workgroup.  Returns true when the loop is to stop.
+// Early exit of a per-iteration pass launch, the same for every wave of the
+// workgroup.  The stop flag can change during a launch only when that launch
+// applies the stopping test (block 0 then sets it), so in that case wave 0
+// alone reads the flag and evaluates the test, and one barrier hands the
+// decision to the other waves; otherwise the flag is fixed for the whole
+// launch and every wave reads it directly.
+__device__ __forceinline__ bool pass_exit(const PassLaunch& L, uint32_t* exit_sh) {
+    const bool test = L.test_stop && L.tol > 0.0 && L.iter > 1;
+    if (!test) return L.check_done && ld_volatile_u32(&L.ctrl->done) != 0;
+    if (threadIdx.x < 64) {
+        const uint32_t flag = L.check_done ? ld_volatile_u32(&L.ctrl->done) : 0u;
+        bool quit = __builtin_amdgcn_readfirstlane(flag) != 0;
+        if (!quit) {
+            const double err = stop_error(L.blockpart, L.fin_blocks, threadIdx.x);
+            quit = err <= L.tol;
+            if (quit && blockIdx.x == 0 && threadIdx.x == 0) {
+                L.ctrl->iters = L.iter - 1;
+                L.ctrl->err = err;
+                L.ctrl->done = 1;
+            }
+        }
+        if (threadIdx.x == 0) *exit_sh = quit ? 1u : 0u;
+    }
+    __syncthreads();
+    return *exit_sh != 0;
+}
+
+// Stopping test of the cooperative loop: every wave of every workgroup
+// evaluates it at the same point (no early flag read).
 __device__ __forceinline__ bool stop_test(const PassLaunch& L, int64_t iter, double* err_sh) {
     if (!(L.tol > 0.0) || iter <= 1) return false;
     if ((threadIdx.x >> 6) == 0) {

@@ -1,0 +1,173 @@
+"""Kernel-free solve (uot_sinkhorn_points): the Gibbs kernel of a
+squared-Euclidean point cost recomputed inside every pass, never stored,
+against the FP64 oracle run on the dense kernel of the same cost.
+
+Bar: 1e-6 relative on u, v and the objective, the bar of an FP32-stored K:
+each recomputed entry carries a relative error of about 1e-7 (the FP32
+rounding of the fractional exponent fed to the hardware exp2), the size of
+an FP32 storage rounding, and the lane arithmetic is FP32 as for an FP32 K.
+Shapes cover every column layout of the pass (1, 2, 4, 8 and 16 columns
+per lane), row counts that leave a partial row group at the end of a
+strip, a single row and column, and the full-size 2-D and 3-D workloads."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from gpu_helpers import compare, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+import paper_2412_11079_amd as uot  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    say(f"libuot: {uot.lib_path()}")
+
+
+def _max_sqdist(x, y) -> float:
+    """max_ij ||x_i - y_j||^2 by brute force in row blocks (test-side input
+    preparation: the scale a max-normalised cost divides by)."""
+    best = 0.0
+    for i0 in range(0, x.shape[0], 512):
+        d = x[i0:i0 + 512, None, :] - y[None, :, :]
+        best = max(best, float(np.max(np.einsum("ijk,ijk->ij", d, d))))
+    return best
+
+
+def _oracle(prob, scale, max_iter, tol=0.0):
+    C = oracle.cost_points(prob.x, prob.y, 0, False) * scale
+    K = oracle.kernel(C, prob.eps)
+    return oracle.sinkhorn(K, prob.a, prob.b, prob.eps, prob.tau, max_iter, tol)
+
+
+def _gpu(prob, scale, max_iter, tol=0.0, check_every=1, a=None):
+    res = uot.sinkhorn_points(to_dev(prob.x), to_dev(prob.y), to_dev(prob.a if a is None else a),
+                              to_dev(prob.b), eps=prob.eps, tau=prob.tau, max_iter=max_iter, cost_scale=scale,
+                              tol=tol, check_every=check_every)
+    torch.cuda.synchronize()
+    return res
+
+
+@pytest.mark.parametrize("n,m,d", [(1000, 777, 2), (1001, 1024, 3), (257, 1500, 2), (700, 2048, 3),
+                                   (1000, 3001, 3), (513, 4096, 2), (1000, 5000, 3), (300, 8192, 2),
+                                   (5001, 2500, 3), (1, 1, 2), (5, 8191, 3), (3, 4097, 2), (700, 300, 3),
+                                   (64, 512, 2), (2999, 8000, 3)])
+def test_ragged_shapes_against_oracle(n, m, d):
+    prob = workloads.random_small(n, m, seed=7000 + n + m + d, eps=0.02, tau=1.0, d=d, max_iter=30)
+    say(f"kernel-free n={n} m={m} d={d}")
+    ref = _oracle(prob, 1.0, 30)
+    res = _gpu(prob, 1.0, 30)
+    info = res.info()
+    assert info["iters"] == 30 and info["flags"] == 0, info
+    compare(res, ref, 1e-6, 1e-6, f"kernel-free {n}x{m} d={d}")
+    np.testing.assert_allclose(res.r.cpu().numpy(), ref.r, rtol=1e-6, atol=0)
+    np.testing.assert_allclose(res.c.cpu().numpy(), ref.c, rtol=1e-6, atol=0)
+
+
+def test_max_normalised_cost_and_balanced_limit():
+    """A max-normalised 3-D mixture cost (the shape of the headline
+    workload, cut to 2000 x 6000) with tau finite and tau = inf."""
+    for tau in (0.5, math.inf):
+        prob = workloads.headline(n=2000, m=6000, max_iter=40)
+        prob.tau = tau
+        scale = 1.0 / _max_sqdist(prob.x, prob.y)
+        say(f"mixture 2000x6000 tau={tau} scale={scale:.6f}")
+        ref = _oracle(prob, scale, 40)
+        res = _gpu(prob, scale, 40)
+        assert res.info()["flags"] == 0
+        compare(res, ref, 1e-6, 1e-6, f"mixture tau={tau}")
+
+
+def test_tolerance_stop_matches_oracle_iteration():
+    prob = workloads.random_small(900, 1100, seed=7101, eps=0.05, tau=1.0, d=2)
+    ref = _oracle(prob, 1.0, 3000, tol=1e-6)
+    assert 10 < ref.iters < 3000
+    for every in (1, 4):
+        res = _gpu(prob, 1.0, 3000, tol=1e-6, check_every=every)
+        info = res.info()
+        say(f"  check_every={every}: GPU {info['iters']} iterations, oracle {ref.iters}")
+        assert info["iters"] == ref.iters and info["err"] <= 1e-6 and info["flags"] == 0
+        compare(res, ref, 1e-6, 1e-6, f"tol stop every={every}")
+
+
+def test_zero_mass_rows_and_not_converged_flag():
+    prob = workloads.random_small(600, 700, seed=7102, eps=0.05, tau=1.0, d=3)
+    a = prob.a.copy()
+    a[::7] = 0.0
+    prob.a = a
+    ref = _oracle(prob, 1.0, 20)
+    res = _gpu(prob, 1.0, 20, a=a)
+    u = res.u.cpu().numpy()
+    assert np.all(u[::7] == 0.0)
+    compare(res, ref, 1e-6, 1e-6, "zero-mass rows")
+    res = _gpu(prob, 1.0, 3, tol=1e-12)
+    info = res.info()
+    assert info["iters"] == 3 and info["flags"] & uot.UOT_FLAG_NOT_CONVERGED
+
+
+def test_bitwise_reproducible():
+    prob = workloads.random_small(3000, 5000, seed=7103, eps=0.02, tau=1.0, d=3)
+    r1 = _gpu(prob, 1.0, 15)
+    r2 = _gpu(prob, 1.0, 15)
+    assert torch.equal(r1.u, r2.u) and torch.equal(r1.v, r2.v) and torch.equal(r1.loss, r2.loss)
+
+
+def test_agrees_with_the_stored_fp32_kernel():
+    """Same problem through the streamed FP32 K (built from the dense cost):
+    both are within the FP32 bar of the oracle, hence of each other."""
+    prob = workloads.random_small(2000, 3000, seed=7104, eps=0.02, tau=0.5, d=3, max_iter=50)
+    x, y = to_dev(prob.x), to_dev(prob.y)
+    C = uot.cost_from_points(x, y, 0, False)
+    K = uot.kernel_from_cost(C, prob.eps, torch.float32)
+    st = uot.sinkhorn(to_dev(prob.a), to_dev(prob.b), K, m=prob.m, eps=prob.eps, tau=prob.tau, max_iter=50)
+    on = _gpu(prob, 1.0, 50)
+    for name in ("u", "v"):
+        p, q = getattr(on, name).cpu().numpy(), getattr(st, name).cpu().numpy()
+        e = float(np.max(np.abs(p / q - 1.0)))
+        say(f"  kernel-free vs stored FP32 {name}: {e:.3e}")
+        assert e < 2e-6
+
+
+def test_argument_errors():
+    prob = workloads.random_small(10, 20, seed=7105, d=3)
+    a, b = to_dev(prob.a), to_dev(prob.b)
+    x, y = to_dev(prob.x), to_dev(prob.y)
+    with pytest.raises(uot.UOTError, match="8192"):
+        uot.sinkhorn_points(x, to_dev(np.zeros((8193, 3))), a, to_dev(np.ones(8193)), eps=0.1, tau=1.0,
+                            max_iter=1)
+    with pytest.raises(uot.UOTError, match="dimension"):
+        uot.sinkhorn_points(to_dev(np.zeros((10, 4))), to_dev(np.zeros((20, 4))), a, b, eps=0.1, tau=1.0,
+                            max_iter=1)
+    with pytest.raises(uot.UOTError, match="cost_scale"):
+        uot.sinkhorn_points(x, y, a, b, eps=0.1, tau=1.0, max_iter=1, cost_scale=0.0)
+    with pytest.raises(uot.UOTError, match="eps"):
+        uot.sinkhorn_points(x, y, a, b, eps=0.0, tau=1.0, max_iter=1)
+
+
+def test_plain_2d_workload_full_size():
+    """The plain 2-D workload (1024 x 1024, uniform points, eps 0.05,
+    tau 1, 100 iterations) recomputing K in every pass."""
+    prob = workloads.plain_fp64()
+    ref = _oracle(prob, 1.0, prob.max_iter)
+    res = _gpu(prob, 1.0, prob.max_iter)
+    assert res.info()["flags"] == 0
+    compare(res, ref, 1e-6, 1e-6, "plain 1024^2 2-D")
+
+
+def test_differentiation_workload_forward_full_size():
+    """The 3-D differentiation workload's forward solve (8192 x 8192, unit
+    cube, target shifted by 0.2, eps 0.02, tau 1) at full size, 50
+    iterations, element by element against the oracle."""
+    prob = workloads.grad()
+    say("8192^2 3-D, 50 iterations: oracle on the host ...")
+    ref = _oracle(prob, 1.0, 50)
+    say("  GPU ...")
+    res = _gpu(prob, 1.0, 50)
+    assert res.info()["flags"] == 0
+    compare(res, ref, 1e-6, 1e-6, "8192^2 3-D")
