@@ -14,7 +14,10 @@ Prints ONE JSON line (rank 0).  Besides the contract fields it carries:
   fwd_bwd       forward + reverse pass of the differentiation workload;
   batched       1024 uneven problems in one persistent launch;
   multi         256 histogram pairs sharing one 8192^2 kernel (matrix cores);
-  precision     65536 x 8192 with BF16 / FP8 / FP32 K and absorption.
+  precision     65536 x 8192 with BF16 / FP8 / FP32 K and absorption;
+  kernel_free   the kernel-free solve (K recomputed in every pass) on the
+                3-D differentiation and 2-D plain workloads, against the
+                streamed FP32 K at the same shapes, with its ALU roofline.
 """
 from __future__ import annotations
 
@@ -51,6 +54,7 @@ def parse():
     p.add_argument("--no-batched", action="store_true", help="skip the batched-problems timing")
     p.add_argument("--no-multi", action="store_true", help="skip the multi-right-hand-side timing")
     p.add_argument("--no-precision", action="store_true", help="skip the low-precision timing")
+    p.add_argument("--no-kernel-free", action="store_true", help="skip the kernel-free solve timing")
     p.add_argument("--only", default="", help="comma list of sections to run alone (profiling)")
     p.add_argument("--cpu-leg", type=int, default=0, help=argparse.SUPPRESS)
     p.add_argument("--cpu-rows", type=int, default=0, help=argparse.SUPPRESS)
@@ -103,7 +107,8 @@ def main():
     torch.cuda.set_device(0)
 
     if args.only:
-        sections = {"grad": fwd_bwd, "batched": batched, "multi": multi, "precision": precision}
+        sections = {"grad": fwd_bwd, "batched": batched, "multi": multi, "precision": precision,
+                    "kernel_free": kernel_free}
         res = {k: sections[k](uot, workloads, torch, dev, args) for k in args.only.split(",")}
         print(json.dumps(res), flush=True)
         return
@@ -204,6 +209,8 @@ def main():
         out["multi"] = multi(uot, workloads, torch, dev, args)
     if not args.no_precision:
         out["precision"] = precision(uot, workloads, torch, dev, args)
+    if not args.no_kernel_free:
+        out["kernel_free"] = kernel_free(uot, workloads, torch, dev, args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)
@@ -313,6 +320,76 @@ def fwd_bwd(uot, workloads, torch, dev, args):
             "cost_grad_tflop_s": round(2.0 * prob.n * prob.m * (2 * prob.max_iter + 2) / ((c_ms - b_ms) * 1e-3) / 1e12, 2)
             if c_ms > b_ms else None,
             "k_passes": passes, "k_bytes_tb_s": round(passes * kb / ((f_ms + b_ms) * 1e-3) / 1e12, 3)}
+
+
+# VALU issue slots per entry of the kernel-free pass (FP64 exponent: one
+# add and one FMA per coordinate, rint, subtract, FP32 conversion, clamp and
+# integer conversion; exp2, which issues at half rate, counts two; ldexp;
+# the row-dot and column FMAs), and the chip's lane-slot rate:
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
+KF_SLOTS_PER_ENTRY = {2: 13, 3: 14}
+LANE_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
+
+
+def kernel_free(uot, workloads, torch, dev, args):
+    """Kernel-free solve (K recomputed from the points in every pass) on the
+    differentiation workload's forward problem (8192^2, 3-D, eps 0.02, 500
+    iterations) and the plain 2-D workload (1024^2, eps 0.05, 100
+    iterations), against the streamed FP32 K on the same problems (cost and
+    kernel build included, as the kernel-free solve includes its setup).
+    Per-iteration time from two solves of T and 2T iterations (setup
+    cancels); it covers the pass and the column finalize, so the ALU
+    fraction is a lower bound."""
+    import numpy as np
+    out = {}
+    for key, prob, T in (("diff_8192x8192_3d", workloads.grad(), 500), ("plain_1024x1024_2d", workloads.plain_fp64(), 100)):
+        x = torch.from_numpy(prob.x).to(dev)
+        y = torch.from_numpy(prob.y).to(dev)
+        a = torch.from_numpy(prob.a).to(dev)
+        b = torch.from_numpy(prob.b).to(dev)
+        d = prob.x.shape[1]
+
+        def online(T_):
+            return uot.sinkhorn_points(x, y, a, b, eps=prob.eps, tau=prob.tau, max_iter=T_)
+
+        def streamed(T_):
+            C = uot.cost_from_points(x, y, prob.cost_kind, prob.normalize_max)
+            K = uot.kernel_from_cost(C, prob.eps, torch.float32)
+            del C
+            return uot.sinkhorn(a, b, K, m=prob.m, eps=prob.eps, tau=prob.tau, max_iter=T_)
+
+        def timed(fn, T_):
+            fn(3)
+            torch.cuda.synchronize()
+            e0, e1 = _events(torch)
+            e0.record()
+            r = fn(T_)
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1), r
+
+        ms_on, r_on = timed(online, T)
+        ms_on2, _ = timed(online, 2 * T)
+        ms_st, r_st = timed(streamed, T)
+        ms_st2, _ = timed(streamed, 2 * T)
+        assert r_on.info()["flags"] == 0 and r_st.info()["flags"] == 0
+        it_on = (ms_on2 - ms_on) / T * 1e3
+        it_st = (ms_st2 - ms_st) / T * 1e3
+        ent = prob.n * prob.m
+        eps_ach = ent / (it_on * 1e-6)
+        peak = LANE_SLOTS_PER_S / KF_SLOTS_PER_ENTRY[d]
+        du = float(np.max(np.abs(r_on.u.cpu().numpy() / r_st.u.cpu().numpy() - 1.0)))
+        out[key] = {
+            "workload": f"{prob.n}x{prob.m} {d}-D points, eps={prob.eps}, tau={prob.tau}, {T} iterations",
+            "solve_ms": round(ms_on, 3), "streamed_fp32_solve_ms": round(ms_st, 3),
+            "iter_us": round(it_on, 2), "streamed_fp32_iter_us": round(it_st, 2),
+            "speedup_solve_over_streamed": round(ms_st / ms_on, 3),
+            "u_rel_diff_vs_streamed": float(f"{du:.3e}"),
+            "roofline": {"bound": "alu", "achieved": round(eps_ach / 1e9, 1), "peak": round(peak / 1e9, 1),
+                         "unit": "Gentries/s", "frac": round(eps_ach / peak, 4),
+                         "slots_per_entry": KF_SLOTS_PER_ENTRY[d], "traffic": None},
+        }
+    return out
 
 
 def _events(torch, n=2):

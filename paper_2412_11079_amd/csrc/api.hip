@@ -1145,9 +1145,11 @@ uot_status make_points_plan(const uot_problem* p, int64_t dim, double cost_scale
     if (o->u0 && !aligned(o->u0, 8)) return fail(UOT_ERR_ALIGN, "u0 must be 8-byte aligned");
     if (o->v0 && !aligned(o->v0, 8)) return fail(UOT_ERR_ALIGN, "v0 must be 8-byte aligned");
     // As many workgroups as the compute units hold at once (the pass is
-    // ALU-bound: one wave of strips, no tail).
+    // ALU-bound: one wave of strips, no tail), each with at least one full
+    // group of rows.
     const int per_cu = std::max(1, online_wgs_per_cu((int)dim, p->m));
-    const int64_t target = std::min<int64_t>((int64_t)per_cu * cu_count(), p->n);
+    const int64_t rg = std::max(1, online_rows_per_group((int)dim, p->m));
+    const int64_t target = std::min<int64_t>((int64_t)per_cu * cu_count(), (p->n + rg - 1) / rg);
     P.rows_per_wg = (p->n + target - 1) / target;
     P.G = (int32_t)((p->n + P.rows_per_wg - 1) / P.rows_per_wg);
     P.ldp = round_up(p->m, 64);

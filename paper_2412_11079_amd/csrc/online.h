@@ -16,7 +16,8 @@ struct OnlineLaunch {
 
 // Rows of at most online_max_m() columns.
 int64_t online_max_m();
-constexpr int kOnlineWG = 512;   // lanes per workgroup of the kernel-free pass
+// Rows a workgroup of the pass takes per group (and barrier).
+int online_rows_per_group(int dim, int64_t m);
 // Workgroups of the pass for rows of m columns that one compute unit holds.
 int online_wgs_per_cu(int dim, int64_t m);
 // Row and column terms of the exponent (rows, beta above) from the points

@@ -14,9 +14,10 @@
 // rounding of K), 2^k by ldexp.  An FP32 argument would not do: t reaches
 // hundreds, and its rounding alone would move K by ~1e-5.
 //
-// Workgroup: 512 lanes owning a strip of rows; lane l holds the columns
-// j = l + 512 c (c < CPL, m <= 512 CPL) in registers: coordinates and beta
-// in FP64, v and the column partials in FP32.  Rows are taken R at a time
+// Workgroup: WG lanes owning a strip of rows; lane l holds the columns
+// j = l + WG c (c < CPL, m <= WG CPL) in registers: coordinates and beta
+// in FP64 (beta in LDS for the widest rows), v and the column partials in
+// FP32.  Rows are taken R at a time
 // (column-outer, row-inner, so each column's data serves R independent
 // exponent chains): the R rows' K values are formed and dotted with v, the
 // R row totals are reduced over the wave (FP64) and met in one LDS exchange
@@ -56,12 +57,11 @@ __global__ void online_setup_kernel(const double* __restrict__ x, const double* 
 
 // BL: beta and v of the lane's columns sit in LDS (read once per group of R
 // rows) instead of registers, for 16 columns per lane.
-template <int DIM, int CPL, int R, int MODE, bool BL>
-__global__ __launch_bounds__(kOnlineWG) void online_kernel(OnlineLaunch O, const double* __restrict__ rows,
-                                                           const double* __restrict__ beta) {
+template <int DIM, int WG, int CPL, int R, int MODE, bool BL>
+__global__ __launch_bounds__(WG) void online_kernel(OnlineLaunch O, const double* __restrict__ rows,
+                                                    const double* __restrict__ beta) {
     static_assert(MODE == MODE_FUSED || MODE == MODE_MARG, "online fused or marginal pass");
     static_assert(R >= 1 && R <= 64, "rows per group");
-    constexpr int WG = kOnlineWG;
     constexpr int NW = WG / 64;
     const PassLaunch& L = O.P;
     __shared__ double red[2][R][NW];
@@ -184,26 +184,42 @@ hipError_t launch_online_setup(const double* x, const double* y, const double* a
     return hipGetLastError();
 }
 
-// Columns per lane (CPL) and rows per group (R) for rows of m columns: the
-// R CPL K values of a group stay in registers until its scalings are known.
+// Lanes per workgroup (WG), columns per lane (CPL) and rows per group (R)
+// for rows of m columns: the R CPL K values of a group stay in registers
+// until its scalings are known; BL puts beta and v in LDS.
+#ifndef UOT_ONLINE_WIDE
+#define UOT_ONLINE_WIDE(DIM, X) X(DIM, 512, 16, (DIM == 3 ? 3 : 4), true)
+#endif
 #define UOT_ONLINE_SHAPES(DIM, X)                   \
-    if (m <= 512) X(DIM, 1, 8, false);              \
-    else if (m <= 1024) X(DIM, 2, 8, false);        \
-    else if (m <= 2048) X(DIM, 4, 8, false);        \
-    else if (m <= 4096) X(DIM, 8, 8, false);        \
-    else X(DIM, 16, (DIM == 3 ? 3 : 4), true)
+    if (m <= 512) X(DIM, 512, 1, 8, false);         \
+    else if (m <= 1024) X(DIM, 512, 2, 8, false);   \
+    else if (m <= 2048) X(DIM, 512, 4, 8, false);   \
+    else if (m <= 4096) X(DIM, 512, 8, 8, false);   \
+    else UOT_ONLINE_WIDE(DIM, X)
 
-// Dynamic LDS of the pass for rows of m columns.
-static size_t online_lds(int64_t m) { return m > 4096 ? (size_t)kOnlineWG * 16 * (8 + 4) : 0; }
+// Dynamic LDS of a shape: beta (FP64) and v (FP32) of every column with BL.
+static constexpr size_t online_lds_of(int wg, int cpl, bool bl) { return bl ? (size_t)wg * cpl * 12 : 0; }
 
-int64_t online_max_m() { return 16 * kOnlineWG; }
+int64_t online_max_m() { return 8192; }
+
+int online_rows_per_group(int dim, int64_t m) {
+    int rg = 0;
+#define UOT_RG(DIM, WG, CPL, R, BL) rg = R
+    if (dim == 2) {
+        UOT_ONLINE_SHAPES(2, UOT_RG);
+    } else {
+        UOT_ONLINE_SHAPES(3, UOT_RG);
+    }
+#undef UOT_RG
+    return rg;
+}
 
 int online_wgs_per_cu(int dim, int64_t m) {
     int nb = 0;
     hipError_t e = hipSuccess;
-#define UOT_OCC(DIM, CPL, R, BL)                                                                           \
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, online_kernel<DIM, CPL, R, MODE_FUSED, BL>, kOnlineWG, \
-                                                     online_lds(m))
+#define UOT_OCC(DIM, WG, CPL, R, BL)                                                                          \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, online_kernel<DIM, WG, CPL, R, MODE_FUSED, BL>, WG, \
+                                                     online_lds_of(WG, CPL, BL))
     if (dim == 2) {
         UOT_ONLINE_SHAPES(2, UOT_OCC);
     } else {
@@ -217,18 +233,18 @@ hipError_t launch_online(int mode, const OnlineLaunch& O, hipStream_t stream) {
     const int64_t m = O.P.m;
     if ((O.dim != 2 && O.dim != 3) || m > online_max_m() || (mode != MODE_FUSED && mode != MODE_MARG))
         return hipErrorInvalidValue;
-    const size_t lds = online_lds(m);
-#define UOT_LAUNCH(DIM, CPL, R, BL)                                                                             \
+#define UOT_LAUNCH(DIM, WG, CPL, R, BL)                                                                         \
     do {                                                                                                        \
-        auto kf = online_kernel<DIM, CPL, R, MODE_FUSED, BL>;                                                   \
-        auto km = online_kernel<DIM, CPL, R, MODE_MARG, BL>;                                                    \
+        auto kf = online_kernel<DIM, WG, CPL, R, MODE_FUSED, BL>;                                               \
+        auto km = online_kernel<DIM, WG, CPL, R, MODE_MARG, BL>;                                                \
         auto kk = mode == MODE_FUSED ? kf : km;                                                                 \
+        const size_t lds = online_lds_of(WG, CPL, BL);                                                          \
         if (lds > 65536) {                                                                                      \
             hipError_t ea = hipFuncSetAttribute((const void*)kk, hipFuncAttributeMaxDynamicSharedMemorySize,   \
                                                 (int)lds);                                                      \
             if (ea != hipSuccess) return ea;                                                                    \
         }                                                                                                       \
-        hipLaunchKernelGGL(kk, dim3(O.P.grid), dim3(kOnlineWG), lds, stream, O, O.rows, O.beta);               \
+        hipLaunchKernelGGL(kk, dim3(O.P.grid), dim3(WG), lds, stream, O, O.rows, O.beta);                      \
     } while (0)
     if (O.dim == 2) {
         UOT_ONLINE_SHAPES(2, UOT_LAUNCH);
