@@ -92,6 +92,10 @@ def _load():
         lib.orc_loss_potentials.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp, _i64, _i64, ctypes.c_double,
                                             ctypes.c_double]
         lib.orc_loss_potentials.restype = ctypes.c_double
+        lib.orc_sinkhorn_lse.argtypes = [_dp, _dp, _dp, _i64, _i64, ctypes.c_double, ctypes.c_double, _i64,
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_double, _i64, _dp, _dp, _dp,
+                                         _dp, _dp, _dp]
+        lib.orc_sinkhorn_lse.restype = _i64
         _lib = lib
     return _lib
 
@@ -345,6 +349,34 @@ def sinkhorn_absorbed(C, a, b, eps: float, tau: float, max_iter: int, threshold:
                                   _p(checks), _p(arms))
     return AbsorbedResult(f=f, g=g, r=r, c=c, loss=float(loss.value), absorptions=int(nabs.value),
                           checks=checks[:max_iter], arms=arms[:max_iter])
+
+
+@dataclass
+class LseResult:
+    f: np.ndarray          # eps log u
+    g: np.ndarray          # eps log v
+    r: np.ndarray          # row marginal of P = exp((f_i + g_j - C_ij)/eps)
+    c: np.ndarray          # column marginal
+    loss: float
+    iters: int             # iterations over all stages
+    err: float
+
+
+def sinkhorn_lse(C, a, b, eps: float, tau: float, max_iter: int, tol: float = 0.0,
+                 eps0: float = 0.0, factor: float = 0.5, stage_iters: int = 0) -> LseResult:
+    """Log-domain iteration on potentials (log-sum-exp rows and columns), with
+    the eps-scaling schedule of orc_sinkhorn_lse when eps0 > eps."""
+    C = _f64(C)
+    a = _f64(a)
+    b = _f64(b)
+    n, m = C.shape
+    f, g, r, c = np.empty(n), np.empty(m), np.empty(n), np.empty(m)
+    loss = ctypes.c_double(0.0)
+    err = ctypes.c_double(0.0)
+    it = _load().orc_sinkhorn_lse(_p(C), _p(a), _p(b), n, m, float(eps), float(tau), int(max_iter), float(tol),
+                                  float(eps0), float(factor), int(stage_iters), _p(f), _p(g), _p(r), _p(c),
+                                  ctypes.byref(loss), ctypes.byref(err))
+    return LseResult(f=f, g=g, r=r, c=c, loss=float(loss.value), iters=int(it), err=float(err.value))
 
 
 def fi_exponent(eps: float, tau: float) -> float:

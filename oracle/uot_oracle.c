@@ -805,3 +805,122 @@ ORC_EXPORT int64_t orc_sinkhorn_absorbed(const double* C, const double* a, const
     free(Kt); free(f); free(g); free(u); free(v); free(s); free(w);
     return max_iter;
 }
+
+/* ------------------------------------------------------------------ */
+/* Log-domain (log-sum-exp) iteration and eps-scaling                   */
+/* ------------------------------------------------------------------ */
+
+/* LSE over a row of z_j = (g_j - C_ij) / eps (or a column of
+ * (f_i - C_ij) / eps): M + log sum exp(z - M) with M = max z, so every
+ * exponential is <= 1 whatever eps.  All z = -inf gives -inf. */
+static double orc_lse_row(const double* Crow, const double* g, int64_t m, double eps) {
+    double M = -INFINITY;
+    for (int64_t j = 0; j < m; ++j) {
+        double z = (g[j] - Crow[j]) / eps;
+        if (z > M) M = z;
+    }
+    if (M == -INFINITY) return -INFINITY;
+    double s = 0.0;
+    for (int64_t j = 0; j < m; ++j) s += exp((g[j] - Crow[j]) / eps - M);
+    return M + log(s);
+}
+
+/* Column LSEs L_j = LSE_i (f_i - C_ij) / eps for all j (column blocks). */
+static void orc_lse_cols(const double* C, const double* f, int64_t n, int64_t m, double eps, double* L) {
+    const int64_t BLK = 64;
+    int64_t nblk = (m + BLK - 1) / BLK;
+    #pragma omp parallel for schedule(static)
+    for (int64_t blk = 0; blk < nblk; ++blk) {
+        int64_t j0 = blk * BLK, j1 = j0 + BLK < m ? j0 + BLK : m;
+        double M[64], s[64];
+        for (int64_t j = j0; j < j1; ++j) M[j - j0] = -INFINITY;
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = j0; j < j1; ++j) {
+                double z = (f[i] - C[i * m + j]) / eps;
+                if (z > M[j - j0]) M[j - j0] = z;
+            }
+        for (int64_t j = j0; j < j1; ++j) s[j - j0] = 0.0;
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = j0; j < j1; ++j)
+                if (M[j - j0] > -INFINITY) s[j - j0] += exp((f[i] - C[i * m + j]) / eps - M[j - j0]);
+        for (int64_t j = j0; j < j1; ++j) L[j] = M[j - j0] == -INFINITY ? -INFINITY : M[j - j0] + log(s[j - j0]);
+    }
+}
+
+/* Potential update fi (eps log target - eps L); zero mass gives -inf. */
+static double orc_lse_update(double target, double L, double eps, double fi) {
+    if (target == 0.0) return -INFINITY;
+    return fi * (eps * log(target) - eps * L);
+}
+
+/*
+ * The iteration of Section 2.1 (vector form, rows first) written on the
+ * potentials f = eps log u, g = eps log v:
+ *     f_i = fi (eps log a_i - eps LSE_j((g_j - C_ij)/eps))
+ *     g_j = fi (eps log b_j - eps LSE_i((f_i - C_ij)/eps)),
+ * from g = 0 (v = 1); in exact arithmetic the same iterates as
+ * orc_sinkhorn on K = exp(-C/eps), at any eps (no exponential exceeds 1).
+ *
+ * eps-scaling (the paper gives no schedule; this is the reading used):
+ * when eps0 > eps, stage k = 0, 1, ... runs at eps_k = max(eps, eps0 *
+ * factor^k) (0 < factor < 1); every stage before the one at eps runs
+ * stage_iters iterations, each starting from the previous stage's
+ * potentials; the stage at eps runs up to max_iter iterations with the
+ * stopping rule of orc_sinkhorn (relative L1 change of the column marginal
+ * c_j = exp(g_j/eps + LSE_i((f_i - C_ij)/eps)), c_0 = 0 at the stage's
+ * start).  Without scaling (eps0 <= eps) only that last stage runs.
+ *
+ * Outputs: f, g; r, c, the marginals of P_ij = exp((f_i + g_j - C_ij)/eps)
+ * at the final potentials; *loss the objective (orc_loss_potentials);
+ * *err the last error.  Returns the iterations run over all stages.
+ */
+ORC_EXPORT int64_t orc_sinkhorn_lse(const double* C, const double* a, const double* b,
+                                    int64_t n, int64_t m, double eps, double tau,
+                                    int64_t max_iter, double tol,
+                                    double eps0, double factor, int64_t stage_iters,
+                                    double* f, double* g, double* r, double* c,
+                                    double* loss, double* err_out) {
+    double* L = (double*)malloc(sizeof(double) * (size_t)m);
+    double* c_prev = (double*)malloc(sizeof(double) * (size_t)m);
+    for (int64_t i = 0; i < n; ++i) f[i] = 0.0;
+    for (int64_t j = 0; j < m; ++j) g[j] = 0.0;
+    int64_t total = 0;
+    double err = 0.0;
+    double e = eps0 > eps ? eps0 : eps;
+    for (;;) {
+        const int last = !(e > eps);
+        const double fi = orc_fi(e, tau);
+        const int64_t T = last ? max_iter : stage_iters;
+        for (int64_t j = 0; j < m; ++j) c_prev[j] = 0.0;
+        for (int64_t t = 0; t < T; ++t) {
+            #pragma omp parallel for schedule(static)
+            for (int64_t i = 0; i < n; ++i) f[i] = orc_lse_update(a[i], orc_lse_row(C + i * m, g, m, e), e, fi);
+            orc_lse_cols(C, f, n, m, e, L);
+            for (int64_t j = 0; j < m; ++j) g[j] = orc_lse_update(b[j], L[j], e, fi);
+            ++total;
+            if (last) {
+                double num = 0.0, den = 0.0;
+                for (int64_t j = 0; j < m; ++j) {
+                    double cj = exp(g[j] / e + L[j]);
+                    num += fabs(cj - c_prev[j]);
+                    den += fabs(cj);
+                    c_prev[j] = cj;
+                }
+                err = num / den;
+                if (tol > 0.0 && err <= tol) break;
+            }
+        }
+        if (last) break;
+        e = e * factor > eps ? e * factor : eps;
+    }
+    /* marginals at the final potentials */
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) r[i] = exp(f[i] / eps + orc_lse_row(C + i * m, g, m, eps));
+    orc_lse_cols(C, f, n, m, eps, L);
+    for (int64_t j = 0; j < m; ++j) c[j] = exp(g[j] / eps + L[j]);
+    *loss = orc_loss_potentials(f, g, r, c, a, b, n, m, eps, tau);
+    if (err_out) *err_out = err;
+    free(L);
+    free(c_prev);
+    return total;
+}

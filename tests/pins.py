@@ -55,6 +55,22 @@ def one_by_one(a: float, b: float, C: float, eps: float, tau: float, T: int):
     return math.exp(lu), math.exp(lv)
 
 
+def one_by_one_log(a: float, b: float, C: float, eps: float, tau: float, T: int):
+    """(log u_T, log v_T) of the 1 x 1 problem from v_0 = 1, the recurrence
+    of one_by_one kept in logs (finite where u, v leave the FP64 range)."""
+    fi = fi_of(eps, tau)
+    lk = -C / eps
+    la, lb = math.log(a), math.log(b)
+    alpha = fi * (lb - lk) - fi * fi * (la - lk)
+    q = fi * fi
+    if T == 0:
+        return 0.0, 0.0
+    lv_prev = alpha * (T - 1) if q == 1.0 else alpha * (1.0 - q ** (T - 1)) / (1.0 - q)
+    lu = fi * (la - lk - lv_prev)
+    lv = fi * (lb - lk - lu)
+    return lu, lv
+
+
 def one_by_one_limit(a: float, b: float, C: float, eps: float, tau: float) -> float:
     """Optimal plan of the 1 x 1 problem: exp((tau (log a + log b) - C) / (eps + 2 tau))."""
     return math.exp((tau * (math.log(a) + math.log(b)) - C) / (eps + 2.0 * tau))

@@ -586,3 +586,91 @@ def test_round_storage_e4m3_matches_torch_in_range():
     x = x[x <= 448].astype(np.float32)
     ref = torch.from_numpy(x).to(torch.float8_e4m3fn).to(torch.float64).numpy()
     assert np.array_equal(oracle.round_storage(x.astype(np.float64), "e4m3"), ref)
+
+
+# ---------------------------------------------------------------------------
+# Log-domain (log-sum-exp) iteration and eps-scaling
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("eps,tau,zero", [(0.1, 1.0, False), (0.05, math.inf, False), (0.2, 0.5, True)])
+def test_lse_equals_vector_form(eps, tau, zero):
+    """Same iterates as the vector form on K = exp(-C/eps) (where K is
+    representable), zero-mass entries included (u_i = 0 <=> f_i = -inf)."""
+    p = workloads.random_small(60, 45, seed=11, eps=eps, tau=tau)
+    a, b = p.a.copy(), p.b.copy()
+    if zero:
+        a[3] = 0.0
+        b[7] = 0.0
+    C = oracle.cost_points(p.x, p.y)
+    ref = oracle.sinkhorn(oracle.kernel(C, eps), a, b, eps, tau, 40)
+    lse = oracle.sinkhorn_lse(C, a, b, eps, tau, 40)
+    u, v = np.exp(lse.f / eps), np.exp(lse.g / eps)
+    assert np.all((u == 0) == (ref.u == 0)) and np.all((v == 0) == (ref.v == 0))
+    pos_u, pos_v = ref.u > 0, ref.v > 0
+    assert np.max(np.abs(u[pos_u] / ref.u[pos_u] - 1)) < 1e-12
+    assert np.max(np.abs(v[pos_v] / ref.v[pos_v] - 1)) < 1e-12
+    np.testing.assert_allclose(lse.r, ref.r, rtol=1e-12, atol=0)
+    np.testing.assert_allclose(lse.c, ref.c, rtol=1e-12, atol=0)
+    assert abs(lse.loss / ref.loss - 1) < 1e-12
+
+
+def test_lse_one_by_one_closed_form_where_the_kernel_underflows():
+    """1 x 1 problem at eps = 1e-4 with C = 3: K = e^-30000 is 0 in FP64, the
+    log-domain iterates still follow the closed-form recurrence, and the
+    converged plan is the closed-form optimum."""
+    a, b, c, eps, tau = 0.7, 1.9, 3.0, 1e-4, 0.5
+    for T in (1, 2, 7, 50):
+        lu, lv = pins.one_by_one_log(a, b, c, eps, tau, T)
+        r = oracle.sinkhorn_lse(np.array([[c]]), np.array([a]), np.array([b]), eps, tau, T)
+        assert abs(r.f[0] - eps * lu) <= 1e-13 * max(1.0, abs(eps * lu))
+        assert abs(r.g[0] - eps * lv) <= 1e-13 * max(1.0, abs(eps * lv))
+    # fi^2 = 0.9996 per iteration: 3e5 iterations leave e^-120 of the start
+    r = oracle.sinkhorn_lse(np.array([[c]]), np.array([a]), np.array([b]), eps, tau, 300000)
+    P = math.exp((r.f[0] + r.g[0] - c) / eps)
+    assert abs(P / pins.one_by_one_limit(a, b, c, eps, tau) - 1) < 1e-10
+    # P from potentials carries |C|/eps = 3e4 times the unit roundoff
+    assert abs(r.r[0] / P - 1) < 1e-11
+
+
+@pytest.mark.parametrize("T", [1, 5, 30])
+def test_lse_rank1_closed_form_at_small_eps(T):
+    """Separable cost alpha_i + beta_j in [0, 2) at eps = 2e-3: kernel entries
+    down to e^-1000 (FP64 underflow for the vector form); potentials against
+    the closed form of the rank-1 recurrence."""
+    rng = np.random.default_rng(21)
+    n, m, eps, tau = 70, 50, 2e-3, 0.5
+    alpha, beta = rng.random(n), rng.random(m)
+    a, b = rng.dirichlet(np.ones(n)), 0.8 * rng.dirichlet(np.ones(m))
+    lu, lv = pins.rank1(alpha, beta, a, b, eps, tau, T)
+    r = oracle.sinkhorn_lse(np.add.outer(alpha, beta), a, b, eps, tau, T)
+    assert np.max(np.abs(r.f - eps * lu)) < 1e-12
+    assert np.max(np.abs(r.g - eps * lv)) < 1e-12
+
+
+def test_lse_tolerance_stop_matches_vector_form():
+    p = workloads.random_small(80, 70, seed=12, eps=0.05, tau=1.0)
+    C = oracle.cost_points(p.x, p.y)
+    ref = oracle.sinkhorn(oracle.kernel(C, p.eps), p.a, p.b, p.eps, p.tau, 5000, tol=1e-9)
+    lse = oracle.sinkhorn_lse(C, p.a, p.b, p.eps, p.tau, 5000, tol=1e-9)
+    assert 10 < ref.iters < 5000 and lse.iters == ref.iters
+    # the error is a difference of nearly equal marginals: compare absolutely
+    assert abs(lse.err - ref.err) < 1e-14
+
+
+def test_eps_scaling_schedule_and_fixed_point():
+    """Stages at eps0 factor^k down to eps (each stage_iters iterations, the
+    last up to max_iter): a fixed count runs sum of stages; a schedule that
+    starts at eps is the plain run; a converged scaled run reaches the plain
+    run's fixed point (unique for tau < inf)."""
+    p = workloads.random_small(40, 30, seed=13, eps=0.01, tau=1.0)
+    C = oracle.cost_points(p.x, p.y)
+    # stages 0.16, 0.08, 0.04, 0.02 (3 iterations each), then 0.01 (5)
+    r = oracle.sinkhorn_lse(C, p.a, p.b, 0.01, 1.0, 5, eps0=0.16, factor=0.5, stage_iters=3)
+    assert r.iters == 4 * 3 + 5
+    plain = oracle.sinkhorn_lse(C, p.a, p.b, 0.01, 1.0, 7)
+    same = oracle.sinkhorn_lse(C, p.a, p.b, 0.01, 1.0, 7, eps0=0.01, factor=0.5, stage_iters=9)
+    assert np.array_equal(plain.f, same.f) and np.array_equal(plain.g, same.g)
+    direct = oracle.sinkhorn_lse(C, p.a, p.b, 0.01, 1.0, 100000, tol=1e-14)
+    scaled = oracle.sinkhorn_lse(C, p.a, p.b, 0.01, 1.0, 100000, tol=1e-14, eps0=1.0, factor=0.5, stage_iters=20)
+    assert direct.iters < 100000 and scaled.iters < 100000
+    assert np.max(np.abs(scaled.f - direct.f)) < 1e-9 and np.max(np.abs(scaled.g - direct.g)) < 1e-9
