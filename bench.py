@@ -17,7 +17,11 @@ Prints ONE JSON line (rank 0).  Besides the contract fields it carries:
   precision     65536 x 8192 with BF16 / FP8 / FP32 K and absorption;
   kernel_free   the kernel-free solve (K recomputed in every pass) on the
                 3-D differentiation and 2-D plain workloads, against the
-                streamed FP32 K at the same shapes, with its ALU roofline.
+                streamed FP32 K at the same shapes, with its ALU roofline;
+  log_domain    the log-domain (log-sum-exp) solve on the precision workload
+                (FP64 and FP32 cost, no absorption) with its errors against
+                the FP64 oracle, and eps-scaling against the direct run to a
+                tolerance.
 """
 from __future__ import annotations
 
@@ -55,6 +59,7 @@ def parse():
     p.add_argument("--no-multi", action="store_true", help="skip the multi-right-hand-side timing")
     p.add_argument("--no-precision", action="store_true", help="skip the low-precision timing")
     p.add_argument("--no-kernel-free", action="store_true", help="skip the kernel-free solve timing")
+    p.add_argument("--no-log-domain", action="store_true", help="skip the log-domain solve timing")
     p.add_argument("--only", default="", help="comma list of sections to run alone (profiling)")
     p.add_argument("--cpu-leg", type=int, default=0, help=argparse.SUPPRESS)
     p.add_argument("--cpu-rows", type=int, default=0, help=argparse.SUPPRESS)
@@ -108,7 +113,7 @@ def main():
 
     if args.only:
         sections = {"grad": fwd_bwd, "batched": batched, "multi": multi, "precision": precision,
-                    "kernel_free": kernel_free}
+                    "kernel_free": kernel_free, "log_domain": log_domain}
         res = {k: sections[k](uot, workloads, torch, dev, args) for k in args.only.split(",")}
         print(json.dumps(res), flush=True)
         return
@@ -211,6 +216,8 @@ def main():
         out["precision"] = precision(uot, workloads, torch, dev, args)
     if not args.no_kernel_free:
         out["kernel_free"] = kernel_free(uot, workloads, torch, dev, args)
+    if not args.no_log_domain:
+        out["log_domain"] = log_domain(uot, workloads, torch, dev, args)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)
@@ -539,6 +546,55 @@ def precision(uot, workloads, torch, dev, args):
                                                            float(r.loss.cpu()), ref, prob.eps)
     if ref is None:
         out["err_vs_oracle"] = f"missing {PRECISION_REF}"
+    return out
+
+
+def log_domain(uot, workloads, torch, dev, args):
+    """Log-domain solve on the precision workload (65536 x 8192, eps 1e-3,
+    tau 0.1, 2000 iterations): the cost read as FP64 (8 bytes per entry and
+    iteration) and as FP32 (4), no absorption; iterations/s, the pass's cost
+    stream rate (per-iteration time from two solves of T and 2T iterations,
+    pass plus column finalize) and the errors against the FP64 oracle.  Then
+    eps-scaling: the same problem to tol 1e-5 directly and from eps0 = 0.064
+    (halving, 20 iterations per stage), iterations and time of each."""
+    prob = workloads.precision()
+    C = uot.cost_from_points(torch.from_numpy(prob.x).to(dev), torch.from_numpy(prob.y).to(dev),
+                             prob.cost_kind, prob.normalize_max)
+    a = torch.from_numpy(prob.a).to(dev)
+    b = torch.from_numpy(prob.b).to(dev)
+    ref = _load_precision_ref(prob)
+    out = {"workload": f"precision: {prob.n}x{prob.m}, 16-D normal points, eps={prob.eps}, tau={prob.tau}, "
+                       f"{prob.max_iter} iterations, log-domain passes over the stored cost"}
+
+    def timed(T, **kw):
+        e0, e1 = _events(torch)
+        e0.record()
+        r = uot.sinkhorn_lse(C, a, b, eps=prob.eps, tau=prob.tau, max_iter=T, **kw)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1), r
+
+    for name, dt, eb in (("f64_cost", torch.float64, 8), ("f32_cost", torch.float32, 4)):
+        timed(3, cost_dtype=dt)
+        ms1, _ = timed(100, cost_dtype=dt)
+        ms2, _ = timed(200, cost_dtype=dt)
+        it_us = (ms2 - ms1) / 100 * 1e3
+        ms, r = timed(prob.max_iter, cost_dtype=dt)
+        info = r.info()
+        out[name] = {"ms_per_solve": round(ms, 2), "iters_per_s": round(prob.max_iter / (ms * 1e-3), 1),
+                     "iter_us": round(it_us, 2), "cost_tb_s": round(prob.n * prob.m * eb / (it_us * 1e-6) / 1e12, 3),
+                     "hbm_frac": round(prob.n * prob.m * eb / (it_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                     "flags": info["flags"]}
+        if ref is not None:
+            out[name]["err_vs_oracle"] = _precision_errors(r.f.cpu().numpy(), r.g.cpu().numpy(), float(r.loss.cpu()),
+                                                           ref, prob.eps)
+    sched = {"direct": {}, "eps_scaled": {"eps0": 0.064, "factor": 0.5, "stage_iters": 20}}
+    out["to_tol_1e-5"] = {}
+    for name, kw in sched.items():
+        ms, r = timed(20000, tol=1e-5, check_every=10, **kw)
+        info = r.info()
+        out["to_tol_1e-5"][name] = {"iters": info["iters"], "ms": round(ms, 2), "err": float(f"{info['err']:.3e}"),
+                                    "flags": info["flags"]}
     return out
 
 

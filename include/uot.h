@@ -305,6 +305,52 @@ uot_status uot_sinkhorn_points(const uot_problem* prob, const double* x, const d
                                double cost_scale, const uot_options* opt, const uot_outputs* out,
                                void* ws, size_t ws_bytes, void* stream);
 
+/* Decreasing-eps schedule of uot_sinkhorn_lse (host memory). */
+typedef struct uot_eps_schedule {
+    double eps0;              /* first stage's eps; <= prob->eps: no schedule */
+    double factor;            /* eps_{k+1} = max(eps, eps_k * factor), 0 < factor < 1 */
+    int32_t stage_iters;      /* iterations of every stage before the one at eps (>= 1) */
+    int32_t reserved;
+} uot_eps_schedule;
+
+/*
+ * Log-domain (log-sum-exp) solve: the iteration of Section 2.1 (vector
+ * form, rows first) carried on the potentials f = eps log u, g = eps log v,
+ *     f_i = fi (eps log a_i - eps LSE_j((g_j - C_ij)/eps))
+ *     g_j = fi (eps log b_j - eps LSE_i((f_i - C_ij)/eps)),
+ * every sum taken under its maximum, so no exponential exceeds 1 at any
+ * eps: no absorption is needed where the scalings leave the FP64 range.
+ * One fused pass per iteration reads the cost C once; the exponents are
+ * formed in FP64 and each exponential is the hardware exp2 (FP32, relative
+ * error about 1e-7 on the terms that carry the sums), summed in FP32 per
+ * lane and in FP64 across lanes and workgroups.
+ *   prob: n, m, a, b, C (FP64, n x ldc, 16-byte aligned, even ldc >= m),
+ *     eps, tau; k_dtype chooses the cost the passes read: UOT_F64 (C
+ *     itself, 8 bytes per entry and iteration) or UOT_F32 (C rounded to
+ *     FP32 once into the workspace, 4 bytes; its rounding moves each
+ *     exponent by up to |C_ij|/eps * 2^-24, so it suits costs with
+ *     |C|/eps well below 2^24 * 1e-6).  K, ldk, k_scale ignored.
+ *   sched: NULL, or a schedule: stages at eps0, eps0 factor, ... down to
+ *     eps, each before the last running stage_iters iterations from the
+ *     previous stage's potentials; the stage at eps runs up to max_iter
+ *     iterations with the stopping rule of uot_sinkhorn (its first
+ *     iteration is compared with a zero marginal).
+ *   opt: max_iter, tol, check_every; fused = 1, accum = UOT_ACC_F32 and no
+ *     absorption, checkpoints, cooperative loop or warm start (else
+ *     UOT_ERR_UNSUPPORTED).
+ *   out: u, v (required) receive the totals e^{f/eps}, e^{g/eps} (inf where
+ *     they leave the FP64 range), f, g (optional) the potentials, r, c,
+ *     loss, info as uot_sinkhorn (info.iters counts every stage's iterations).
+ * Rows of at most 8192 columns.
+ * Errors: UOT_ERR_ARG, UOT_ERR_DTYPE, UOT_ERR_ALIGN, UOT_ERR_WORKSPACE,
+ * UOT_ERR_UNSUPPORTED, UOT_ERR_HIP.  Workspace:
+ * uot_sinkhorn_lse_workspace_size bytes (0 on invalid arguments).
+ */
+size_t uot_sinkhorn_lse_workspace_size(const uot_problem* prob, const uot_options* opt,
+                                       const uot_eps_schedule* sched);
+uot_status uot_sinkhorn_lse(const uot_problem* prob, const uot_options* opt, const uot_eps_schedule* sched,
+                            const uot_outputs* out, void* ws, size_t ws_bytes, void* stream);
+
 /*
  * For callers that cannot allocate (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): uot_sinkhorn without a

@@ -275,6 +275,55 @@ def sinkhorn_points(x: torch.Tensor, y: torch.Tensor, a: torch.Tensor, b: torch.
     return res
 
 
+def sinkhorn_lse(C: torch.Tensor, a: torch.Tensor, b: torch.Tensor, *, eps: float, tau: float, max_iter: int,
+                 m: Optional[int] = None, tol: float = 0.0, check_every: int = 1,
+                 cost_dtype: torch.dtype = torch.float64, eps0: float = 0.0, factor: float = 0.5,
+                 stage_iters: int = 0) -> SinkhornResult:
+    """Log-domain solve on the FP64 cost ``C`` (include/uot.h,
+    uot_sinkhorn_lse): potentials f, g, log-sum-exp passes reading C in
+    ``cost_dtype`` (float64 or float32), optional eps-scaling from ``eps0``."""
+    if C.dtype != torch.float64 or C.dim() != 2 or C.stride(1) != 1:
+        raise ValueError("C must be a row-major float64 matrix")
+    device = a.device
+    n = a.shape[0]
+    m = b.shape[0] if m is None else int(m)
+    if C.stride(0) % 2:
+        Cp = torch.zeros((C.shape[0], C.stride(0) + 1), dtype=torch.float64, device=device)
+        Cp[:, :C.shape[1]] = C
+        C = Cp
+    a = _vec64(a, "a", n, device)
+    b = _vec64(b, "b", m, device)
+    prob = _problem(a, b, None, C, m, eps, tau, device)
+    prob.k_dtype = _DTYPES[cost_dtype]
+    opt = _lib.Options()
+    opt.max_iter = int(max_iter)
+    opt.check_every = int(check_every)
+    opt.tol = float(tol)
+    opt.fused = 1
+    opt.accum = UOT_ACC_F32
+    sch = _lib.EpsSchedule(float(eps0), float(factor), int(stage_iters), 0)
+    L = _lib.lib()
+    need = L.uot_sinkhorn_lse_workspace_size(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(sch))
+    if need == 0:
+        _lib.check(L.uot_sinkhorn_lse(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(sch), None, None, 0, None))
+    ws = _workspace(need, device)
+    u = torch.empty(n, dtype=torch.float64, device=device)
+    v = torch.empty(m, dtype=torch.float64, device=device)
+    r = torch.empty(n, dtype=torch.float64, device=device)
+    c = torch.empty(m, dtype=torch.float64, device=device)
+    loss = torch.empty((), dtype=torch.float64, device=device)
+    info = torch.zeros(ctypes.sizeof(_lib.Info), dtype=torch.uint8, device=device)
+    fpot = torch.empty(n, dtype=torch.float64, device=device)
+    gpot = torch.empty(m, dtype=torch.float64, device=device)
+    out = _lib.Outputs(u.data_ptr(), v.data_ptr(), r.data_ptr(), c.data_ptr(), loss.data_ptr(), info.data_ptr(),
+                       None, fpot.data_ptr(), gpot.data_ptr())
+    _lib.check(L.uot_sinkhorn_lse(ctypes.byref(prob), ctypes.byref(opt), ctypes.byref(sch), ctypes.byref(out),
+                                  _ptr(ws), ws.numel(), _stream(device)))
+    res = SinkhornResult(u=u, v=v, r=r, c=c, loss=loss, info_raw=info, f=fpot, g=gpot)
+    res._keepalive = (ws, C, a, b)
+    return res
+
+
 @dataclass
 class MatrixResult:
     alpha: torch.Tensor       # (n,) last row factors

@@ -54,6 +54,10 @@ class BatchedMeta(ctypes.Structure):
                 ("pool_bytes", _i64)]
 
 
+class EpsSchedule(ctypes.Structure):
+    _fields_ = [("eps0", _dbl), ("factor", _dbl), ("stage_iters", _i32), ("reserved", _i32)]
+
+
 # Every symbol that include/uot.h declares, with its ctypes signature.
 SIGNATURES = {
     "uot_status_string": ([_i32], ctypes.c_char_p),
@@ -70,6 +74,10 @@ SIGNATURES = {
     "uot_sinkhorn_points_workspace_size": ([ctypes.POINTER(Problem), _i64, _dbl, ctypes.POINTER(Options)], _sz),
     "uot_sinkhorn_points": ([ctypes.POINTER(Problem), _vp, _vp, _i64, _dbl, ctypes.POINTER(Options),
                              ctypes.POINTER(Outputs), _vp, _sz, _vp], _i32),
+    "uot_sinkhorn_lse_workspace_size": ([ctypes.POINTER(Problem), ctypes.POINTER(Options),
+                                         ctypes.POINTER(EpsSchedule)], _sz),
+    "uot_sinkhorn_lse": ([ctypes.POINTER(Problem), ctypes.POINTER(Options), ctypes.POINTER(EpsSchedule),
+                          ctypes.POINTER(Outputs), _vp, _sz, _vp], _i32),
     "uot_sinkhorn_noalloc": ([ctypes.POINTER(Problem), ctypes.POINTER(Options), ctypes.POINTER(Outputs), _vp],
                              _i32),
     "uot_sinkhorn_profiled": ([ctypes.POINTER(Problem), ctypes.POINTER(Options), ctypes.POINTER(Outputs), _vp,

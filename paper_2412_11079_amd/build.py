@@ -12,7 +12,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libuot.so")
-SOURCES = ["pass.hip", "aux.hip", "adj.hip", "batch.hip", "multi.hip", "online.hip", "api.hip"]
+SOURCES = ["pass.hip", "aux.hip", "adj.hip", "batch.hip", "multi.hip", "online.hip", "lse.hip", "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are disabled for every device compile.

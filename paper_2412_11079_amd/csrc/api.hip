@@ -13,6 +13,7 @@
 #include "batch.h"
 #include "multi.h"
 #include "online.h"
+#include "lse.h"
 #include "plan.h"
 #include "uot_common.h"
 
@@ -1298,6 +1299,227 @@ uot_status run_points(const uot_problem* p, const double* x, const double* y, in
 }
 
 // ---------------------------------------------------------------------------
+// Log-domain (log-sum-exp) solve with an optional eps-scaling schedule
+// ---------------------------------------------------------------------------
+struct LsePlan {
+    int32_t G;
+    int64_t rows_per_wg, ldp, ldc32;
+    int32_t fin_blocks;
+    size_t off_ctrl, off_cprev, off_f, off_g, off_la2, off_lb2, off_ones_n, off_ones_m, off_r, off_c, off_bp,
+        off_pmax, off_psum, off_c32, total;
+};
+
+uot_status make_lse_plan(const uot_problem* p, const uot_options* o, const uot_eps_schedule* sch, LsePlan& P) {
+    if (!p || !o) return fail(UOT_ERR_ARG, "problem and options must not be NULL");
+    if (p->n < 1 || p->m < 1) return fail(UOT_ERR_ARG, "empty problem (n=%lld, m=%lld)", (long long)p->n, (long long)p->m);
+    if (!p->a || !p->b) return fail(UOT_ERR_ARG, "a and b must not be NULL");
+    if (!p->C) return fail(UOT_ERR_ARG, "the log-domain solve reads the cost C (NULL given)");
+    if (!aligned(p->a, 8) || !aligned(p->b, 8)) return fail(UOT_ERR_ALIGN, "a and b must be 8-byte aligned");
+    if (!aligned(p->C, 16) || p->ldc < p->m || p->ldc % 2 != 0)
+        return fail(UOT_ERR_ALIGN, "C must be 16-byte aligned with an even ldc >= m");
+    if (!(p->eps > 0.0) || !isfinite(p->eps)) return fail(UOT_ERR_ARG, "eps must be finite and > 0");
+    if (!(p->tau > 0.0)) return fail(UOT_ERR_ARG, "tau must be > 0 (or +inf)");
+    if (p->k_dtype != UOT_F64 && p->k_dtype != UOT_F32)
+        return fail(UOT_ERR_DTYPE, "the cost is read as FP64 or FP32 (k_dtype %d)", (int)p->k_dtype);
+    if (p->m > lse_max_m(p->k_dtype))
+        return fail(UOT_ERR_UNSUPPORTED, "rows of at most %lld columns for this cost storage (m=%lld)",
+                    (long long)lse_max_m(p->k_dtype), (long long)p->m);
+    if (o->max_iter < 0) return fail(UOT_ERR_ARG, "max_iter must be >= 0");
+    if (o->absorb_log_threshold != 0.0 || o->checkpoint_every != 0 || o->persistent || !o->fused || o->u0 || o->v0 ||
+        o->accum != UOT_ACC_F32)
+        return fail(UOT_ERR_UNSUPPORTED,
+                    "the log-domain solve runs its own fused pass: no absorption, checkpoints, cooperative loop, "
+                    "warm start or accumulation option");
+    if (sch) {
+        if (sch->eps0 > p->eps) {
+            if (!(sch->factor > 0.0 && sch->factor < 1.0)) return fail(UOT_ERR_ARG, "eps-scaling factor must lie in (0, 1)");
+            if (sch->stage_iters < 1) return fail(UOT_ERR_ARG, "eps-scaling stages need stage_iters >= 1");
+            if (!isfinite(sch->eps0)) return fail(UOT_ERR_ARG, "eps0 must be finite");
+        }
+    }
+    // One wave of workgroups over the compute units.
+    const int per_cu = std::max(1, lse_wgs_per_cu(p->k_dtype, p->m));
+    const int64_t target = std::min<int64_t>((int64_t)per_cu * cu_count(), p->n);
+    P.rows_per_wg = (p->n + target - 1) / target;
+    P.G = (int32_t)((p->n + P.rows_per_wg - 1) / P.rows_per_wg);
+    P.ldp = round_up(p->m, 64);
+    P.ldc32 = round_up(p->m, 4);
+    const int64_t csize = p->k_dtype == UOT_F32 ? 4 : 8;
+    const int64_t ldc_read = p->k_dtype == UOT_F32 ? P.ldc32 : p->ldc;
+    if ((P.rows_per_wg + 4) * ldc_read * csize >= (1LL << 31))
+        return fail(UOT_ERR_UNSUPPORTED, "a strip of %lld rows exceeds 2 GiB", (long long)P.rows_per_wg);
+    P.fin_blocks = lse_finalize_blocks(p->m);
+    size_t off = 0;
+    P.off_ctrl = off; off = align_up(off + sizeof(Ctrl), kAlign);
+    P.off_cprev = off; off = align_up(off + sizeof(double) * p->m, kAlign);
+    P.off_f = off; off = align_up(off + sizeof(double) * p->n, kAlign);
+    P.off_g = off; off = align_up(off + sizeof(double) * p->m, kAlign);
+    P.off_la2 = off; off = align_up(off + sizeof(double) * p->n, kAlign);
+    P.off_lb2 = off; off = align_up(off + sizeof(double) * p->m, kAlign);
+    P.off_ones_n = off; off = align_up(off + sizeof(double) * p->n, kAlign);
+    P.off_ones_m = off; off = align_up(off + sizeof(double) * p->m, kAlign);
+    P.off_r = off; off = align_up(off + sizeof(double) * p->n, kAlign);
+    P.off_c = off; off = align_up(off + sizeof(double) * p->m, kAlign);
+    P.off_bp = off; off = align_up(off + sizeof(double) * 2 * (size_t)P.fin_blocks, kAlign);
+    P.off_pmax = off; off = align_up(off + sizeof(double) * (size_t)P.G * P.ldp, kAlign);
+    P.off_psum = off; off = align_up(off + sizeof(float) * (size_t)P.G * P.ldp, kAlign);
+    P.off_c32 = off;
+    if (p->k_dtype == UOT_F32) off = align_up(off + sizeof(float) * (size_t)p->n * P.ldc32, kAlign);
+    P.total = off;
+    return UOT_OK;
+}
+
+uot_status run_lse(const uot_problem* p, const uot_options* o, const uot_eps_schedule* sch, const uot_outputs* out,
+                   void* ws, size_t ws_bytes, hipStream_t stream) {
+    LsePlan P;
+    uot_status st = make_lse_plan(p, o, sch, P);
+    if (st != UOT_OK) return st;
+    if (!out || !out->u || !out->v) return fail(UOT_ERR_ARG, "outputs u and v are required");
+    if (!aligned(out->u, 8) || !aligned(out->v, 8)) return fail(UOT_ERR_ALIGN, "u and v must be 8-byte aligned");
+    if (ws_bytes < P.total || !ws) return fail(UOT_ERR_WORKSPACE, "workspace of %zu bytes needed, %zu given", P.total, ws_bytes);
+    if (!aligned(ws, kAlign)) return fail(UOT_ERR_ALIGN, "workspace must be 256-byte aligned");
+    PinnedGuard pin;
+    if (o->tol > 0.0) UOT_HIP(pinned_acquire(pin.slot), "hipHostMalloc");
+    uint32_t* flag_host = o->tol > 0.0 ? pin.slot.flag() : nullptr;
+    char* base = (char*)ws;
+    Ctrl* ctrl = (Ctrl*)(base + P.off_ctrl);
+    double* cprev = (double*)(base + P.off_cprev);
+    double* f = (double*)(base + P.off_f);
+    double* g = (double*)(base + P.off_g);
+    double* la2 = (double*)(base + P.off_la2);
+    double* lb2 = (double*)(base + P.off_lb2);
+    double* ones_n = (double*)(base + P.off_ones_n);
+    double* ones_m = (double*)(base + P.off_ones_m);
+    double* rbuf = (double*)(base + P.off_r);
+    double* cbuf = (double*)(base + P.off_c);
+    double* bp = (double*)(base + P.off_bp);
+    double* pmax = (double*)(base + P.off_pmax);
+    float* psum = (float*)(base + P.off_psum);
+    const void* Cread = p->C;
+    int64_t ldc_read = p->ldc;
+    if (p->k_dtype == UOT_F32) {
+        float* c32 = (float*)(base + P.off_c32);
+        UOT_HIP(launch_cost_to_f32(p->C, p->ldc, p->n, p->m, c32, P.ldc32, stream), "cost to FP32");
+        Cread = c32;
+        ldc_read = P.ldc32;
+    }
+    // init: u = v = 1 in the ones vectors, f = g = 0, flags and stop state cleared
+    UOT_HIP(launch_init(ones_n, p->n, nullptr, ones_m, p->m, nullptr, cprev, ctrl, stream), "init");
+    UOT_HIP(launch_fill_f64(f, p->n, 0.0, stream), "f");
+    UOT_HIP(launch_fill_f64(g, p->m, 0.0, stream), "g");
+    UOT_HIP(launch_lse_setup(p->a, p->n, p->b, p->m, la2, lb2, stream), "log targets");
+
+    LseLaunch L;
+    memset(&L, 0, sizeof(L));
+    L.P.n = p->n;
+    L.P.m = p->m;
+    L.P.rows_per_wg = P.rows_per_wg;
+    L.P.grid = P.G;
+    L.P.ctrl = ctrl;
+    L.P.check_done = 1;
+    L.P.tol = o->tol;
+    L.P.fin_blocks = P.fin_blocks;
+    L.P.blockpart = bp;
+    L.C = Cread;
+    L.c_dtype = p->k_dtype;
+    L.ldc = ldc_read;
+    L.g = g;
+    L.f = f;
+    L.la2 = la2;
+    L.pmax = pmax;
+    L.psum = psum;
+    L.ldp = P.ldp;
+    LseFinLaunch F;
+    memset(&F, 0, sizeof(F));
+    F.pmax = pmax;
+    F.psum = psum;
+    F.ldp = P.ldp;
+    F.G = P.G;
+    F.m = p->m;
+    F.lb2 = lb2;
+    F.g = g;
+    F.cprev = cprev;
+    F.ctrl = ctrl;
+    F.blockpart = bp;
+
+    // Stages: eps0 factor^k down to eps (stage_iters each), then eps (max_iter, stopping rule).
+    const bool scaled = sch && sch->eps0 > p->eps;
+    double e = scaled ? sch->eps0 : p->eps;
+    const int check_every = o->check_every > 0 ? o->check_every : 1;
+    int64_t total = 0;
+    for (;;) {
+        const bool last = !(e > p->eps);
+        const double fi = fi_of(e, p->tau);
+        L.c = 1.4426950408889634 / e;
+        L.inv_c = e * 0.6931471805599453;
+        L.fi = fi;
+        F.c = L.c;
+        F.inv_c = L.inv_c;
+        F.fi = fi;
+        const int64_t T = last ? o->max_iter : sch->stage_iters;
+        if (last && total > 0) UOT_HIP(launch_fill_f64(cprev, p->m, 0.0, stream), "stage reset");
+        for (int64_t t = 0; t < T; ++t) {
+            LseLaunch L1 = L;
+            L1.P.iter = total + 1;
+            L1.P.test_stop = (last && t > 0) ? 1 : 0;      // the stage's first iteration has no previous marginal
+            UOT_HIP(launch_lse(MODE_FUSED, L1, stream), "log-domain pass");
+            UOT_HIP(launch_lse_finalize(F, stream), "log-domain finalize");
+            ++total;
+            if (last && flag_host && (t + 1) % check_every == 0 && t + 1 < T) {
+                UOT_HIP(hipMemcpyAsync(flag_host, &ctrl->done, sizeof(uint32_t), hipMemcpyDeviceToHost, stream),
+                        "flag copy");
+                UOT_HIP(hipStreamSynchronize(stream), "flag sync");
+                if (*(volatile uint32_t*)flag_host) break;
+            }
+        }
+        if (last) break;
+        e = e * sch->factor > p->eps ? e * sch->factor : p->eps;
+    }
+    // Marginals at the final potentials, then the objective in potential form.
+    {
+        LseLaunch LM = L;
+        LM.P.check_done = 0;
+        LM.P.test_stop = 0;
+        LM.r_out = rbuf;
+        UOT_HIP(launch_lse(MODE_MARG, LM, stream), "log-domain marginal pass");
+        LseFinLaunch FM = F;
+        FM.marginal_only = 1;
+        FM.c_out = cbuf;
+        UOT_HIP(launch_lse_finalize(FM, stream), "log-domain marginal finalize");
+    }
+    ObjLaunch O;
+    memset(&O, 0, sizeof(O));
+    O.u = ones_n;
+    O.v = ones_m;
+    O.s = rbuf;
+    O.w = cbuf;
+    O.a = p->a;
+    O.b = p->b;
+    O.n = p->n;
+    O.m = p->m;
+    O.eps = p->eps;
+    O.tau = p->tau;
+    O.tau_inf = isinf(p->tau) ? 1 : 0;
+    O.r_out = out->r;
+    O.c_out = out->c;
+    O.loss = out->loss;
+    O.info = out->info;
+    O.ctrl = ctrl;
+    O.tol = o->tol;
+    O.iters_run = total;
+    O.blockpart = bp;
+    O.fin_blocks = P.fin_blocks;
+    O.fpot = f;
+    O.gpot = g;
+    O.f_out = out->f;
+    O.g_out = out->g;
+    O.u_tot = out->u;
+    O.v_tot = out->v;
+    UOT_HIP(launch_objective(O, stream), "objective");
+    return UOT_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Implicit (envelope) backward: marginal passes only
 // ---------------------------------------------------------------------------
 struct ImpPlan {
@@ -2156,6 +2378,17 @@ uot_status uot_sinkhorn_points(const uot_problem* prob, const double* x, const d
                                double cost_scale, const uot_options* opt, const uot_outputs* out, void* ws,
                                size_t ws_bytes, void* stream) {
     return run_points(prob, x, y, dim, cost_scale, opt, out, ws, ws_bytes, (hipStream_t)stream);
+}
+
+size_t uot_sinkhorn_lse_workspace_size(const uot_problem* prob, const uot_options* opt, const uot_eps_schedule* sched) {
+    LsePlan P;
+    if (make_lse_plan(prob, opt, sched, P) != UOT_OK) return 0;
+    return P.total;
+}
+
+uot_status uot_sinkhorn_lse(const uot_problem* prob, const uot_options* opt, const uot_eps_schedule* sched,
+                            const uot_outputs* out, void* ws, size_t ws_bytes, void* stream) {
+    return run_lse(prob, opt, sched, out, ws, ws_bytes, (hipStream_t)stream);
 }
 
 size_t uot_matrix_rescale_workspace_size(const uot_problem* prob, const uot_options* opt) {

@@ -43,7 +43,8 @@ def test_struct_layouts_match_header(tmp_path):
     import subprocess
     from paper_2412_11079_amd import _lib
     structs = {"uot_info": _lib.Info, "uot_problem": _lib.Problem, "uot_options": _lib.Options,
-               "uot_outputs": _lib.Outputs, "uot_profile": _lib.Profile, "uot_batched_meta": _lib.BatchedMeta}
+               "uot_outputs": _lib.Outputs, "uot_profile": _lib.Profile, "uot_batched_meta": _lib.BatchedMeta,
+               "uot_eps_schedule": _lib.EpsSchedule}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "uot.h"', "int main(void){"]
     for cname, cls in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
