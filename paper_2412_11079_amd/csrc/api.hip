@@ -268,7 +268,7 @@ uot_status make_plan(const uot_problem* p, const uot_options* o, Plan& P, bool o
     P.persistent = o->persistent != 0;
     if (P.persistent && !o->fused)
         return fail(UOT_ERR_ARG, "the persistent loop runs the fused pass only");
-    if (P.persistent && s.rb != 1)
+    if (P.persistent && (s.rb != 1 || P.shape > 7))
         return fail(UOT_ERR_UNSUPPORTED, "the persistent loop runs the one-row shapes (0-7) only");
     int64_t target = 256LL * (1024 / s.wg);     // about one wave of workgroups on 256 CUs
     if (!P.persistent) {
