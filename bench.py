@@ -301,6 +301,29 @@ def fwd_bwd(uot, workloads, torch, dev, args):
         c_ms += e1.elapsed_time(e2)
         del gr
     c_ms /= reps
+    # every iterate stored by the forward (131 MB at 8192^2, T = 500): the
+    # reverse pass repeats no forward pass
+    s_fms = s_bms = 0.0
+    for _ in range(reps + 1):
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record()
+        C = uot.cost_from_points(x, y)
+        K = uot.kernel_from_cost(C, prob.eps, torch.float32)
+        del C
+        rs = uot.sinkhorn(a, b, K, eps=prob.eps, tau=prob.tau, max_iter=prob.max_iter, store_iterates=True)
+        e1.record()
+        gs = uot.sinkhorn_backward(rs, g, x=x, y=y)
+        e2.record()
+        torch.cuda.synchronize()
+        if _ > 0:       # the first round allocates the record
+            s_fms += e0.elapsed_time(e1)
+            s_bms += e1.elapsed_time(e2)
+    s_fms /= reps
+    s_bms /= reps
+    gc = uot.sinkhorn_backward(fwd(), g, x=x, y=y)
+    torch.cuda.synchronize()
+    stored_same = all(torch.equal(getattr(gs, k), getattr(gc, k)) for k in ("grad_a", "grad_b", "grad_x"))
+    del rs, gs, gc, K
     # implicit (envelope) gradients at the final scalings: no checkpoints
     r = uot.sinkhorn(a, b, uot.kernel_from_cost(uot.cost_from_points(x, y), prob.eps, torch.float32), eps=prob.eps,
                      tau=prob.tau, max_iter=prob.max_iter)
@@ -323,6 +346,8 @@ def fwd_bwd(uot, workloads, torch, dev, args):
                         f"{prob.checkpoint_every}, gradients for x, a, b",
             "fwd_ms": round(f_ms, 3), "bwd_ms": round(b_ms, 3), "fwd_bwd_ms": round(f_ms + b_ms, 3),
             "bwd_with_cost_grad_ms": round(c_ms, 3),
+            "stored_iterates": {"fwd_ms": round(s_fms, 3), "bwd_ms": round(s_bms, 3),
+                                "fwd_bwd_ms": round(s_fms + s_bms, 3), "grads_equal_checkpointed": stored_same},
             "implicit_bwd_ms": round(i_ms, 3), "implicit_vs_unrolled_normwise": imp_err,
             "cost_grad_tflop_s": round(2.0 * prob.n * prob.m * (2 * prob.max_iter + 2) / ((c_ms - b_ms) * 1e-3) / 1e12, 2)
             if c_ms > b_ms else None,

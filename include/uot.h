@@ -119,7 +119,9 @@ typedef struct uot_options {
     int32_t persistent;       /* fused only: 1 = the whole loop in one cooperative launch with grid
                                  barriers (UOT_ERR_UNSUPPORTED when the grid cannot be co-resident
                                  or m > workgroup size * grid); 0 = two launches per iteration */
-    int32_t reserved0;
+    int32_t store_iterates;   /* 1: write every iterate to outputs.ckpt (the reverse pass then reads
+                                 them instead of re-running forward passes); needs checkpoint_every = 0,
+                                 tol <= 0, persistent = 0 and no absorption; 0 = off */
 } uot_options;
 
 typedef struct uot_outputs {
@@ -131,7 +133,11 @@ typedef struct uot_outputs {
     uot_info* info;           /* optional: device report */
     double* ckpt;             /* with options.checkpoint_every = k > 0: device buffer of
                                  (ceil(max_iter/k) + 1) x 2m doubles; slot c holds v and K^T u
-                                 after iteration c*k (slot 0: the starting v) */
+                                 after iteration c*k (slot 0: the starting v).
+                                 With options.store_iterates = 1 and T = max_iter: device buffer of
+                                 (2T + 1) m + 2T n doubles, in four blocks: v_0 .. v_T (m each),
+                                 K^T u_1 .. K^T u_T (m each), u_1 .. u_T (n each) and the row sums
+                                 K v_0 .. K v_{T-1} (n each) */
     double* f;                /* optional: device n, eps * log(u_T) (finite where u_T overflows) */
     double* g;                /* optional: device m, eps * log(v_T) */
 } uot_outputs;
@@ -395,7 +401,11 @@ uot_status uot_sinkhorn_profiled(const uot_problem* prob, const uot_options* opt
  * with it and v_{t-1} times each coordinate of y), then the column partials
  * of K^T sbar.  Iterates are recomputed segment by segment from the
  * checkpoints of the forward call (same problem and options, including
- * checkpoint_every; the forward must not have been given u0/v0).
+ * checkpoint_every; the forward must not have been given u0/v0), or, when
+ * the forward stored every iterate (options.store_iterates = 1), read from
+ * that record with no forward pass repeated (one pass over K per reverse
+ * step instead of two; the gradients are the same to the bit, since the
+ * recomputed iterates are).
  *
  * The adjoint of K, Kbar, is a sum of 2T + 2 rank-1 terms (two per
  * iteration, two from the objective); dL/dC_ij = -Kbar_ij K_ij / eps.  When
@@ -405,7 +415,7 @@ uot_status uot_sinkhorn_profiled(const uot_problem* prob, const uot_options* opt
  * its epilogue.
  *
  *   u, v        forward results u_T, v_T (device, n and m)
- *   ckpt        the forward's outputs.ckpt
+ *   ckpt        the forward's outputs.ckpt (checkpoints or the stored iterates)
  *   grad_loss   device scalar g; outputs are g times dL/d(input)
  *   grad_a      device n or NULL;  grad_b  device m or NULL
  *   grad_C      device n x ldgc FP64 (row-major, ldgc >= m; columns [m, ldgc)
@@ -419,7 +429,8 @@ uot_status uot_sinkhorn_profiled(const uot_problem* prob, const uot_options* opt
  *   grad_y      device m x dim or NULL: dL/dy_j = 2 sum_i G_ij (y_j - x_i),
  *               from column sums in the product's epilogue (needs x)
  *
- * Requirements: max_iter >= 1, checkpoint_every >= 1, tol <= 0, histogram
+ * Requirements: max_iter >= 1, checkpoint_every >= 1 or store_iterates = 1
+ * (not both), tol <= 0, histogram
  * entries > 0, rows of at most 8192 columns (FP32 or FP64 K).
  * Errors: UOT_ERR_ARG, UOT_ERR_UNSUPPORTED, UOT_ERR_WORKSPACE, UOT_ERR_ALIGN,
  * UOT_ERR_HIP.  Workspace: uot_sinkhorn_backward_workspace_size bytes, with

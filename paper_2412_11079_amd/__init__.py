@@ -165,12 +165,15 @@ def sinkhorn(a: torch.Tensor, b: torch.Tensor, K: Optional[torch.Tensor] = None,
              k_dtype: Optional[torch.dtype] = None, u0: Optional[torch.Tensor] = None,
              v0: Optional[torch.Tensor] = None, persistent: bool = False,
              checkpoint_every: int = 0, absorb_log_threshold: float = 0.0,
-             profile: bool = False) -> SinkhornResult:
+             profile: bool = False, store_iterates: bool = False) -> SinkhornResult:
     """UOT Sinkhorn scaling loop on the GPU (see include/uot.h, uot_sinkhorn).
 
     ``K`` is an (n, ldk) FP32/FP64 kernel (as returned by kernel_from_cost);
     ``m`` is the logical column count (default ``b.shape[0]``).  Without K, the
-    FP64 cost ``C`` is turned into a kernel of ``k_dtype`` inside the call."""
+    FP64 cost ``C`` is turned into a kernel of ``k_dtype`` inside the call.
+    ``checkpoint_every=k`` keeps every k-th v for ``sinkhorn_backward``;
+    ``store_iterates`` keeps every iterate instead ((2T + 1) m + 2T n
+    doubles), so that the reverse pass repeats no forward pass."""
     device = a.device
     n = a.shape[0]
     m = b.shape[0] if m is None else int(m)
@@ -192,6 +195,7 @@ def sinkhorn(a: torch.Tensor, b: torch.Tensor, K: Optional[torch.Tensor] = None,
     opt.u0 = None if u0 is None else _vec64(u0, "u0", n, device).data_ptr()
     opt.v0 = None if v0 is None else _vec64(v0, "v0", m, device).data_ptr()
     opt.persistent = 1 if persistent else 0
+    opt.store_iterates = 1 if store_iterates else 0
     L = _lib.lib()
     need = L.uot_sinkhorn_workspace_size(ctypes.byref(prob), ctypes.byref(opt))
     if need == 0:
@@ -207,6 +211,9 @@ def sinkhorn(a: torch.Tensor, b: torch.Tensor, K: Optional[torch.Tensor] = None,
     if checkpoint_every > 0:
         slots = (int(max_iter) + int(checkpoint_every) - 1) // int(checkpoint_every) + 1
         ckpt = torch.zeros(slots * 2 * m, dtype=torch.float64, device=device)
+    elif store_iterates and max_iter > 0:
+        T = int(max_iter)
+        ckpt = torch.empty((2 * T + 1) * m + 2 * T * n, dtype=torch.float64, device=device)
     fpot = torch.empty(n, dtype=torch.float64, device=device)
     gpot = torch.empty(m, dtype=torch.float64, device=device)
     out = _lib.Outputs(u.data_ptr(), v.data_ptr(), r.data_ptr(), c.data_ptr(), loss.data_ptr(), info.data_ptr(),
@@ -465,13 +472,14 @@ class Gradients:
 def sinkhorn_backward(res: SinkhornResult, grad_loss: torch.Tensor, *, x: Optional[torch.Tensor] = None,
                       y: Optional[torch.Tensor] = None, want_a: bool = True, want_b: bool = True,
                       want_x: bool = True, want_C: bool = False, want_y: bool = False) -> Gradients:
-    """Reverse pass of ``sinkhorn(..., checkpoint_every=k)`` (include/uot.h,
+    """Reverse pass of ``sinkhorn(..., checkpoint_every=k)`` or
+    ``sinkhorn(..., store_iterates=True)`` (include/uot.h,
     uot_sinkhorn_backward).  ``grad_loss`` is a device FP64 scalar.  With the
     points ``x`` (n x d) and ``y`` (m x d) of an un-normalised squared-Euclidean
     cost, also dL/dx (``want_x``) and dL/dy (``want_y``); ``want_C`` gives
     the dense dL/dC (n x m FP64)."""
     if res.ckpt is None:
-        raise ValueError("the forward call needs checkpoint_every > 0")
+        raise ValueError("the forward call needs checkpoint_every > 0 or store_iterates")
     prob, opt = res._problem, res._options
     device = res.u.device
     n, m = res.u.shape[0], res.v.shape[0]

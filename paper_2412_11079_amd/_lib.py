@@ -33,7 +33,7 @@ class Problem(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("max_iter", _i32), ("check_every", _i32), ("tol", _dbl), ("fused", _i32), ("accum", _i32),
                 ("absorb_log_threshold", _dbl), ("checkpoint_every", _i32), ("tune", _i32),
-                ("u0", _vp), ("v0", _vp), ("persistent", _i32), ("reserved0", _i32)]
+                ("u0", _vp), ("v0", _vp), ("persistent", _i32), ("store_iterates", _i32)]
 
 
 class Outputs(ctypes.Structure):

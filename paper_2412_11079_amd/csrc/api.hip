@@ -162,6 +162,10 @@ struct Plan {
     size_t off_ctrl, off_cprev, off_w, off_s, off_bp, off_part, off_k, off_stab, total;
 };
 
+// Options that record the forward's iterates (checkpoints or every iterate),
+// which only the single-problem stored-kernel loop supports.
+bool records_iterates(const uot_options* o) { return o->checkpoint_every != 0 || o->store_iterates != 0; }
+
 uot_status check_problem(const uot_problem* p, const uot_options* o) {
     if (!p || !o) return fail(UOT_ERR_ARG, "problem and options must not be NULL");
     if (p->n < 1 || p->m < 1) return fail(UOT_ERR_ARG, "empty problem (n=%lld, m=%lld)", (long long)p->n, (long long)p->m);
@@ -179,6 +183,11 @@ uot_status check_problem(const uot_problem* p, const uot_options* o) {
     if (o->checkpoint_every < 0) return fail(UOT_ERR_ARG, "checkpoint_every must be >= 0");
     if (o->checkpoint_every > 0 && (o->tol > 0.0 || o->persistent))
         return fail(UOT_ERR_UNSUPPORTED, "checkpoints need a fixed iteration count (tol <= 0) and per-iteration launches");
+    if (o->store_iterates != 0 && o->store_iterates != 1) return fail(UOT_ERR_ARG, "store_iterates must be 0 or 1");
+    if (o->store_iterates && (o->checkpoint_every != 0 || o->tol > 0.0 || o->persistent || stab))
+        return fail(UOT_ERR_UNSUPPORTED,
+                    "stored iterates need checkpoint_every = 0, a fixed iteration count (tol <= 0), per-iteration "
+                    "launches and no absorption");
     if (p->k_dtype != UOT_F64 && p->k_dtype != UOT_F32 && p->k_dtype != UOT_BF16 && p->k_dtype != UOT_FP8_E4M3)
         return fail(UOT_ERR_DTYPE, "K dtype %d not supported", (int)p->k_dtype);
     if ((p->k_dtype == UOT_BF16 || p->k_dtype == UOT_FP8_E4M3) && (!o->fused || o->persistent))
@@ -428,6 +437,20 @@ uot_status run_sinkhorn(const uot_problem* p, const uot_options* o, const uot_ou
         UOT_HIP(hipMemcpyAsync(out->ckpt, out->v, sizeof(double) * p->m, hipMemcpyDeviceToDevice, stream),
                 "checkpoint copy");
     }
+    // Stored iterates: iteration t reads v_{t-1} and writes u_t, its row sums,
+    // v_t and K^T u_t straight into the record (blocks V, W, U, S).
+    const bool store = o->store_iterates != 0;
+    double *tr_v = nullptr, *tr_w = nullptr, *tr_u = nullptr, *tr_s = nullptr;
+    if (store && o->max_iter > 0) {
+        if (!out->ckpt) return fail(UOT_ERR_ARG, "store_iterates needs outputs->ckpt");
+        if (!aligned(out->ckpt, 8)) return fail(UOT_ERR_ALIGN, "ckpt must be 8-byte aligned");
+        const size_t T = (size_t)o->max_iter;
+        tr_v = out->ckpt;
+        tr_w = tr_v + (T + 1) * p->m;
+        tr_u = tr_w + T * p->m;
+        tr_s = tr_u + T * p->n;
+        UOT_HIP(hipMemcpyAsync(tr_v, sv, sizeof(double) * p->m, hipMemcpyDeviceToDevice, stream), "iterate copy");
+    }
 
     PassLaunch L;
     memset(&L, 0, sizeof(L));
@@ -527,17 +550,27 @@ uot_status run_sinkhorn(const uot_problem* p, const uot_options* o, const uot_ou
         sample = prof && (t % kProfileStride == 0);
         L.iter = t + 1;
         PassLaunch L1 = L;
+        FinLaunch F1 = F;
+        if (store) {
+            L1.v = tr_v + (size_t)t * p->m;
+            L1.u = tr_u + (size_t)t * p->n;
+            L1.s_trace = tr_s + (size_t)t * p->n;
+            F1.v = tr_v + (size_t)(t + 1) * p->m;
+            F1.w_out = tr_w + (size_t)t * p->m;
+        }
+        PassLaunch L2 = L1;     // the column pass of the unfused form
         L1.test_stop = 1;       // the first pass of an iteration applies the stopping test
+        L2.s_trace = nullptr;
         if (fused) {
             UOT_HIP(timed(K_FUSED, [&] { return launch_pass(P.k_dtype, P.acc64, MODE_FUSED, P.shape, L1, stream); }),
                     "fused pass");
         } else {
             UOT_HIP(timed(K_ROW, [&] { return launch_pass(P.k_dtype, P.acc64, MODE_ROW, P.shape, L1, stream); }),
                     "row pass");
-            UOT_HIP(timed(K_COL, [&] { return launch_pass(P.k_dtype, P.acc64, MODE_COL, P.shape, L, stream); }),
+            UOT_HIP(timed(K_COL, [&] { return launch_pass(P.k_dtype, P.acc64, MODE_COL, P.shape, L2, stream); }),
                     "column pass");
         }
-        UOT_HIP(timed(K_FIN, [&] { return launch_finalize(F, stream); }), "column finalize");
+        UOT_HIP(timed(K_FIN, [&] { return launch_finalize(F1, stream); }), "column finalize");
         iters_run = t + 1;
         if (P.stab && (t + 1) % check_every == 0 && t + 1 < o->max_iter) {
             // Absorb when a scaling's log leaves [-threshold, threshold] (above
@@ -583,6 +616,14 @@ uot_status run_sinkhorn(const uot_problem* p, const uot_options* o, const uot_ou
     }
     sample = false;
     if (prof) UOT_HIP(hipEventRecord(ev[evi++], stream), "hipEventRecord");
+    if (store && iters_run > 0) {
+        UOT_HIP(hipMemcpyAsync(su, tr_u + (size_t)(iters_run - 1) * p->n, sizeof(double) * p->n,
+                               hipMemcpyDeviceToDevice, stream),
+                "iterate copy");
+        UOT_HIP(hipMemcpyAsync(sv, tr_v + (size_t)iters_run * p->m, sizeof(double) * p->m, hipMemcpyDeviceToDevice,
+                               stream),
+                "iterate copy");
+    }
 
     // Marginals of the final scalings: s = K v_T and w = K^T u_T in one pass.
     PassLaunch LM = L;
@@ -667,6 +708,7 @@ struct BwdPlan {
     int32_t G;
     int32_t dim;
     int k, nseg;
+    bool stored;              // the forward stored every iterate: no recompute
     bool cost_grad;           // store the factors of Kbar for dL/dC or dL/dy
     int64_t nterms;           // 2T + 2, padded to a multiple of kGradcSlotPad
     int64_t ldl, ldr;         // n and m padded to kGradcRowPad (factor row lengths)
@@ -682,7 +724,8 @@ uot_status make_bwd_plan(const uot_problem* p, const uot_options* o, int64_t dim
     uot_status st = make_plan(p, &fo, B.F);
     if (st != UOT_OK) return st;
     if (o->max_iter < 1) return fail(UOT_ERR_ARG, "the reverse pass needs max_iter >= 1");
-    if (o->checkpoint_every < 1) return fail(UOT_ERR_ARG, "the reverse pass needs checkpoint_every >= 1");
+    if (o->store_iterates ? o->checkpoint_every != 0 : o->checkpoint_every < 1)
+        return fail(UOT_ERR_ARG, "the reverse pass needs checkpoint_every >= 1 or stored iterates (not both)");
     if (o->tol > 0.0) return fail(UOT_ERR_UNSUPPORTED, "the reverse pass differentiates a fixed iteration count (tol <= 0)");
     if (p->k_dtype != UOT_F32 && p->k_dtype != UOT_F64)
         return fail(UOT_ERR_DTYPE, "the reverse pass runs with FP32 or FP64 K");
@@ -698,8 +741,9 @@ uot_status make_bwd_plan(const uot_problem* p, const uot_options* o, int64_t dim
     B.rows_per_wg = (p->n + target - 1) / target;
     B.G = (int32_t)((p->n + B.rows_per_wg - 1) / B.rows_per_wg);
     B.dim = (int32_t)dim;
-    B.k = o->checkpoint_every;
-    B.nseg = (o->max_iter + B.k - 1) / B.k;
+    B.stored = o->store_iterates != 0;
+    B.k = B.stored ? 0 : o->checkpoint_every;      // recompute buffers hold one segment
+    B.nseg = B.stored ? 0 : (o->max_iter + B.k - 1) / B.k;
     const int64_t n = p->n, m = p->m;
     const size_t d8 = sizeof(double);
     const size_t acc = (p->k_dtype == UOT_F64) ? 8 : 4;
@@ -896,8 +940,48 @@ uot_status run_backward(const uot_problem* p, const uot_options* o, const double
         C2.w = wfin;
         UOT_HIP(launch_adj_col(C2, stream), "adjoint columns");
     }
-    // 4. segments, newest first: recompute the forward iterates, then reverse.
+    // 4. reverse steps t = T .. 1 over the iterates: read from the forward's
+    // record, or recomputed segment by segment (newest first) from checkpoints.
     const int T = o->max_iter;
+    auto reverse_step = [&](int t, const double* vprev, const double* ut, const double* st,
+                            const double* wprev) -> uot_status {
+        AdjLaunch S = A;
+        S.A = avec;
+        S.B = vprev;
+        S.u = ut;
+        S.s = st;
+        S.add_seed = (t == T) ? 1 : 0;
+        if (cost_grad) {
+            // slot 2t: u_t wbar_t^T, slot 2t + 1: sbar_t v_{t-1}^T
+            S.st_u = Lf + (int64_t)(2 * t) * ldl;
+            S.st_q = Lf + (int64_t)(2 * t + 1) * ldl;
+            S.st_a = Rf + (int64_t)(2 * t) * ldr;
+            S.st_b = Rf + (int64_t)(2 * t + 1) * ldr;
+        }
+        UOT_HIP(launch_adj(p->k_dtype, B.nc, ADJ_STEP, (int)dim, S, stream), "adjoint step pass");
+        if (t > 1) {
+            AdjColLaunch C3 = Cc;
+            C3.partials = A.partials;
+            C3.G = B.G;
+            C3.acc64 = (p->k_dtype == UOT_F64);
+            C3.mode = ADJ_COL_STEP;
+            C3.v = vprev;
+            C3.w = (double*)wprev;
+            UOT_HIP(launch_adj_col(C3, stream), "adjoint columns");
+        }
+        return UOT_OK;
+    };
+    if (B.stored) {
+        const double* tv = ckpt;                       // v_0 .. v_T
+        const double* tw = tv + (size_t)(T + 1) * m;   // K^T u_1 .. K^T u_T
+        const double* tu = tw + (size_t)T * m;         // u_1 .. u_T
+        const double* ts = tu + (size_t)T * n;         // K v_0 .. K v_{T-1}
+        for (int t = T; t >= 1; --t) {
+            st = reverse_step(t, tv + (size_t)(t - 1) * m, tu + (size_t)(t - 1) * n, ts + (size_t)(t - 1) * n,
+                              t > 1 ? tw + (size_t)(t - 2) * m : nullptr);
+            if (st != UOT_OK) return st;
+        }
+    }
     for (int c = B.nseg - 1; c >= 0; --c) {
         const int t0 = c * B.k;
         const int len = std::min(B.k, T - t0);
@@ -915,32 +999,9 @@ uot_status run_backward(const uot_problem* p, const uot_options* o, const double
             UOT_HIP(launch_finalize(FF, stream), "recompute finalize");
         }
         for (int q = len - 1; q >= 0; --q) {
-            const int t = t0 + q + 1;
-            const double* vprev = (q == 0) ? v0 : vtr + (size_t)(q - 1) * m;
-            AdjLaunch S = A;
-            S.A = avec;
-            S.B = vprev;
-            S.u = utr + (size_t)q * n;
-            S.s = str + (size_t)q * n;
-            S.add_seed = (t == T) ? 1 : 0;
-            if (cost_grad) {
-                // slot 2t: u_t wbar_t^T, slot 2t + 1: sbar_t v_{t-1}^T
-                S.st_u = Lf + (int64_t)(2 * t) * ldl;
-                S.st_q = Lf + (int64_t)(2 * t + 1) * ldl;
-                S.st_a = Rf + (int64_t)(2 * t) * ldr;
-                S.st_b = Rf + (int64_t)(2 * t + 1) * ldr;
-            }
-            UOT_HIP(launch_adj(p->k_dtype, B.nc, ADJ_STEP, (int)dim, S, stream), "adjoint step pass");
-            if (t > 1) {
-                AdjColLaunch C3 = Cc;
-                C3.partials = A.partials;
-                C3.G = B.G;
-                C3.acc64 = (p->k_dtype == UOT_F64);
-                C3.mode = ADJ_COL_STEP;
-                C3.v = vprev;
-                C3.w = (double*)((q == 0) ? w0 : wtr + (size_t)(q - 1) * m);
-                UOT_HIP(launch_adj_col(C3, stream), "adjoint columns");
-            }
+            st = reverse_step(t0 + q + 1, (q == 0) ? v0 : vtr + (size_t)(q - 1) * m, utr + (size_t)q * n,
+                              str + (size_t)q * n, (q == 0) ? w0 : wtr + (size_t)(q - 1) * m);
+            if (st != UOT_OK) return st;
         }
     }
     AdjFinish Fin;
@@ -994,7 +1055,7 @@ uot_status make_matrix_plan(const uot_problem* p, const uot_options* o, Plan& P)
     if (!p->K) return fail(UOT_ERR_ARG, "the in-place form rescales the matrix given as K");
     if (p->k_dtype != UOT_F32 && p->k_dtype != UOT_F64)
         return fail(UOT_ERR_DTYPE, "the in-place form rescales an FP32 or FP64 matrix");
-    if (o->absorb_log_threshold != 0.0 || o->checkpoint_every != 0 || o->persistent || o->u0 || o->v0 || !o->fused ||
+    if (o->absorb_log_threshold != 0.0 || records_iterates(o) || o->persistent || o->u0 || o->v0 || !o->fused ||
         (p->k_dtype == UOT_F32 && o->accum == UOT_ACC_F64))
         return fail(UOT_ERR_UNSUPPORTED,
                     "the in-place form runs the fused per-iteration pass with the storage type's own arithmetic: "
@@ -1138,7 +1199,7 @@ uot_status make_points_plan(const uot_problem* p, int64_t dim, double cost_scale
         return fail(UOT_ERR_UNSUPPORTED, "the kernel-free pass holds rows of up to %lld columns (m=%lld)",
                     (long long)online_max_m(), (long long)p->m);
     if (o->max_iter < 0) return fail(UOT_ERR_ARG, "max_iter must be >= 0");
-    if (o->absorb_log_threshold != 0.0 || o->checkpoint_every != 0 || o->persistent || !o->fused ||
+    if (o->absorb_log_threshold != 0.0 || records_iterates(o) || o->persistent || !o->fused ||
         o->accum != UOT_ACC_F32)
         return fail(UOT_ERR_UNSUPPORTED,
                     "the kernel-free solve runs the fused per-iteration pass with FP32 lane arithmetic: no "
@@ -1325,7 +1386,7 @@ uot_status make_lse_plan(const uot_problem* p, const uot_options* o, const uot_e
         return fail(UOT_ERR_UNSUPPORTED, "rows of at most %lld columns for this cost storage (m=%lld)",
                     (long long)lse_max_m(p->k_dtype), (long long)p->m);
     if (o->max_iter < 0) return fail(UOT_ERR_ARG, "max_iter must be >= 0");
-    if (o->absorb_log_threshold != 0.0 || o->checkpoint_every != 0 || o->persistent || !o->fused || o->u0 || o->v0 ||
+    if (o->absorb_log_threshold != 0.0 || records_iterates(o) || o->persistent || !o->fused || o->u0 || o->v0 ||
         o->accum != UOT_ACC_F32)
         return fail(UOT_ERR_UNSUPPORTED,
                     "the log-domain solve runs its own fused pass: no absorption, checkpoints, cooperative loop, "
@@ -1535,6 +1596,7 @@ uot_status make_imp_plan(const uot_problem* p, const uot_options* o, int64_t dim
     fo.tol = 0.0;
     fo.absorb_log_threshold = 0.0;
     fo.checkpoint_every = 0;
+    fo.store_iterates = 0;
     fo.u0 = fo.v0 = nullptr;
     fo.max_iter = 1;
     uot_status st = make_plan(p, &fo, B.F);
@@ -1684,7 +1746,7 @@ uot_status check_batch_options(const uot_options* o) {
     if (!o) return fail(UOT_ERR_ARG, "options must not be NULL");
     if (o->max_iter < 0) return fail(UOT_ERR_ARG, "max_iter must be >= 0");
     if (o->tol > 0.0 && o->check_every < 1) return fail(UOT_ERR_ARG, "check_every must be >= 1");
-    if (o->absorb_log_threshold != 0.0 || o->checkpoint_every != 0 || o->persistent || o->u0 || o->v0)
+    if (o->absorb_log_threshold != 0.0 || records_iterates(o) || o->persistent || o->u0 || o->v0)
         return fail(UOT_ERR_UNSUPPORTED,
                     "batched problems run the plain iteration: no absorption, checkpoints, warm start or "
                     "cooperative loop");
@@ -2075,7 +2137,7 @@ uot_status make_multi_plan(const uot_problem* p, int32_t R, const uot_options* o
     if (!(p->eps > 0.0) || !isfinite(p->eps)) return fail(UOT_ERR_ARG, "eps must be finite and > 0");
     if (!(p->tau > 0.0)) return fail(UOT_ERR_ARG, "tau must be > 0 (or +inf)");
     if (o->max_iter < 1) return fail(UOT_ERR_ARG, "max_iter must be >= 1");
-    if (o->tol > 0.0 || o->absorb_log_threshold != 0.0 || o->checkpoint_every != 0 || o->persistent || o->u0 || o->v0)
+    if (o->tol > 0.0 || o->absorb_log_threshold != 0.0 || records_iterates(o) || o->persistent || o->u0 || o->v0)
         return fail(UOT_ERR_UNSUPPORTED,
                     "the multi-right-hand-side form runs a fixed iteration count with no absorption, "
                     "checkpoints or warm start");

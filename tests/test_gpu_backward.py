@@ -38,8 +38,9 @@ def _gpu_grads(prob, T, k, k_dtype, with_x=True, full=False, scale=1.0):
     x, y = to_dev(prob.x), to_dev(prob.y)
     C = uot.cost_from_points(x, y, prob.cost_kind, prob.normalize_max)
     K = uot.kernel_from_cost(C, prob.eps, k_dtype)
+    # k = 0: the forward stores every iterate
     res = uot.sinkhorn(to_dev(prob.a), to_dev(prob.b), K, m=prob.m, eps=prob.eps, tau=prob.tau, max_iter=T,
-                       checkpoint_every=k)
+                       checkpoint_every=k, store_iterates=(k == 0))
     g = torch.full((), scale, dtype=torch.float64, device="cuda")
     gr = uot.sinkhorn_backward(res, g, x=x if with_x else None, y=y if with_x else None, want_C=full,
                                want_y=full and with_x)
@@ -94,6 +95,30 @@ def test_checkpoint_interval_does_not_change_gradients():
             assert np.array_equal(g, g0)
 
 
+@pytest.mark.parametrize("k_dtype", [torch.float32, torch.float64])
+def test_stored_iterates_give_the_checkpointed_gradients(k_dtype):
+    """The reverse pass reading every stored iterate equals, to the bit, the
+    one recomputing them from checkpoints (same pass kernels on the same
+    inputs), for every gradient including dL/dC and dL/dy; the forward's
+    results do not change when it stores, and the record's last u and v are
+    the results."""
+    prob = workloads.grad(n=777, m=1500, max_iter=13)
+    say(f"stored iterates {k_dtype}")
+    ck = _gpu_grads(prob, 13, 5, k_dtype, full=True)
+    sto = _gpu_grads(prob, 13, 0, k_dtype, full=True)
+    for g, g0 in zip(sto[1:], ck[1:]):
+        assert np.array_equal(g, g0)
+    r0, r1 = ck[0], sto[0]
+    assert torch.equal(r0.u, r1.u) and torch.equal(r0.v, r1.v) and torch.equal(r0.loss, r1.loss)
+    n, m, T = prob.n, prob.m, 13
+    tr = r1.ckpt
+    assert tr.numel() == (2 * T + 1) * m + 2 * T * n
+    assert torch.equal(tr[T * m:(T + 1) * m], r1.v)
+    u_blk = tr[(2 * T + 1) * m:(2 * T + 1) * m + T * n]
+    assert torch.equal(u_blk[(T - 1) * n:], r1.u)
+    assert torch.all(tr[:m] == 1.0)
+
+
 def test_autograd_function_matches_direct_call():
     prob = workloads.grad(n=400, m=300, max_iter=30)
     x = to_dev(prob.x).requires_grad_(True)
@@ -120,6 +145,10 @@ def test_backward_argument_errors():
     with pytest.raises(uot.UOTError):
         uot.sinkhorn(to_dev(prob.a), to_dev(prob.b), K, eps=prob.eps, tau=prob.tau, max_iter=5,
                      checkpoint_every=2, tol=1e-6)
+    for bad in (dict(checkpoint_every=2), dict(tol=1e-6), dict(persistent=True)):
+        with pytest.raises(uot.UOTError, match="stored iterates"):
+            uot.sinkhorn(to_dev(prob.a), to_dev(prob.b), K, eps=prob.eps, tau=prob.tau, max_iter=5,
+                         store_iterates=True, **bad)
 
 
 def test_backward_directional_finite_differences_gpu():
