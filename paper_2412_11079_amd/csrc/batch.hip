@@ -20,6 +20,7 @@
 #include <math.h>
 
 #include "batch.h"
+#include "scalemath.h"
 #include "strip.h"
 
 namespace uot {
@@ -46,10 +47,15 @@ constexpr int nc_max() {
 // with one LDS exchange, and its R scaling factors are computed side by
 // side (lane r of each wave evaluates row r), so the long FP64 chain of the
 // power is paid once per batch, not once per row.  Two batches are in
-// registers (one being processed, the next one loading).
+// registers (one being processed, the next one loading).  A problem's time
+// follows its batch count, so R is as large as the registers allow (FP32:
+// 6, measured against 3, 4 and 5; a few spilled values cost less than the
+// batches saved).
+constexpr int kBatchMaxRows = 8;
 template <typename KT>
 constexpr int rows_per_batch() {
-    return (nc_max<KT>() >= 4 || KVec<KT>::N >= 16) ? 2 : 3;     // within 256 VGPRs
+    if (nc_max<KT>() >= 4 || KVec<KT>::N >= 16) return 2;      // FP64, FP8: within 256 VGPRs
+    return KVec<KT>::N == 4 ? 6 : 4;                            // FP32, BF16
 }
 
 // Block-wide FP64 sum in a fixed order; every thread receives the result.
@@ -89,6 +95,17 @@ __device__ __forceinline__ void part_barrier(uint32_t* hdr, uint32_t target) {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
+// (target / sum)^fi in FP64 with the log and exp of scalemath.h, whose
+// coefficients stay in scalar registers: the library routines would hold
+// theirs in vector registers across the whole problem loop.  Special
+// quotients follow the plain formula (0 -> 0, +inf -> +inf, NaN -> NaN).
+__device__ __forceinline__ double batch_factor(double target, double sum, double fi, int fi_is_one) {
+    if (target == 0.0) return 0.0;
+    const double q = target / sum;
+    if (fi_is_one || !(q > 0.0) || q == INFINITY) return q;
+    return sm::exp_any(fi * sm::log_pos(q));
+}
+
 __device__ __forceinline__ double kl_term(double x, double y) {
     // x log(x/y) - x + y with 0 log 0 = 0
     if (x > 0.0) return x * log(x / y) - x + y;
@@ -96,7 +113,7 @@ __device__ __forceinline__ double kl_term(double x, double y) {
 }
 
 struct BatchShared {
-    double red[2][4][kBatchNW];
+    double red[2][kBatchMaxRows][kBatchNW];
     double scratch[kBatchNW];
     int32_t idx;
     uint32_t flags;
@@ -110,6 +127,7 @@ struct BatchSolve {
     static constexpr int NCM = nc_max<KT>();
     static constexpr int E = NCM * V;
     static constexpr int R = rows_per_batch<KT>();
+    static_assert(R <= kBatchMaxRows, "row exchange holds kBatchMaxRows rows");
 
     __amdgpu_buffer_rsrc_t rsrc;
     uint32_t row_bytes;
@@ -117,12 +135,18 @@ struct BatchSolve {
     int col[NCM];                       // first column of each chunk (m < 2^31)
     uint32_t voff[NCM];
     Raw buf[2][R][NCM];
+    double abuf[2];                     // a of the batch row lane r (r < R) holds, loaded with the rows
+    const double* pa;
+    int64_t pn;
     double acc[E];
 
     // Rows k = b R + r (r < R) of the group, i = grp + rg k, into buffer Q;
     // rows beyond the matrix read 0.
     template <int Q>
     __device__ __forceinline__ void load_batch(int64_t b) {
+        const int lane = threadIdx.x & 63;
+        const int64_t il = grp + (int64_t)rg * (b * R + (lane < R ? lane : 0));
+        abuf[Q] = (lane < R && il < pn) ? pa[il] : 0.0;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const uint32_t soff = (uint32_t)(grp + (int64_t)rg * (b * R + r)) * row_bytes;
@@ -138,6 +162,21 @@ struct BatchSolve {
     template <int Q>
     __device__ __forceinline__ void unpack(int r, int c, int m, bool ragged, double* x) const {
         Unpack<KT, double>::run(buf[Q][r][c], x);
+        if (ragged) {
+#pragma unroll
+            for (int e = 0; e < V; ++e)
+                if (col[c] + e >= m) x[e] = 0.0;
+        }
+    }
+
+    // The same chunk widened afresh for the column update: the opaque copy
+    // keeps the compiler from holding the row dot's widened values (twice
+    // the registers of the stored ones) across the scaling factors.
+    template <int Q>
+    __device__ __forceinline__ void unpack_again(int r, int c, int m, bool ragged, double* x) const {
+        Raw q = buf[Q][r][c];
+        asm volatile("" : "+v"(q));
+        Unpack<KT, double>::run(q, x);
         if (ragged) {
 #pragma unroll
             for (int e = 0; e < V; ++e)
@@ -202,8 +241,8 @@ struct BatchSolve {
         const int64_t il = grp + (int64_t)rg * (b * R + (lane < R ? lane : 0));
         double ul = 0.0;
         if (lane < R && il < P.n) {
-            const double ai = P.a[il];
-            ul = scale_factor(ai, tl, P.fi, P.fi_is_one, 0.0);
+            const double ai = abuf[Q];
+            ul = batch_factor(ai, tl, P.fi, P.fi_is_one);
             if (gl < R) {              // the group's first wave writes
                 P.u[il] = ul;
                 if (ai > 0.0 && !(tl > 0.0)) fl |= UOT_FLAG_ZERO_SUM;
@@ -217,7 +256,7 @@ struct BatchSolve {
             for (int c = 0; c < NCM; ++c) {
                 if (c < nc) {
                     double x[V];
-                    unpack<Q>(r, c, m, ragged, x);
+                    unpack_again<Q>(r, c, m, ragged, x);
 #pragma unroll
                     for (int e = 0; e < V; ++e) acc[c * V + e] = fma(x[e], ur, acc[c * V + e]);
                 }
@@ -256,9 +295,15 @@ struct BatchSolve {
         gl = tid % lr;
         const int64_t n = P.n;
         const int m = (int)P.m;
+        pa = P.a;
+        pn = n;
         row_bytes = (uint32_t)(P.ldk * (int64_t)sizeof(KT));
         const uint32_t total = (uint32_t)(n * row_bytes);
-        rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)P.K, (short)0, (int)total, kBufferWord3);
+        const uint64_t kp = (uint64_t)(uintptr_t)P.K;
+        const uint32_t k_lo = __builtin_amdgcn_readfirstlane((uint32_t)kp);
+        const uint32_t k_hi = __builtin_amdgcn_readfirstlane((uint32_t)(kp >> 32));
+        rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)(uintptr_t)(((uint64_t)k_hi << 32) | k_lo), (short)0,
+                                                 (int)__builtin_amdgcn_readfirstlane(total), kBufferWord3);
 #pragma unroll
         for (int c = 0; c < NCM; ++c) {
             col[c] = (c * lr + gl) * V;
@@ -350,7 +395,7 @@ struct BatchSolve {
                         if (c < nc && j < m) {
                             const double w = ((rg > 1 || split) ? wl[j] : acc[c * V + e]) * P.k_scale;
                             const double bj = P.b[j];
-                            const double vj = scale_factor(bj, w, P.fi, P.fi_is_one, 0.0);
+                            const double vj = batch_factor(bj, w, P.fi, P.fi_is_one);
                             if (bj > 0.0 && !(w > 0.0)) fl |= UOT_FLAG_ZERO_SUM;
                             if (!isfinite(vj)) fl |= UOT_FLAG_NONFINITE;
                             vl[j] = vj;
