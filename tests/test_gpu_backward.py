@@ -119,6 +119,44 @@ def test_stored_iterates_give_the_checkpointed_gradients(k_dtype):
     assert torch.all(tr[:m] == 1.0)
 
 
+def test_stored_record_layout_and_unfused_forward():
+    """Every block of the record holds the iterate it is documented to hold:
+    v_t and u_t equal the results of a t-iteration solve (same kernels, bit
+    for bit), K^T u_t and the row sums K v_{t-1} match the oracle's products
+    of those iterates; the unfused forward (row pass + column pass) also
+    records, and its reverse pass meets the FP64 gradient bar."""
+    prob = workloads.grad(n=300, m=457, max_iter=9)
+    x, y = to_dev(prob.x), to_dev(prob.y)
+    C = uot.cost_from_points(x, y, prob.cost_kind, prob.normalize_max)
+    K = uot.kernel_from_cost(C, prob.eps, torch.float64)
+    a, b = to_dev(prob.a), to_dev(prob.b)
+    n, m, T = prob.n, prob.m, 9
+    kw = dict(m=m, eps=prob.eps, tau=prob.tau)
+    full = uot.sinkhorn(a, b, K, max_iter=T, store_iterates=True, **kw)
+    torch.cuda.synchronize()
+    tr = full.ckpt
+    V = tr[:(T + 1) * m].reshape(T + 1, m)
+    W = tr[(T + 1) * m:(2 * T + 1) * m].reshape(T, m)
+    U = tr[(2 * T + 1) * m:(2 * T + 1) * m + T * n].reshape(T, n)
+    S = tr[(2 * T + 1) * m + T * n:].reshape(T, n)
+    Kh = K[:, :m].cpu().numpy()
+    for t in (1, 4, T):
+        part = uot.sinkhorn(a, b, K, max_iter=t, **kw)
+        torch.cuda.synchronize()
+        assert torch.equal(V[t], part.v) and torch.equal(U[t - 1], part.u), t
+        np.testing.assert_allclose(W[t - 1].cpu().numpy(), Kh.T @ U[t - 1].cpu().numpy(), rtol=1e-12)
+        np.testing.assert_allclose(S[t - 1].cpu().numpy(), Kh @ V[t - 1].cpu().numpy(), rtol=1e-12)
+    ref, ga0, gb0, gx0 = _oracle_grads(prob, T)
+    unf = uot.sinkhorn(a, b, K, max_iter=T, store_iterates=True, fused=False, **kw)
+    g = torch.ones((), dtype=torch.float64, device="cuda")
+    gr = uot.sinkhorn_backward(unf, g, x=x, y=y)
+    torch.cuda.synchronize()
+    for name, gv, r in (("a", gr.grad_a, ga0), ("b", gr.grad_b, gb0), ("x", gr.grad_x, gx0)):
+        e = _norm_err(gv.cpu().numpy(), r)
+        say(f"  unfused stored grad_{name}: {e:.3e}")
+        assert e <= 1e-9, name
+
+
 def test_autograd_function_matches_direct_call():
     prob = workloads.grad(n=400, m=300, max_iter=30)
     x = to_dev(prob.x).requires_grad_(True)
