@@ -10,7 +10,7 @@ struct OnlineLaunch {
     const double* y;          // m x dim target points
     const double* rows;       // n x 4: x'_i (2 c x_i, zero-padded to 3) and alpha_i = -c |x_i|^2
     const double* beta;       // m: beta_j = -c |y_j|^2
-    const double* loga;       // n: log a_i (0 where a_i = 0)
+    const double* loga;       // n: log2 a_i (0 where a_i = 0)
     int32_t dim;              // 2 or 3
 };
 
@@ -21,7 +21,7 @@ int online_rows_per_group(int dim, int64_t m);
 // Workgroups of the pass for rows of m columns that one compute unit holds.
 int online_wgs_per_cu(int dim, int64_t m);
 // Row and column terms of the exponent (rows, beta above) from the points
-// and log a,
+// and log2 a,
 // c = cost_scale log2(e) / eps; once per solve.
 hipError_t launch_online_setup(const double* x, const double* y, const double* a, int64_t n, int64_t m, int dim,
                                double c, double* rows, double* beta, double* loga, hipStream_t stream);

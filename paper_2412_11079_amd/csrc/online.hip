@@ -27,7 +27,6 @@
 // column finalize sums the partials as for a stored K.  Row terms (x'_i,
 // alpha_i) are wave-uniform and read by scalar loads.
 #include "online.h"
-#include "scalemath.h"
 #include "strip.h"
 
 namespace uot {
@@ -39,7 +38,7 @@ __global__ void online_setup_kernel(const double* __restrict__ x, const double* 
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n) {
         const double ai = a[t];
-        loga[t] = ai > 0.0 ? log(ai) : 0.0;
+        loga[t] = ai > 0.0 ? log2(ai) : 0.0;
         double xd[3] = {0.0, 0.0, 0.0}, nx = 0.0;
         for (int d = 0; d < dim; ++d) {
             xd[d] = x[t * dim + d];
@@ -53,6 +52,27 @@ __global__ void online_setup_kernel(const double* __restrict__ x, const double* 
         for (int d = 0; d < dim; ++d) ny = fma(y[j * dim + d], y[j * dim + d], ny);
         beta[j] = -c * ny;
     }
+}
+
+// u = (a / s)^fi = 2^(fi (log2 a - log2 s)) at the precision of the pass's
+// own entries: log2 s = e + log2(mant), the mantissa's log2 split as
+// log2(mh) + ml / (mh ln 2) with mh its FP32 rounding (hardware log2, error
+// ~6e-8 absolute on [-1, 0)) and ml = mant - mh exact; the exponent is
+// kept in FP64 and split into an integer and a fraction in [-1/2, 1/2]
+// for the hardware exp2 (relative error ~1e-7), the integer applied by
+// ldexp.  Special totals follow the plain formula (0 -> +inf, +inf -> 0).
+__device__ __forceinline__ double online_scaling(double log2a, double s, double fi) {
+    if (s != s) return s;
+    if (s == 0.0) return INFINITY;
+    if (s == INFINITY) return 0.0;
+    int e = 0;
+    const double mt = frexp(s, &e);                   // [1/2, 1)
+    const float mh = (float)mt;
+    const float ml = (float)(mt - (double)mh);
+    const float l2m = __builtin_amdgcn_logf(mh) + ml * __builtin_amdgcn_rcpf(mh) * 1.44269504f;
+    const double y = fi * (log2a - ((double)e + (double)l2m));
+    const double k = __builtin_rint(y);
+    return ldexp((double)__builtin_amdgcn_exp2f((float)(y - k)), (int)fmax(fmin(k, 2100.0), -2100.0));
 }
 
 // BL: beta and v of the lane's columns sit in LDS (read once per group of R
@@ -151,7 +171,7 @@ __global__ __launch_bounds__(WG) void online_kernel(OnlineLaunch O, const double
                 if (wave == 0) L.s_out[i] = tot;
             } else {
                 const double ai = L.a[i];
-                uu = ai == 0.0 ? 0.0 : L.fi_is_one ? ai / tot : sm::scaling_pow(O.loga[i], tot, L.fi);
+                uu = ai == 0.0 ? 0.0 : L.fi_is_one ? ai / tot : online_scaling(O.loga[i], tot, L.fi);
                 if (wave == 0) {
                     L.u[i] = uu;
                     if (ai > 0.0 && !(tot > 0.0)) atomicOr(&L.ctrl->flags, UOT_FLAG_ZERO_SUM);

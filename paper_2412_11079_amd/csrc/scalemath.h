@@ -1,5 +1,5 @@
 // FP64 natural logarithm and exponential for the scaling update
-// u = (a / s)^fi = exp(fi (log a - log s)) of the kernel-free pass.
+// u = (a / s)^fi = exp(fi (log a - log s)) of the batched solve.
 //
 // Written from the textbook reductions, for a caller that evaluates them
 // once per row inside a register-bound loop (the library routines keep
