@@ -1,4 +1,4 @@
-// Accuracy of the kernel-free pass's FP64 log / exp / scaling power
+// Accuracy of the library's FP64 log / exp / scaling power (the batched solve's factors)
 // (paper_2412_11079_amd/csrc/scalemath.h, compiled here for the host)
 // against long-double libm.  Prints one line of key=value pairs.
 #include <cmath>

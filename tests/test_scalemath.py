@@ -1,4 +1,4 @@
-"""The kernel-free pass forms its scalings u = (a/s)^fi with its own FP64
+"""The batched solve forms its scalings u = (a/s)^fi with the library's own FP64
 log and exp (paper_2412_11079_amd/csrc/scalemath.h: the atanh series for
 log, Cody-Waite reduction and the Taylor series for exp).  The same header
 is compiled here for the host with g++ and checked against long-double
