@@ -567,8 +567,9 @@ class UOTLoss(torch.autograd.Function):
 
     Forward: squared-Euclidean cost of (x, y) (not normalised), Gibbs kernel
     in ``k_dtype``, ``max_iter`` fused iterations with v and K^T u saved every
-    ``checkpoint_every``; backward: the library's reverse pass (dL/dy through
-    the dense cost gradient, formed only when y needs a gradient)."""
+    ``checkpoint_every`` (0: every iterate kept, so that the reverse pass
+    repeats no forward pass); backward: the library's reverse pass (dL/dy
+    through the dense cost gradient, formed only when y needs a gradient)."""
 
     @staticmethod
     def forward(ctx, x, y, a, b, eps: float, tau: float, max_iter: int, checkpoint_every: int = 50,
@@ -578,8 +579,10 @@ class UOTLoss(torch.autograd.Function):
         C = cost_from_points(x64, y64, UOT_COST_SQEUCLID, False)
         K = kernel_from_cost(C, eps, k_dtype)
         del C
+        store = not implicit and checkpoint_every == 0
         res = sinkhorn(a.detach().to(torch.float64).contiguous(), b.detach().to(torch.float64).contiguous(), K,
-                       eps=eps, tau=tau, max_iter=max_iter, checkpoint_every=0 if implicit else checkpoint_every)
+                       eps=eps, tau=tau, max_iter=max_iter, checkpoint_every=0 if implicit else checkpoint_every,
+                       store_iterates=store)
         ctx.res = res
         ctx.implicit = implicit
         ctx.save_for_backward(x64, y64)
@@ -602,7 +605,8 @@ class UOTLoss(torch.autograd.Function):
 
 class UOTCostLoss(torch.autograd.Function):
     """UOT objective of the unrolled loop on a dense FP64 cost C, with
-    gradients w.r.t. C (dense, on the matrix cores), a and b."""
+    gradients w.r.t. C (dense, on the matrix cores), a and b
+    (``checkpoint_every`` 0: every iterate kept, as for UOTLoss)."""
 
     @staticmethod
     def forward(ctx, C, a, b, eps: float, tau: float, max_iter: int, checkpoint_every: int = 50,
@@ -610,7 +614,8 @@ class UOTCostLoss(torch.autograd.Function):
         C64 = C.detach().to(torch.float64).contiguous()
         K = kernel_from_cost(C64, eps, k_dtype)
         res = sinkhorn(a.detach().to(torch.float64).contiguous(), b.detach().to(torch.float64).contiguous(), K,
-                       m=C64.shape[1], eps=eps, tau=tau, max_iter=max_iter, checkpoint_every=checkpoint_every)
+                       m=C64.shape[1], eps=eps, tau=tau, max_iter=max_iter, checkpoint_every=checkpoint_every,
+                       store_iterates=checkpoint_every == 0)
         ctx.res = res
         ctx.dtypes = (C.dtype, a.dtype, b.dtype)
         return res.loss.clone().to(C.dtype)

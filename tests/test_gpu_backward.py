@@ -268,6 +268,27 @@ def test_autograd_cost_and_target_points():
     np.testing.assert_allclose(C.grad.cpu().numpy(), 0.5 * G, rtol=1e-14, atol=0)
 
 
+def test_autograd_with_every_iterate_kept():
+    """checkpoint_every = 0 in the autograd functions keeps every iterate:
+    the same gradients, to the bit, as with checkpoints."""
+    prob = workloads.grad(n=300, m=260, max_iter=20)
+    a = to_dev(prob.a)
+    b = to_dev(prob.b)
+    grads = []
+    for every in (5, 0):
+        x = to_dev(prob.x).requires_grad_(True)
+        y = to_dev(prob.y).requires_grad_(True)
+        a1 = to_dev(prob.a).requires_grad_(True)
+        L = uot.uot_loss(x, y, a1, b, prob.eps, prob.tau, 20, checkpoint_every=every, k_dtype=torch.float32)
+        L.backward()
+        C = uot.cost_from_points(to_dev(prob.x), to_dev(prob.y)).requires_grad_(True)
+        L2 = uot.uot_loss_cost(C, a, b, prob.eps, prob.tau, 20, checkpoint_every=every, k_dtype=torch.float64)
+        L2.backward()
+        grads.append((x.grad, y.grad, a1.grad, C.grad))
+    for g0, g1 in zip(*grads):
+        assert torch.equal(g0, g1)
+
+
 def test_backward_full_size_against_oracle():
     """Differentiation workload at full size: 8192^2 FP32, 500 iterations,
     checkpoints every 50, against the oracle's adjoint run at full size
