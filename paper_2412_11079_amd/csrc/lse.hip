@@ -26,6 +26,7 @@
 namespace uot {
 
 constexpr int kLseWG = 512;
+constexpr int kLseRowsMax = 1024;      // strip rows whose row inputs are staged in LDS (longer strips read HBM)
 constexpr double kColMargin = 32.0;    // log2 headroom of a raised column shift
 constexpr double kLog2E = 1.4426950408889634;
 constexpr double kLn2 = 0.6931471805599453;
@@ -75,6 +76,7 @@ __global__ __launch_bounds__(WG) void lse_kernel(LseLaunch L) {
     const PassLaunch& P = L.P;
     __shared__ double red[2][2][NW];
     __shared__ uint32_t exit_sh;
+    __shared__ double rowv[kLseRowsMax];       // the strip's log2 a_i (FUSED) or f_i (MARG)
     extern __shared__ __align__(16) double g2s[];     // G2 of every column
 
     if (pass_exit(P, &exit_sh)) return;
@@ -92,6 +94,11 @@ __global__ __launch_bounds__(WG) void lse_kernel(LseLaunch L) {
     // G2 of every column the lanes cover (E per lane): -inf past m, so those
     // entries add nothing to the row sums.
     for (int j = tid; j < WG * E; j += WG) g2s[j] = j < m ? c * L.g[j] : -INFINITY;
+    // The strip's row inputs (log2 a, or f for the marginal pass), read once:
+    // the row's chain after its barrier then waits on LDS, not on an HBM load.
+    const bool in_lds = nrows <= kLseRowsMax;
+    if (in_lds)
+        for (int k = tid; k < nrows; k += WG) rowv[k] = MODE == MODE_MARG ? L.f[r0 + k] : L.la2[r0 + k];
 
     // Buffer resource over the strip: chunks of lanes past column m and rows
     // past the strip read 0 (they are masked below).
@@ -179,10 +186,10 @@ __global__ __launch_bounds__(WG) void lse_kernel(LseLaunch L) {
             const double lse2 = S > 0.0 ? M + log2_pos(S) : -INFINITY;     // log2 sum_j 2^(G2_j - c C_ij)
             double F2;
             if constexpr (MODE == MODE_MARG) {
-                F2 = c * L.f[i];
+                F2 = c * (in_lds ? rowv[k] : L.f[i]);
                 if (tid == 0) L.r_out[i] = F2 == -INFINITY ? 0.0 : exp2_any(F2 + lse2);
             } else {
-                const double la = L.la2[i];
+                const double la = in_lds ? rowv[k] : L.la2[i];
                 F2 = la == -INFINITY ? -INFINITY : L.fi * (la - lse2);
                 if (tid == 0) {
                     L.f[i] = F2 * L.inv_c;
