@@ -75,6 +75,8 @@ __device__ __forceinline__ double online_scaling(double log2a, double s, double 
     return ldexp((double)__builtin_amdgcn_exp2f((float)(y - k)), (int)fmax(fmin(k, 2100.0), -2100.0));
 }
 
+constexpr int kOnlineRowsMax = 512;    // strip rows whose row inputs are staged in LDS (longer strips read HBM)
+
 // BL: beta and v of the lane's columns sit in LDS (read once per group of R
 // rows) instead of registers, for 16 columns per lane.
 template <int DIM, int WG, int CPL, int R, int MODE, bool BL>
@@ -86,6 +88,7 @@ __global__ __launch_bounds__(WG) void online_kernel(OnlineLaunch O, const double
     const PassLaunch& L = O.P;
     __shared__ double red[2][R][NW];
     __shared__ uint32_t exit_sh;
+    __shared__ double row_a[kOnlineRowsMax], row_la[kOnlineRowsMax];   // a and log2 a (FUSED) or u (MARG)
     extern __shared__ __align__(16) double on_lds[];    // BL: beta (WG CPL), then v (WG CPL, FP32)
 
     if (pass_exit(L, &exit_sh)) return;
@@ -98,6 +101,18 @@ __global__ __launch_bounds__(WG) void online_kernel(OnlineLaunch O, const double
     if (r1 > L.n) r1 = L.n;
     const int nrows = (int)(r1 - r0);
     const int64_t m = L.m;
+    // The strip's row inputs, read once: a group's chain after its barrier
+    // then waits on LDS, not on HBM.
+    const bool rows_in_lds = nrows <= kOnlineRowsMax;
+    if (rows_in_lds)
+        for (int k = tid; k < nrows; k += WG) {
+            if constexpr (MODE == MODE_MARG) {
+                row_a[k] = L.u[r0 + k];
+            } else {
+                row_a[k] = L.a[r0 + k];
+                row_la[k] = O.loga[r0 + k];
+            }
+        }
 
     // The lane's columns (columns past m: a copy of the last one, v = 0).
     double yc[CPL][DIM], bc[BL ? 1 : CPL];
@@ -167,11 +182,12 @@ __global__ __launch_bounds__(WG) void online_kernel(OnlineLaunch O, const double
             for (int w = 0; w < NW; ++w) tot += red[slot][lane][w];
             const int64_t i = r0 + k + lane;
             if constexpr (MODE == MODE_MARG) {
-                uu = L.u[i];
+                uu = rows_in_lds ? row_a[k + lane] : L.u[i];
                 if (wave == 0) L.s_out[i] = tot;
             } else {
-                const double ai = L.a[i];
-                uu = ai == 0.0 ? 0.0 : L.fi_is_one ? ai / tot : online_scaling(O.loga[i], tot, L.fi);
+                const double ai = rows_in_lds ? row_a[k + lane] : L.a[i];
+                const double l2a = rows_in_lds ? row_la[k + lane] : O.loga[i];
+                uu = ai == 0.0 ? 0.0 : L.fi_is_one ? ai / tot : online_scaling(l2a, tot, L.fi);
                 if (wave == 0) {
                     L.u[i] = uu;
                     if (ai > 0.0 && !(tot > 0.0)) atomicOr(&L.ctrl->flags, UOT_FLAG_ZERO_SUM);
