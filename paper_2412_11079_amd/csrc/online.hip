@@ -222,9 +222,11 @@ hipError_t launch_online_setup(const double* x, const double* y, const double* a
 
 // Lanes per workgroup (WG), columns per lane (CPL) and rows per group (R)
 // for rows of m columns: the R CPL K values of a group stay in registers
-// until its scalings are known; BL puts beta and v in LDS.
+// until its scalings are known; BL puts beta and v in LDS.  At 16 columns
+// per lane, 4 rows per group (3-D: a few values spilled, still faster than
+// 3 rows; 2-D: 5 rows were slower).
 #ifndef UOT_ONLINE_WIDE
-#define UOT_ONLINE_WIDE(DIM, X) X(DIM, 512, 16, (DIM == 3 ? 3 : 4), true)
+#define UOT_ONLINE_WIDE(DIM, X) X(DIM, 512, 16, 4, true)
 #endif
 #define UOT_ONLINE_SHAPES(DIM, X)                   \
     if (m <= 512) X(DIM, 512, 1, 8, false);         \
