@@ -299,8 +299,12 @@ uot_status uot_matrix_rescale(const uot_problem* prob, const uot_options* opt, c
  *     loop (else UOT_ERR_UNSUPPORTED)
  *   out: as uot_sinkhorn (u, v required; r, c, loss, info, f, g optional;
  *     ckpt ignored)
- * Rows of at most 8192 columns (m <= 8192, else UOT_ERR_UNSUPPORTED): a
- * workgroup keeps the target points of a whole row on chip.
+ * Rows of up to 8192 columns run one fused pass per iteration (a workgroup
+ * keeps the target points of a whole row on chip); wider rows (m up to
+ * 2^20, else UOT_ERR_UNSUPPORTED) run in column tiles of 8192: a row pass
+ * (each tile's row sums), the row scalings, then a column pass, each pass
+ * forming K again, so an iteration costs twice the arithmetic of the fused
+ * pass.  The workspace then also holds ceil(m / 8192) doubles per row.
  * Errors: UOT_ERR_ARG, UOT_ERR_ALIGN, UOT_ERR_WORKSPACE, UOT_ERR_UNSUPPORTED,
  * UOT_ERR_HIP.  Workspace: uot_sinkhorn_points_workspace_size bytes (0 on
  * invalid arguments).

@@ -1178,11 +1178,16 @@ uot_status run_matrix(const uot_problem* p, const uot_options* o, const uot_outp
 // ---------------------------------------------------------------------------
 // Kernel-free solve from points (the Gibbs kernel recomputed in every pass)
 // ---------------------------------------------------------------------------
+// Widest rows of the kernel-free solve (the column-tiled form's row-sum
+// buffer holds ceil(m / 8192) doubles per row).
+constexpr int64_t kPointsMaxM = 1 << 20;
+
 struct PtsPlan {
     int32_t G;
     int64_t rows_per_wg, ldp;
     int32_t fin_blocks;
-    size_t off_ctrl, off_cprev, off_w, off_s, off_bp, off_part, off_rows, off_beta, off_loga, total;
+    int32_t tiles;        // 0: fused pass; > 0: column-tiled row and column passes
+    size_t off_ctrl, off_cprev, off_w, off_s, off_bp, off_part, off_rows, off_beta, off_loga, off_rowpart, total;
 };
 
 uot_status make_points_plan(const uot_problem* p, int64_t dim, double cost_scale, const uot_options* o,
@@ -1195,9 +1200,9 @@ uot_status make_points_plan(const uot_problem* p, int64_t dim, double cost_scale
     if (!(p->tau > 0.0)) return fail(UOT_ERR_ARG, "tau must be > 0 (or +inf)");
     if (!(cost_scale > 0.0) || !isfinite(cost_scale)) return fail(UOT_ERR_ARG, "cost_scale must be finite and > 0");
     if (dim != 2 && dim != 3) return fail(UOT_ERR_UNSUPPORTED, "point dimension %lld (2 or 3)", (long long)dim);
-    if (p->m > online_max_m())
-        return fail(UOT_ERR_UNSUPPORTED, "the kernel-free pass holds rows of up to %lld columns (m=%lld)",
-                    (long long)online_max_m(), (long long)p->m);
+    if (p->m > kPointsMaxM)
+        return fail(UOT_ERR_UNSUPPORTED, "the kernel-free solve takes rows of up to %lld columns (m=%lld)",
+                    (long long)kPointsMaxM, (long long)p->m);
     if (o->max_iter < 0) return fail(UOT_ERR_ARG, "max_iter must be >= 0");
     if (o->absorb_log_threshold != 0.0 || records_iterates(o) || o->persistent || !o->fused ||
         o->accum != UOT_ACC_F32)
@@ -1208,11 +1213,20 @@ uot_status make_points_plan(const uot_problem* p, int64_t dim, double cost_scale
     if (o->v0 && !aligned(o->v0, 8)) return fail(UOT_ERR_ALIGN, "v0 must be 8-byte aligned");
     // As many workgroups as the compute units hold at once (the pass is
     // ALU-bound: one wave of strips, no tail), each with at least one full
-    // group of rows.
-    const int per_cu = std::max(1, online_wgs_per_cu((int)dim, p->m));
-    const int64_t rg = std::max(1, online_rows_per_group((int)dim, p->m));
-    const int64_t target = std::min<int64_t>((int64_t)per_cu * cu_count(), (p->n + rg - 1) / rg);
-    P.rows_per_wg = (p->n + target - 1) / target;
+    // group of rows.  Rows wider than the fused pass holds run as strips x
+    // column tiles.
+    P.tiles = p->m > online_max_m() ? (int32_t)((p->m + online_tile_cols() - 1) / online_tile_cols()) : 0;
+    if (P.tiles > 0) {
+        const int per_cu = std::max(1, online_tile_wgs_per_cu((int)dim));
+        const int64_t strips = std::max<int64_t>(1, (int64_t)per_cu * cu_count() / P.tiles);
+        const int64_t target = std::min<int64_t>(strips, (p->n + 7) / 8);
+        P.rows_per_wg = (p->n + target - 1) / target;
+    } else {
+        const int per_cu = std::max(1, online_wgs_per_cu((int)dim, p->m));
+        const int64_t rg = std::max(1, online_rows_per_group((int)dim, p->m));
+        const int64_t target = std::min<int64_t>((int64_t)per_cu * cu_count(), (p->n + rg - 1) / rg);
+        P.rows_per_wg = (p->n + target - 1) / target;
+    }
     P.G = (int32_t)((p->n + P.rows_per_wg - 1) / P.rows_per_wg);
     P.ldp = round_up(p->m, 64);
     P.fin_blocks = finalize_blocks(p->m);
@@ -1226,6 +1240,7 @@ uot_status make_points_plan(const uot_problem* p, int64_t dim, double cost_scale
     P.off_rows = off; off = align_up(off + sizeof(double) * 4 * (size_t)p->n, kAlign);
     P.off_beta = off; off = align_up(off + sizeof(double) * (size_t)p->m, kAlign);
     P.off_loga = off; off = align_up(off + sizeof(double) * (size_t)p->n, kAlign);
+    P.off_rowpart = off; off = align_up(off + sizeof(double) * (size_t)P.tiles * p->n, kAlign);
     P.total = off;
     return UOT_OK;
 }
@@ -1285,6 +1300,8 @@ uot_status run_points(const uot_problem* p, const double* x, const double* y, in
     OL.beta = beta;
     OL.loga = loga;
     OL.dim = (int32_t)dim;
+    OL.rowpart = (double*)(base + P.off_rowpart);
+    OL.tiles = P.tiles;
 
     FinLaunch F;
     memset(&F, 0, sizeof(F));
@@ -1310,7 +1327,13 @@ uot_status run_points(const uot_problem* p, const double* x, const double* y, in
         OnlineLaunch O1 = OL;
         O1.P.iter = t + 1;
         O1.P.test_stop = 1;
-        UOT_HIP(launch_online(MODE_FUSED, O1, stream), "kernel-free pass");
+        if (P.tiles > 0) {
+            UOT_HIP(launch_online_tile_rows(O1, stream), "kernel-free row pass");
+            UOT_HIP(launch_online_row_finish(OL, 0, stream), "row finish");
+            UOT_HIP(launch_online_tile_cols(OL, stream), "kernel-free column pass");
+        } else {
+            UOT_HIP(launch_online(MODE_FUSED, O1, stream), "kernel-free pass");
+        }
         UOT_HIP(launch_finalize(F, stream), "column finalize");
         iters_run = t + 1;
         if (flag_host && (t + 1) % check_every == 0 && t + 1 < o->max_iter) {
@@ -1325,7 +1348,13 @@ uot_status run_points(const uot_problem* p, const double* x, const double* y, in
         OnlineLaunch OM = OL;
         OM.P.check_done = 0;
         OM.P.s_out = sbuf;
-        UOT_HIP(launch_online(MODE_MARG, OM, stream), "kernel-free marginal pass");
+        if (P.tiles > 0) {
+            UOT_HIP(launch_online_tile_rows(OM, stream), "kernel-free row pass");
+            UOT_HIP(launch_online_row_finish(OM, 1, stream), "row sums");
+            UOT_HIP(launch_online_tile_cols(OM, stream), "kernel-free column pass");
+        } else {
+            UOT_HIP(launch_online(MODE_MARG, OM, stream), "kernel-free marginal pass");
+        }
         FinLaunch FM = F;
         FM.marginal_only = 1;
         FM.c_out = nullptr;

@@ -211,6 +211,230 @@ __global__ __launch_bounds__(WG) void online_kernel(OnlineLaunch O, const double
     }
 }
 
+// ---------------------------------------------------------------------------
+// Column-tiled form: rows wider than one workgroup's 8192 columns.  A row's
+// total needs every tile before its scaling exists, so the fused pass
+// splits into a row pass and a column pass that each form K again (twice
+// the arithmetic of the fused pass).  Workgroup (strip, tile): 512 lanes,
+// lane l holding columns t T + l + 512 c (c < 16) of tile t, coordinates
+// in registers, beta (and v) in LDS as in the widest fused shape.
+// ---------------------------------------------------------------------------
+constexpr int kTileWG = 512;
+constexpr int kTileCPL = 16;
+constexpr int64_t kTileCols = (int64_t)kTileWG * kTileCPL;
+constexpr int kTileRows = 8;              // rows per group (no K values are kept between phases)
+
+int64_t online_tile_cols() { return kTileCols; }
+
+// The lane's columns of tile blockIdx.y: coordinates into yc, beta (and v
+// with WITH_V) into LDS; columns past m copy the last column (v = 0).
+template <int DIM, bool WITH_V>
+__device__ __forceinline__ void tile_columns(const OnlineLaunch& O, const double* __restrict__ beta, int64_t m,
+                                             double (&yc)[kTileCPL][DIM], double* bl, float* vl) {
+    const int tid = threadIdx.x;
+    const int64_t j0 = (int64_t)blockIdx.y * kTileCols;
+#pragma unroll
+    for (int c = 0; c < kTileCPL; ++c) {
+        const int64_t j = j0 + (int64_t)c * kTileWG + tid;
+        const int64_t jj = j < m ? j : m - 1;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) yc[c][d] = O.y[jj * DIM + d];
+        bl[c * kTileWG + tid] = beta[jj];
+        if constexpr (WITH_V) vl[c * kTileWG + tid] = j < m ? (float)O.P.v[j] : 0.0f;
+    }
+}
+
+// 2^t of entry (row terms xr, al; column c) as in the fused pass.
+template <int DIM>
+__device__ __forceinline__ float tile_entry(const double (&xr)[DIM], double al, double bcc,
+                                            const double (&ycc)[DIM]) {
+    double t = al + bcc;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) t = fma(xr[d], ycc[d], t);
+    const double kf = __builtin_rint(t);
+    const float f = (float)(t - kf);
+    return __builtin_ldexpf(__builtin_amdgcn_exp2f(f), (int)fmax(kf, -1000.0));
+}
+
+// Row pass: each tile's FP32 lane dots of its rows with v, reduced over the
+// workgroup in FP64 (fixed order) into rowpart[tile n + i].
+template <int DIM>
+__global__ __launch_bounds__(kTileWG) void online_tile_rows_kernel(OnlineLaunch O, const double* __restrict__ rows,
+                                                                  const double* __restrict__ beta) {
+    constexpr int NW = kTileWG / 64;
+    constexpr int R = kTileRows;
+    const PassLaunch& L = O.P;
+    __shared__ double red[2][R][NW];
+    __shared__ uint32_t exit_sh;
+    extern __shared__ __align__(16) double on_lds[];    // beta (T), then v (T, FP32)
+    if (pass_exit(L, &exit_sh)) return;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * L.rows_per_wg;
+    int64_t r1 = r0 + L.rows_per_wg;
+    if (r1 > L.n) r1 = L.n;
+    const int nrows = (int)(r1 - r0);
+    double yc[kTileCPL][DIM];
+    double* bl = on_lds;
+    float* vl = (float*)(on_lds + kTileCols);
+    tile_columns<DIM, true>(O, beta, L.m, yc, bl, vl);
+    double* out = O.rowpart + (int64_t)blockIdx.y * L.n;
+    int slot = 0;
+    for (int k = 0; k < nrows; k += R) {
+        const int nr = nrows - k < R ? nrows - k : R;
+        double xr[R][DIM], al[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t i = r0 + k + (r < nr ? r : nr - 1);
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) xr[r][d] = rows[4 * i + d];
+            al[r] = rows[4 * i + 3];
+        }
+        float s[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) s[r] = 0.0f;
+#pragma unroll
+        for (int c = 0; c < kTileCPL; ++c) {
+            // Each lane reads only the LDS words it wrote: no barrier needed.
+            const double bcc = bl[c * kTileWG + tid];
+            const float vcc = vl[c * kTileWG + tid];
+#pragma unroll
+            for (int r = 0; r < R; ++r) s[r] = fmaf(tile_entry<DIM>(xr[r], al[r], bcc, yc[c]), vcc, s[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double d = wave_sum_f64((double)s[r]);
+            if (lane == 0) red[slot][r][wave] = d;
+        }
+        __syncthreads();
+        if (wave == 0 && lane < nr) {
+            double tot = 0.0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) tot += red[slot][lane][w];
+            out[r0 + k + lane] = tot;
+        }
+        slot ^= 1;
+    }
+}
+
+// Row finish: s_i = sum of the tiles' row sums in tile order; then u_i
+// (fused step) or, with marginal, s_i itself into s_out.
+__global__ void online_row_finish_kernel(OnlineLaunch O, int marginal) {
+    const PassLaunch& L = O.P;
+    if (!marginal && L.check_done && ld_volatile_u32(&L.ctrl->done) != 0) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= L.n) return;
+    double tot = 0.0;
+    for (int t = 0; t < O.tiles; ++t) tot += O.rowpart[(int64_t)t * L.n + i];
+    if (marginal) {
+        L.s_out[i] = tot;
+        return;
+    }
+    const double ai = L.a[i];
+    const double uu = ai == 0.0 ? 0.0 : L.fi_is_one ? ai / tot : online_scaling(O.loga[i], tot, L.fi);
+    L.u[i] = uu;
+    if (ai > 0.0 && !(tot > 0.0)) atomicOr(&L.ctrl->flags, UOT_FLAG_ZERO_SUM);
+    if (!isfinite(uu)) atomicOr(&L.ctrl->flags, UOT_FLAG_NONFINITE);
+}
+
+// Column pass: each tile's column partials of K^T u over its strip rows
+// (u staged in LDS), no cross-lane exchange at all.
+template <int DIM>
+__global__ __launch_bounds__(kTileWG) void online_tile_cols_kernel(OnlineLaunch O, const double* __restrict__ rows,
+                                                                  const double* __restrict__ beta) {
+    constexpr int R = kTileRows;
+    const PassLaunch& L = O.P;
+    __shared__ uint32_t exit_sh;
+    __shared__ double row_u[kOnlineRowsMax];
+    extern __shared__ __align__(16) double on_lds[];    // beta (T)
+    if (pass_exit(L, &exit_sh)) return;
+    const int tid = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * L.rows_per_wg;
+    int64_t r1 = r0 + L.rows_per_wg;
+    if (r1 > L.n) r1 = L.n;
+    const int nrows = (int)(r1 - r0);
+    const int64_t m = L.m;
+    const bool rows_in_lds = nrows <= kOnlineRowsMax;
+    if (rows_in_lds)
+        for (int k = tid; k < nrows; k += kTileWG) row_u[k] = L.u[r0 + k];
+    double yc[kTileCPL][DIM];
+    double* bl = on_lds;
+    tile_columns<DIM, false>(O, beta, m, yc, bl, nullptr);
+    float acc[kTileCPL];
+#pragma unroll
+    for (int c = 0; c < kTileCPL; ++c) acc[c] = 0.0f;
+    __syncthreads();
+    for (int k = 0; k < nrows; k += R) {
+        const int nr = nrows - k < R ? nrows - k : R;
+        double xr[R][DIM], al[R];
+        float ur[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int rr = r < nr ? r : nr - 1;
+            const int64_t i = r0 + k + rr;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) xr[r][d] = rows[4 * i + d];
+            al[r] = rows[4 * i + 3];
+            // rows past the strip repeat its last row with scaling 0
+            ur[r] = r < nr ? (float)(rows_in_lds ? row_u[k + rr] : L.u[i]) : 0.0f;
+        }
+#pragma unroll
+        for (int c = 0; c < kTileCPL; ++c) {
+            const double bcc = bl[c * kTileWG + tid];
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[c] = fmaf(tile_entry<DIM>(xr[r], al[r], bcc, yc[c]), ur[r], acc[c]);
+        }
+    }
+    float* P = (float*)L.partials + (int64_t)blockIdx.x * L.ldp;
+    const int64_t j0 = (int64_t)blockIdx.y * kTileCols;
+#pragma unroll
+    for (int c = 0; c < kTileCPL; ++c) {
+        const int64_t j = j0 + (int64_t)c * kTileWG + tid;
+        if (j < m) __builtin_nontemporal_store(acc[c], &P[j]);
+    }
+}
+
+static constexpr size_t kTileRowsLds = (size_t)kTileCols * 12;   // beta FP64 + v FP32
+static constexpr size_t kTileColsLds = (size_t)kTileCols * 8;    // beta FP64
+
+int online_tile_wgs_per_cu(int dim) {
+    int nb = 0;
+    hipError_t e = dim == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, online_tile_rows_kernel<2>, kTileWG,
+                                                                           kTileRowsLds)
+                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, online_tile_rows_kernel<3>, kTileWG,
+                                                                           kTileRowsLds);
+    return e == hipSuccess ? nb : 0;
+}
+
+template <typename Fn>
+static hipError_t tile_launch(Fn fn, size_t lds, const OnlineLaunch& O, hipStream_t stream) {
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(fn, dim3(O.P.grid, O.tiles), dim3(kTileWG), lds, stream, O, O.rows, O.beta);
+    return hipGetLastError();
+}
+
+hipError_t launch_online_tile_rows(const OnlineLaunch& O, hipStream_t stream) {
+    if (O.dim == 2) return tile_launch(online_tile_rows_kernel<2>, kTileRowsLds, O, stream);
+    if (O.dim == 3) return tile_launch(online_tile_rows_kernel<3>, kTileRowsLds, O, stream);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_online_tile_cols(const OnlineLaunch& O, hipStream_t stream) {
+    if (O.dim == 2) return tile_launch(online_tile_cols_kernel<2>, kTileColsLds, O, stream);
+    if (O.dim == 3) return tile_launch(online_tile_cols_kernel<3>, kTileColsLds, O, stream);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_online_row_finish(const OnlineLaunch& O, int marginal, hipStream_t stream) {
+    const unsigned blocks = (unsigned)((O.P.n + 255) / 256);
+    hipLaunchKernelGGL(online_row_finish_kernel, dim3(blocks), dim3(256), 0, stream, O, marginal);
+    return hipGetLastError();
+}
+
 hipError_t launch_online_setup(const double* x, const double* y, const double* a, int64_t n, int64_t m, int dim,
                                double c, double* rows, double* beta, double* loga, hipStream_t stream) {
     const int64_t total = n + m;
