@@ -188,6 +188,20 @@ def test_column_tiles_tolerance_stop_and_zero_mass():
         compare(res, ref, 1e-6, 1e-6, f"tiles tol stop every={every}")
 
 
+@pytest.mark.parametrize("m", [3000, 12000])
+def test_warm_start_resume_is_bitwise(m):
+    """10 iterations, then 10 more from the returned (u, v), equal 20 in one
+    call bit for bit (fused pass and column tiles)."""
+    prob = workloads.random_small(800, m, seed=7400 + m, eps=0.03, tau=1.0, d=3)
+    x, y, a, b = to_dev(prob.x), to_dev(prob.y), to_dev(prob.a), to_dev(prob.b)
+    kw = dict(eps=prob.eps, tau=prob.tau)
+    r20 = uot.sinkhorn_points(x, y, a, b, max_iter=20, **kw)
+    r10 = uot.sinkhorn_points(x, y, a, b, max_iter=10, **kw)
+    r1010 = uot.sinkhorn_points(x, y, a, b, max_iter=10, u0=r10.u, v0=r10.v, **kw)
+    torch.cuda.synchronize()
+    assert torch.equal(r20.u, r1010.u) and torch.equal(r20.v, r1010.v) and torch.equal(r20.loss, r1010.loss)
+
+
 def test_headline_workload_full_size_kernel_free():
     """The headline workload (16384 x 16384, 3-D mixture, max-normalised
     cost, eps 0.01, tau 0.5) kernel-free in column tiles: 10 iterations and
